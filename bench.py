@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the circuit-cutting pipeline on one MI355X.
+
+Workload (the metric's configuration): random Ry.Rz + CZ brickwork, q = 28
+qubits, two equal segments of 14, depth d = 20, c_total = 6 cut CZs
+(K = 64 merge terms), seed 0.  One step is the whole cut pipeline of
+Eq. (runtime_decomp): cut_plan + device-table upload (T_pre), every
+subcircuit variant (T_sub) and the merge into the 2^28 complex64 state
+(T_merge).  value = 2^q amplitudes per step / seconds per step.
+
+Beside the steps it times the uncut simulation of the same circuit on the
+same GPU (T_orig), checks the cut state against the uncut state (1 - F,
+float64 reductions) and against oracle amplitudes at sampled indices, and
+times the complex128 CPU oracle on a bounded sample (cpu_baseline).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+Q, D, NSEG, CTOTAL, SEED = 28, 20, 2, 6, 0
+HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(gates, sizes):
+    """Times the complex128 oracle on a bounded sample of the same workload.
+
+    Sample: the oracle's cut plan and all 2 * 2^6 subcircuit variants in full,
+    then its merge (the plain sum over all 64 terms) restricted to the first
+    R rows of the high segment, i.e. R * 2^14 of the 2^28 amplitudes; the merge
+    time is scaled by 2^14 / R to the full state.
+    """
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cutting
+
+    rows = 128
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        cuts = cutting.find_cuts(Q, gates, sizes)
+        t1 = time.perf_counter()
+        states = cutting.variant_states(Q, gates, sizes, cuts)
+        t2 = time.perf_counter()
+        trunc = {k: (v[:rows] if k[0] == 1 else v) for k, v in states.items()}
+        part = cutting.merge(sizes, cuts, trunc)
+        t3 = time.perf_counter()
+    assert part.shape[0] == rows << sizes[0]
+    t_pre, t_sub, t_merge_s = t1 - t0, t2 - t1, t3 - t2
+    t_merge = t_merge_s * ((1 << sizes[1]) / rows)
+    t_cut = t_pre + t_sub + t_merge
+    return {
+        "value": (1 << Q) / t_cut, "unit": "amps/s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle cut plan + all {len(states)} variant states in full; merge over all "
+                   f"{2 ** len(cuts)} terms on the first {rows} of {1 << sizes[1]} high-segment rows "
+                   f"({rows << sizes[0]} amplitudes), scaled by {(1 << sizes[1]) // rows}; "
+                   f"complex128 numpy, BLAS limited to 1 thread"),
+        "seconds": {"pre": t_pre, "sub": t_sub, "merge_sample": t_merge_s, "merge_scaled": t_merge,
+                    "cut_total_est": t_cut},
+    }, cuts, states
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="auto")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and sampled check")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of "
+              "the merge is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from inputs import brickwork, equal_blocks
+    from paper_2603_01443_amd import ccut
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    sizes = equal_blocks(Q, NSEG)
+    gates = brickwork(Q, D, NSEG, CTOTAL, SEED)
+    garr = ccut.gate_array(gates)
+    plan0 = ccut.cut_plan(Q, garr, NSEG, sizes)
+    info = plan0.info()
+    K = info["n_terms"]
+    arena = torch.empty(info["arena_bytes"], dtype=torch.uint8, device=dev)
+    psi = torch.empty(1 << Q, dtype=torch.complex64, device=dev)
+    prec = args.precision
+    log(f"bench: q={Q} d={D} n={NSEG} c_total={CTOTAL} K={K} n_sub={info['n_sub']} "
+        f"arena={info['arena_bytes'] / 2**20:.1f} MiB precision={prec}")
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t_pre = []
+    keep = []
+
+    def step(i=None):
+        t0 = time.perf_counter()
+        plan = ccut.cut_plan(Q, garr, NSEG, sizes)
+        ccut.plan_prepare(plan)
+        t_pre.append(time.perf_counter() - t0)
+        if i is not None:
+            ev[i][0].record(stream)
+        ccut.simulate_subcircuits(plan, arena, stream=stream)
+        if i is not None:
+            ev[i][1].record(stream)
+        ccut.merge_full_state(plan, arena, psi, prec, stream=stream)
+        if i is not None:
+            ev[i][2].record(stream)
+        keep.append(plan)   # freed after the timed region (freeing syncs the device)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    keep.clear()
+    t_pre.clear()
+    log(f"bench: warmup done, timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    keep.clear()
+    ms_step = 1e3 * wall / args.steps
+    t_sub = [ev[i][0].elapsed_time(ev[i][1]) for i in range(args.steps)]
+    t_merge = [ev[i][1].elapsed_time(ev[i][2]) for i in range(args.steps)]
+    log(f"bench: {ms_step:.3f} ms/step; sub {np.mean(t_sub):.3f} ms, merge {np.mean(t_merge):.3f} ms, "
+        f"pre {1e3 * np.mean(t_pre):.3f} ms")
+
+    # uncut baseline on the same GPU
+    ref = torch.empty_like(psi)
+    for _ in range(2):
+        ccut.simulate_uncut(Q, garr, ref, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(reps):
+        ccut.simulate_uncut(Q, garr, ref, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_orig_wall = 1e3 * (time.perf_counter() - w0) / reps
+    t_orig = e0.elapsed_time(e1) / reps
+    stats = ccut.norm_fidelity(psi, ref, Q, stream=stream)
+    one_minus_f = 1.0 - stats["fidelity"]
+    log(f"bench: uncut {t_orig:.3f} ms; cut vs uncut 1-F {one_minus_f:.3e}, norm drift "
+        f"{abs(stats['norm2'] - 1):.3e}")
+
+    merge_ms = float(np.mean(t_merge))
+    merge_bytes = 8 * (1 << Q) + 8 * K * ((1 << sizes[0]) + (1 << sizes[1]))
+    merge_flops = 8 * K * (1 << Q)
+    used = prec if prec != "auto" else ("fp32" if K < 64 else "fp32")
+    if used == "fp32" and K * 8 > FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9) * 8:
+        roof = {"bound": "alu", "achieved": merge_flops / (merge_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": merge_bytes / (merge_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"merge ({used})"
+    roof["algorithmic_bytes"] = merge_bytes
+    roof["algorithmic_flops"] = merge_flops
+
+    result = {
+        "metric": "full-state amps/s merged; cut vs uncut wall-clock at q=28, 1-F<=1e-6",
+        "value": (1 << Q) / (ms_step * 1e-3),
+        "unit": "amps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"brickwork q={Q} n={NSEG} ({sizes[0]}+{sizes[1]}) d={D} c_total={CTOTAL} K={K}",
+                   "q": Q, "d": D, "n_seg": NSEG, "c_total": CTOTAL, "seed": SEED, "merge_precision": prec},
+        "stages_ms": {"pre": 1e3 * float(np.mean(t_pre)), "sub": float(np.mean(t_sub)), "merge": merge_ms,
+                      "uncut": t_orig, "uncut_wall": t_orig_wall},
+        "merge_amps_per_s": (1 << Q) / (merge_ms * 1e-3),
+        "cut_vs_uncut": {"speedup": t_orig / ms_step, "one_minus_F": one_minus_f,
+                         "norm_drift": abs(stats["norm2"] - 1.0), "max_abs": stats["max_abs"]},
+        "roofline": roof,
+    }
+
+    if not args.no_cpu:
+        log("bench: timing the CPU oracle on a bounded sample")
+        cb, cuts, states = cpu_baseline(gates, sizes)
+        result["cpu_baseline"] = cb
+        from oracle import cutting
+        rng = np.random.default_rng(0)
+        xs = sorted(set(int(x) for x in rng.integers(0, 1 << Q, size=256)))
+        want = cutting.amplitudes(xs, sizes, cuts, states)
+        got = psi[torch.tensor(xs, device=dev)].cpu().numpy().astype(np.complex128)
+        result["oracle_sampled_max_abs"] = float(np.max(np.abs(got - want)))
+        result["oracle_sampled_n"] = len(xs)
+        log(f"bench: cpu oracle {cb['value']:.3e} amps/s; sampled max-abs vs oracle "
+            f"{result['oracle_sampled_max_abs']:.3e}")
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * ccut.h - C ABI of the MI355X (gfx950) circuit-cutting library.
+ *
+ * The library reproduces the classical state-vector pipeline of
+ * "Applicability and Limitations of Quantum Circuit Cutting in Classical
+ * State-Vector Simulation" (arXiv 2603.01443):
+ *
+ *   T_cut = T_pre + T_sub + T_merge               (Sec. III.A, Eq. runtime_decomp)
+ *   cut_plan            - preprocessing           (Appendix B, Algorithm 1)
+ *   simulate_subcircuits- subcircuit simulation   (Appendix B, Algorithm 2)
+ *   merge_full_state    - full-state merging      (Appendix B, Algorithm 3)
+ *   simulate_uncut      - the uncut baseline T_orig = O(2^q D) (Sec. III.A)
+ *
+ * Every cross-segment CZ is cut with the rank-2 decomposition of Eq. (CZ),
+ *   CZ = (S (x) S + i S^dag (x) S^dag) / (1 + i),   S = diag(1, i),
+ * and every cross-segment CX through CX = (I (x) H) CZ (I (x) H) (Sec. II.A.2),
+ * so the target side of a cut CX receives H S H or H S^dag H.
+ *
+ * Conventions shared by every call:
+ *  - Qubit j is bit j of the amplitude index (little-endian, as in Qiskit,
+ *    which the paper uses, Sec. V.A.1).  Segment 0 holds the lowest qubits;
+ *    segments are contiguous blocks of qubits.
+ *  - A state of m qubits is 2^m complex64 values, interleaved (re, im) float32,
+ *    contiguous, in device memory.
+ *  - Device pointers are plain addresses returned by hipMalloc (or a PyTorch
+ *    tensor's data_ptr()).  The caller owns every device buffer it passes in.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls that take a stream only enqueue work and return; errors in kernels
+ *    surface at the caller's next synchronisation.
+ *  - Return value: CCUT_OK (0) or a negative CCUT_E* code; the message of the
+ *    last failure on the calling thread is returned by ccut_last_error().
+ *    No call aborts the process.
+ */
+#ifndef CCUT_H_
+#define CCUT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ limits */
+#define CCUT_MAX_SEG 8          /* segments per plan */
+#define CCUT_MAX_Q 35           /* 2^35 complex64 = 256 GiB, the largest state one GPU holds */
+#define CCUT_MAX_CUTS_PER_SEG 16 /* c_i <= 16: at most 65536 variants per segment */
+
+/* ------------------------------------------------------------------ status */
+#define CCUT_OK 0
+#define CCUT_EINVAL (-1)        /* bad argument (q, sizes, gate kind, qubit index, NULL) */
+#define CCUT_EUNCUTTABLE (-2)   /* a gate other than CZ/CX crosses a segment boundary */
+#define CCUT_ENOSPC (-3)        /* a caller buffer is smaller than required */
+#define CCUT_ENOMEM (-4)        /* host or device allocation failed */
+#define CCUT_EHIP (-5)          /* a HIP runtime call failed */
+#define CCUT_EUNSUPPORTED (-6)  /* valid request this build does not implement */
+
+/* ------------------------------------------------------------------ gates */
+enum {
+  CCUT_GATE_H = 0, CCUT_GATE_X = 1, CCUT_GATE_Y = 2, CCUT_GATE_Z = 3,
+  CCUT_GATE_S = 4, CCUT_GATE_SDG = 5, CCUT_GATE_T = 6, CCUT_GATE_TDG = 7,
+  CCUT_GATE_RX = 8,   /* exp(-i p0 X / 2) */
+  CCUT_GATE_RY = 9,   /* exp(-i p0 Y / 2) */
+  CCUT_GATE_RZ = 10,  /* exp(-i p0 Z / 2) */
+  CCUT_GATE_RYRZ = 11,/* Ry(p0) . Rz(p1): Rz acts first */
+  CCUT_GATE_CZ = 16,  /* symmetric in q0, q1 */
+  CCUT_GATE_CX = 17   /* q0 = control, q1 = target */
+};
+
+/* One gate.  Single-qubit kinds ignore q1 (set it to -1); 32 bytes. */
+typedef struct ccut_gate {
+  int32_t kind;
+  int32_t q0;
+  int32_t q1;
+  int32_t reserved; /* must be 0 */
+  double p0;
+  double p1;
+} ccut_gate_t;
+
+/* --------------------------------------------------------------- the plan */
+typedef struct ccut_plan ccut_plan_t; /* opaque, owned by the library */
+
+typedef struct ccut_plan_info {
+  int32_t q;                           /* total qubits */
+  int32_t n_seg;                       /* n */
+  int32_t c_total;                     /* cut gates */
+  int32_t n_gates;                     /* gates in the input circuit */
+  int32_t seg_size[CCUT_MAX_SEG];      /* q_i */
+  int32_t seg_offset[CCUT_MAX_SEG];    /* first qubit of segment i */
+  int32_t c_seg[CCUT_MAX_SEG];         /* c_i: cuts adjacent to segment i */
+  int32_t c_boundary[CCUT_MAX_SEG];    /* c_b: cuts between segments b and b+1 */
+  int64_t n_sub;                       /* N_sub = sum_i 2^{c_i}            (Sec. III.A) */
+  int64_t n_terms;                     /* 2^{c_total} global merge terms   (Algorithm 3) */
+  uint64_t seg_state_offset[CCUT_MAX_SEG]; /* byte offset of segment i's variant 0 in the arena */
+  uint64_t state_bytes;                /* bytes of all subcircuit states */
+  uint64_t arena_bytes;                /* state_bytes + merge workspace: size the arena to this */
+  uint64_t psi_bytes;                  /* 8 * 2^q, the merged state */
+} ccut_plan_info_t;
+
+typedef struct ccut_cut_info {
+  int32_t gate_index; /* position in the input gate list */
+  int32_t kind;       /* CCUT_GATE_CZ or CCUT_GATE_CX */
+  int32_t boundary;   /* b: the cut joins segments b and b+1 */
+  int32_t q_low;      /* its qubit in segment b */
+  int32_t q_high;     /* its qubit in segment b+1 */
+  int32_t target_high;/* CX only: 1 if the target sits in segment b+1 */
+  int32_t bit_low;    /* bit of this cut in segment b's variant index */
+  int32_t bit_high;   /* bit of this cut in segment b+1's variant index */
+} ccut_cut_info_t;
+
+/*
+ * Preprocessing, Algorithm 1 (Appendix B).  Scans the circuit for two-qubit
+ * gates whose qubits lie in different segments, splits every segment's gate
+ * list at them, and records, for each segment, one gate program with a
+ * selectable S / S^dag slot per adjacent cut (the 2^{c_i} subcircuits of
+ * Algorithm 1 are these programs with the slots fixed by the variant index;
+ * they are never copied out).  Host-only; touches no GPU.
+ *
+ *   q          total qubits, 1..CCUT_MAX_Q
+ *   gates      n_gates gates (host memory, read during the call only)
+ *   n_seg      number of segments n, 1..CCUT_MAX_SEG
+ *   seg_sizes  n_seg contiguous block sizes adding up to q, or NULL for
+ *              floor(q/n) per block with the remainder on the last blocks
+ *   plan_out   receives the plan; free it with ccut_plan_free
+ *
+ * Cuts are numbered boundary by boundary (lowest boundary first) and in gate
+ * order within a boundary.  Variant index r of segment i: its bits [0, c_{i-1})
+ * select the cuts on the boundary below it, the next c_i' bits those on the
+ * boundary above it (bit = 0: S term, 1: S^dag term).
+ * Arena layout: segment-major, then variant r, each state 2^{q_i} complex64
+ * at seg_state_offset[i] + r * 8 * 2^{q_i} (256-byte aligned bases).
+ *
+ * Errors: CCUT_EINVAL (bad q, sizes, qubit or kind), CCUT_EUNCUTTABLE (a
+ * non-CZ/CX gate, or a CZ/CX between non-adjacent segments, crosses a
+ * boundary), CCUT_EUNSUPPORTED (some c_i > CCUT_MAX_CUTS_PER_SEG).
+ */
+int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gates, int32_t n_seg,
+                  const int32_t* seg_sizes, ccut_plan_t** plan_out);
+
+/* Sizes and counts of a plan (host-only). */
+int ccut_plan_info(const ccut_plan_t* plan, ccut_plan_info_t* info);
+
+/* Cut j (0 <= j < c_total) of a plan, in the plan's numbering (host-only). */
+int ccut_plan_cut(const ccut_plan_t* plan, int32_t j, ccut_cut_info_t* out);
+
+/*
+ * Merge weight of cut term `bit` (0 or 1), Eq. (CZ): s_0 = 1/(1+i), s_1 = i/(1+i).
+ * The weight of a global combination (alpha_m of Algorithm 3) is the product
+ * over all cuts.  Writes (re, im) in float64 to out[0..1].  Host-only.
+ */
+int ccut_cut_weight(int32_t bit, double out[2]);
+
+/* Frees a plan and its device tables.  NULL is ignored. */
+void ccut_plan_free(ccut_plan_t* plan);
+
+/*
+ * Uploads the plan's device tables (gate programs, merge weights) on the
+ * current device.  Part of T_pre.  Called implicitly by the first
+ * simulate/merge call; call it explicitly before capturing those calls in a
+ * HIP graph.  Synchronous.  Errors: CCUT_ENOMEM, CCUT_EHIP.
+ */
+int ccut_plan_prepare(ccut_plan_t* plan);
+
+/*
+ * Subcircuit simulation, Algorithm 2 (Appendix B): for every segment i and
+ * variant r in [0, 2^{c_i}), psi_i^{(r)} = (segment i's gates with the cut
+ * slots set by r) |0...0>, written to the arena at the plan's layout.
+ *
+ *   d_arena      device buffer of at least info.arena_bytes bytes
+ *   arena_bytes  its size
+ * Errors: CCUT_ENOSPC (arena too small), CCUT_EINVAL, CCUT_EHIP.
+ */
+int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* stream);
+
+/* Merge precisions (Algorithm 3 arithmetic). */
+enum {
+  CCUT_PREC_AUTO = -1,   /* pick by term count: FP32 for few terms, BF16X3 above the ridge */
+  CCUT_PREC_FP32 = 0,    /* complex64 factors, float32 FMA accumulation (vector ALUs) */
+  CCUT_PREC_BF16X3 = 1,  /* factors split hi + lo in bfloat16, hi.hi + hi.lo + lo.hi on MFMA, float32 accumulate */
+  CCUT_PREC_FP16X3 = 2,  /* as BF16X3 with float16 halves and power-of-two pre-scaling */
+  CCUT_PREC_BF16 = 3     /* unsplit bfloat16 on MFMA: a low-accuracy control */
+};
+
+/*
+ * Merging, Algorithm 3 (Appendix B):
+ *   Psi = sum over all 2^{c_total} cut-term combinations m of
+ *         alpha_m  psi_{n-1}^{(r_{n-1}(m))} (x) ... (x) psi_0^{(r_0(m))},
+ * alpha_m being the product of the per-cut weights of Eq. (CZ).  For n >= 3 the
+ * sum is contracted boundary by boundary (same result up to rounding).
+ *
+ *   d_arena    the arena filled by ccut_simulate_subcircuits; its workspace
+ *              part (past info.state_bytes) is overwritten
+ *   d_psi      output, 2^q complex64 (psi_bytes >= info.psi_bytes); written once
+ *   precision  one of CCUT_PREC_*
+ * Errors: CCUT_ENOSPC, CCUT_EINVAL (unknown precision), CCUT_EHIP.
+ */
+int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* d_psi,
+                          uint64_t psi_bytes, int32_t precision, void* stream);
+
+/*
+ * The uncut baseline T_orig (Sec. III.A): the whole circuit applied gate by
+ * gate to |0...0> of q qubits, written to d_psi (2^q complex64).  The gate
+ * list is compiled on the host (compiled programs are cached by content) and
+ * run as LDS-blocked passes over the state in HBM.
+ * Errors: CCUT_EINVAL, CCUT_ENOSPC, CCUT_ENOMEM, CCUT_EHIP.
+ */
+int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, void* d_psi,
+                        uint64_t psi_bytes, void* stream);
+
+/*
+ * Float64 diagnostics of a 2^q complex64 state d_psi against an optional
+ * reference d_ref (NULL: reference terms are 0).  Cutting reproduces the uncut
+ * state exactly up to rounding (Sec. III); these measure how closely.
+ *   out[0] = |psi|^2, out[1] = |ref|^2, out[2] = Re <ref|psi>,
+ *   out[3] = Im <ref|psi>, out[4] = max_x |psi[x] - ref[x]|.
+ * `out` is host memory; the call synchronises `stream` before returning.
+ * Errors: CCUT_EINVAL, CCUT_EHIP.
+ */
+int ccut_norm_fidelity(const void* d_psi, const void* d_ref, int32_t q, double out[5], void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* ccut_last_error(void);
+
+/* Library build identification string (static). */
+const char* ccut_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCUT_H_ */

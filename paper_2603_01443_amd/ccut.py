@@ -1,0 +1,242 @@
+"""ctypes binding of libccut.so (argument marshalling only).
+
+Every function here has the name of a C entry point of include/ccut.h
+without its ``ccut_`` prefix and forwards to it unchanged: all computation
+happens in the HIP library.  Device buffers are passed as integer addresses
+(``tensor.data_ptr()``) with their byte sizes, or as objects exposing
+``data_ptr()`` / ``numel()`` / ``element_size()`` (PyTorch tensors); streams as
+integer ``hipStream_t`` handles (``torch.cuda.current_stream().cuda_stream``)
+or None for the default stream.
+
+The library must have been built in-tree (``__graft_entry__.build()``);
+importing this module without it raises ImportError.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libccut.so")
+
+MAX_SEG = 8
+
+OK, EINVAL, EUNCUTTABLE, ENOSPC, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+
+PREC_AUTO, PREC_FP32, PREC_BF16X3, PREC_FP16X3, PREC_BF16 = -1, 0, 1, 2, 3
+PRECISIONS = {"auto": PREC_AUTO, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "fp16x3": PREC_FP16X3,
+              "bf16": PREC_BF16}
+
+GATE_KIND = {
+    "H": 0, "X": 1, "Y": 2, "Z": 3, "S": 4, "SDG": 5, "T": 6, "TDG": 7,
+    "RX": 8, "RY": 9, "RZ": 10, "RYRZ": 11, "CZ": 16, "CX": 17,
+}
+
+GATE_DTYPE = np.dtype([("kind", "<i4"), ("q0", "<i4"), ("q1", "<i4"), ("reserved", "<i4"),
+                       ("p0", "<f8"), ("p1", "<f8")])
+
+
+class CcutError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ccut error {code}: {msg}")
+        self.code = code
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("q", ctypes.c_int32), ("n_seg", ctypes.c_int32), ("c_total", ctypes.c_int32),
+        ("n_gates", ctypes.c_int32),
+        ("seg_size", ctypes.c_int32 * MAX_SEG), ("seg_offset", ctypes.c_int32 * MAX_SEG),
+        ("c_seg", ctypes.c_int32 * MAX_SEG), ("c_boundary", ctypes.c_int32 * MAX_SEG),
+        ("n_sub", ctypes.c_int64), ("n_terms", ctypes.c_int64),
+        ("seg_state_offset", ctypes.c_uint64 * MAX_SEG),
+        ("state_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64), ("psi_bytes", ctypes.c_uint64),
+    ]
+
+
+class CutInfo(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in
+                ("gate_index", "kind", "boundary", "q_low", "q_high", "target_high", "bit_low", "bit_high")]
+
+
+def _load():
+    # PyTorch-ROCm ships its own libamdhip64.so.7.  Loading torch first makes this
+    # library bind to that same runtime, so the process holds one HIP runtime
+    # whichever module the caller imports first.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, u64, i32, i64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "ccut_cut_plan": [i32, vp, i64, i32, vp, ctypes.POINTER(vp)],
+        "ccut_plan_info": [vp, ctypes.POINTER(PlanInfo)],
+        "ccut_plan_cut": [vp, i32, ctypes.POINTER(CutInfo)],
+        "ccut_cut_weight": [i32, ctypes.POINTER(ctypes.c_double)],
+        "ccut_plan_prepare": [vp],
+        "ccut_simulate_subcircuits": [vp, vp, u64, vp],
+        "ccut_merge_full_state": [vp, vp, u64, vp, u64, i32, vp],
+        "ccut_simulate_uncut": [i32, vp, i64, vp, u64, vp],
+        "ccut_norm_fidelity": [vp, vp, i32, ctypes.POINTER(ctypes.c_double), vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.ccut_plan_free.argtypes = [vp]
+    lib.ccut_plan_free.restype = None
+    lib.ccut_last_error.restype = ctypes.c_char_p
+    lib.ccut_version.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _check(rc: int) -> None:
+    if rc != OK:
+        raise CcutError(rc, _lib.ccut_last_error().decode())
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    return int(x)
+
+
+def _nbytes(x, nbytes: Optional[int]) -> int:
+    if nbytes is not None:
+        return int(nbytes)
+    if hasattr(x, "numel"):
+        return int(x.numel() * x.element_size())
+    raise ValueError("byte size required for a raw device address")
+
+
+def _stream(s) -> int:
+    if s is None:
+        return 0
+    if hasattr(s, "cuda_stream"):
+        return int(s.cuda_stream)
+    return int(s)
+
+
+def gate_array(gates: Iterable) -> np.ndarray:
+    """Packs (kind, q0, q1, p0, p1) tuples into the 32-byte ccut_gate_t layout."""
+    gates = list(gates)
+    arr = np.zeros(len(gates), dtype=GATE_DTYPE)
+    for i, g in enumerate(gates):
+        kind, q0 = g[0], g[1]
+        q1 = g[2] if len(g) > 2 else -1
+        p0 = g[3] if len(g) > 3 else 0.0
+        p1 = g[4] if len(g) > 4 else 0.0
+        arr[i] = (GATE_KIND[kind] if isinstance(kind, str) else int(kind), q0, q1, 0, p0, p1)
+    return arr
+
+
+class Plan:
+    """Owner of an opaque ccut_plan_t (freed on garbage collection)."""
+
+    def __init__(self, handle: int, q: int):
+        self._h = ctypes.c_void_p(handle)
+        self.q = q
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(_lib.ccut_plan_info(self._h, ctypes.byref(inf)))
+        n = inf.n_seg
+        return {
+            "q": inf.q, "n_seg": n, "c_total": inf.c_total, "n_gates": inf.n_gates,
+            "seg_size": list(inf.seg_size[:n]), "seg_offset": list(inf.seg_offset[:n]),
+            "c_seg": list(inf.c_seg[:n]), "c_boundary": list(inf.c_boundary[:max(0, n - 1)]),
+            "n_sub": inf.n_sub, "n_terms": inf.n_terms,
+            "seg_state_offset": list(inf.seg_state_offset[:n]),
+            "state_bytes": inf.state_bytes, "arena_bytes": inf.arena_bytes, "psi_bytes": inf.psi_bytes,
+        }
+
+    def cuts(self) -> List[dict]:
+        out = []
+        for j in range(self.info()["c_total"]):
+            c = CutInfo()
+            _check(_lib.ccut_plan_cut(self._h, j, ctypes.byref(c)))
+            out.append({f: getattr(c, f) for f, _ in CutInfo._fields_})
+        return out
+
+    def free(self) -> None:
+        if self._h and self._h.value:
+            _lib.ccut_plan_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def cut_plan(q: int, gates, n_seg: int, seg_sizes: Optional[Sequence[int]] = None) -> Plan:
+    arr = gates if isinstance(gates, np.ndarray) and gates.dtype == GATE_DTYPE else gate_array(gates)
+    arr = np.ascontiguousarray(arr)
+    sizes = None
+    if seg_sizes is not None:
+        sizes = (ctypes.c_int32 * len(seg_sizes))(*seg_sizes)
+    h = ctypes.c_void_p(0)
+    _check(_lib.ccut_cut_plan(q, arr.ctypes.data, len(arr), n_seg, sizes, ctypes.byref(h)))
+    return Plan(h.value, q)
+
+
+def plan_prepare(plan: Plan) -> None:
+    _check(_lib.ccut_plan_prepare(plan.handle))
+
+
+def cut_weight(bit: int) -> complex:
+    out = (ctypes.c_double * 2)()
+    _check(_lib.ccut_cut_weight(bit, out))
+    return complex(out[0], out[1])
+
+
+def simulate_subcircuits(plan: Plan, arena, arena_bytes: Optional[int] = None, stream=None) -> None:
+    _check(_lib.ccut_simulate_subcircuits(plan.handle, _ptr(arena), _nbytes(arena, arena_bytes), _stream(stream)))
+
+
+def merge_full_state(plan: Plan, arena, psi, precision="fp32", arena_bytes: Optional[int] = None,
+                     psi_bytes: Optional[int] = None, stream=None) -> None:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(_lib.ccut_merge_full_state(plan.handle, _ptr(arena), _nbytes(arena, arena_bytes), _ptr(psi),
+                                      _nbytes(psi, psi_bytes), prec, _stream(stream)))
+
+
+def simulate_uncut(q: int, gates, psi, psi_bytes: Optional[int] = None, stream=None) -> None:
+    arr = gates if isinstance(gates, np.ndarray) and gates.dtype == GATE_DTYPE else gate_array(gates)
+    arr = np.ascontiguousarray(arr)
+    _check(_lib.ccut_simulate_uncut(q, arr.ctypes.data, len(arr), _ptr(psi), _nbytes(psi, psi_bytes),
+                                    _stream(stream)))
+
+
+def norm_fidelity(psi, ref, q: int, stream=None) -> dict:
+    out = (ctypes.c_double * 5)()
+    _check(_lib.ccut_norm_fidelity(_ptr(psi), _ptr(ref), q, out, _stream(stream)))
+    n2p, n2r, ore, oim, mx = out[:]
+    res = {"norm2": n2p, "ref_norm2": n2r, "overlap": complex(ore, oim), "max_abs": mx}
+    if ref is not None and n2p > 0 and n2r > 0:
+        res["fidelity"] = (ore * ore + oim * oim) / (n2p * n2r)
+    return res
+
+
+def version() -> str:
+    return _lib.ccut_version().decode()

@@ -1,0 +1,258 @@
+// C-ABI entry points: error reporting, device tables, and the device stages
+// of the pipeline (subcircuit simulation, merge, uncut baseline, diagnostics).
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+
+#include "plan.h"
+
+namespace ccut {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? CCUT_ENOMEM : CCUT_EHIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+void release_device(DeviceTables& t) {
+  if (t.device < 0) return;
+  int cur = 0;
+  if (hipGetDevice(&cur) == hipSuccess && cur != t.device) (void)hipSetDevice(t.device);
+  if (t.ops) (void)hipFree(t.ops);
+  if (t.passes) (void)hipFree(t.passes);
+  if (t.jobs) (void)hipFree(t.jobs);
+  if (t.weights) (void)hipFree(t.weights);
+  if (cur != t.device) (void)hipSetDevice(cur);
+  t = DeviceTables();
+}
+
+template <class T>
+static int upload(const std::vector<T>& v, T** dst) {
+  *dst = nullptr;
+  if (v.empty()) return 0;
+  CCUT_HIP(hipMalloc((void**)dst, v.size() * sizeof(T)));
+  CCUT_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return 0;
+}
+
+int upload_tables(DeviceTables& t, const std::vector<KOp>& ops, const std::vector<PassDesc>& passes,
+                  const std::vector<SimJob>& jobs, const std::vector<float>& weights) {
+  int dev = 0;
+  CCUT_HIP(hipGetDevice(&dev));
+  if (t.device == dev) return 0;
+  release_device(t);
+  int rc;
+  if ((rc = upload(ops, &t.ops)) || (rc = upload(passes, &t.passes)) || (rc = upload(jobs, &t.jobs)) ||
+      (rc = upload(weights, &t.weights))) {
+    t.device = dev;
+    release_device(t);
+    return rc;
+  }
+  t.device = dev;
+  return 0;
+}
+
+// Per-device buffer for reduction partials (allocated once, kept for the process).
+constexpr int RED_BLOCKS = 1024;
+static std::mutex g_red_mu;
+static double* g_red_buf[64] = {nullptr};
+
+int reduction_buffer(double** out) {
+  int dev = 0;
+  CCUT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(CCUT_EUNSUPPORTED, "device id %d", dev);
+  static std::mutex alloc_mu;
+  std::lock_guard<std::mutex> lk(alloc_mu);
+  if (!g_red_buf[dev]) CCUT_HIP(hipMalloc((void**)&g_red_buf[dev], (RED_BLOCKS * 5 + 8) * sizeof(double)));
+  *out = g_red_buf[dev];
+  return 0;
+}
+
+// ---------------------------------------------------------------- uncut cache
+struct UncutProg {
+  uint64_t key = 0;
+  int32_t q = 0;
+  std::vector<ccut_gate_t> gates;
+  std::vector<PassDesc> descs;
+  std::vector<KOp> kops;
+  std::vector<SimJob> jobs;  // one per pass
+  DeviceTables dev;
+  uint64_t stamp = 0;
+};
+
+static std::mutex g_uncut_mu;
+static std::map<uint64_t, std::unique_ptr<UncutProg>> g_uncut;
+static uint64_t g_uncut_clock = 0;
+constexpr size_t UNCUT_CACHE = 8;
+
+static uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  return h;
+}
+
+int compile_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, UncutProg& U) {
+  ProgramBuilder pb(q);
+  for (int64_t k = 0; k < n_gates; ++k) {
+    const ccut_gate_t& g = gates[k];
+    const bool two = g.kind == CCUT_GATE_CZ || g.kind == CCUT_GATE_CX;
+    const bool one = g.kind >= CCUT_GATE_H && g.kind <= CCUT_GATE_RYRZ;
+    if ((!one && !two) || g.q0 < 0 || g.q0 >= q || (two && (g.q1 < 0 || g.q1 >= q || g.q1 == g.q0)))
+      return fail(CCUT_EINVAL, "gate %lld is invalid for q=%d", (long long)k, q);
+    if (g.kind == CCUT_GATE_CZ) pb.cz(g.q0, g.q1);
+    else if (g.kind == CCUT_GATE_CX) pb.cx(g.q0, g.q1);
+    else {
+      cd m[4];
+      gate_matrix(g, m);
+      pb.one_qubit(g.q0, m, m, -1);
+    }
+  }
+  std::vector<Pass> passes;
+  if (int rc = schedule_passes(pb.prog, PASS_MAX_B, 4, passes)) return rc;
+  for (const Pass& p : passes) {
+    int pid = append_pass(p, q, U.descs, U.kops);
+    SimJob j;
+    std::memset(&j, 0, sizeof(j));
+    j.pass_id = pid;
+    U.jobs.push_back(j);
+  }
+  return 0;
+}
+
+}  // namespace ccut
+
+using namespace ccut;
+
+extern "C" const char* ccut_last_error(void) { return g_err; }
+
+extern "C" const char* ccut_version(void) { return "ccut 0.1 gfx950"; }
+
+extern "C" int ccut_plan_prepare(ccut_plan_t* plan) {
+  clear_error();
+  if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
+  return upload_tables(plan->dev, plan->kops, plan->pass_descs, plan->jobs, plan->weights);
+}
+
+extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* stream) {
+  clear_error();
+  if (!plan || !d_arena) return fail(CCUT_EINVAL, "NULL argument");
+  if (arena_bytes < plan->arena_bytes + plan->split_bytes)
+    return fail(CCUT_ENOSPC, "arena has %llu bytes, plan needs %llu", (unsigned long long)arena_bytes,
+                (unsigned long long)(plan->arena_bytes + plan->split_bytes));
+  if (int rc = ccut_plan_prepare(plan)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (const auto& L : plan->launches) {
+    if (int rc = launch_sim(plan->dev.jobs + L.job_begin, L.n_jobs, L.total_wg, plan->dev.passes, plan->dev.ops,
+                            static_cast<float*>(d_arena), plan->bmax, 256, s))
+      return rc;
+  }
+  return CCUT_OK;
+}
+
+extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* d_psi,
+                                     uint64_t psi_bytes, int32_t precision, void* stream) {
+  clear_error();
+  if (!plan || !d_arena || !d_psi) return fail(CCUT_EINVAL, "NULL argument");
+  if (arena_bytes < plan->arena_bytes + plan->split_bytes) return fail(CCUT_ENOSPC, "arena too small");
+  if (psi_bytes < plan->psi_bytes)
+    return fail(CCUT_ENOSPC, "psi has %llu bytes, needs %llu", (unsigned long long)psi_bytes,
+                (unsigned long long)plan->psi_bytes);
+  if (precision < CCUT_PREC_AUTO || precision > CCUT_PREC_BF16)
+    return fail(CCUT_EINVAL, "unknown precision %d", precision);
+  if (precision != CCUT_PREC_AUTO && precision != CCUT_PREC_FP32)
+    return fail(CCUT_EUNSUPPORTED, "precision %d not built yet", precision);
+  if (int rc = ccut_plan_prepare(plan)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* arena = static_cast<char*>(d_arena);
+  if (plan->n_seg == 1) {
+    CCUT_HIP(hipMemcpyAsync(d_psi, arena + plan->segs[0].arena_off, plan->psi_bytes, hipMemcpyDeviceToDevice, s));
+    return CCUT_OK;
+  }
+  auto buf = [&](int id) -> float* {
+    if (id == 0) return reinterpret_cast<float*>(arena);
+    if (id == 1) return reinterpret_cast<float*>(arena + plan->temp_off[0]);
+    if (id == 2) return reinterpret_cast<float*>(arena + plan->temp_off[1]);
+    return static_cast<float*>(d_psi);
+  };
+  for (const MergeStage& st : plan->stages) {
+    if (int rc = launch_merge_f32(st, buf(st.a_src), buf(st.b_src), buf(st.out_dst), plan->dev.weights, s)) return rc;
+  }
+  return CCUT_OK;
+}
+
+extern "C" int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, void* d_psi,
+                                   uint64_t psi_bytes, void* stream) {
+  clear_error();
+  if (q < 1 || q > CCUT_MAX_Q) return fail(CCUT_EINVAL, "q=%d outside [1, %d]", q, CCUT_MAX_Q);
+  if (!d_psi || n_gates < 0 || (n_gates > 0 && !gates)) return fail(CCUT_EINVAL, "bad argument");
+  if (psi_bytes < ((uint64_t)8 << q)) return fail(CCUT_ENOSPC, "psi buffer too small for q=%d", q);
+  uint64_t key = fnv1a(&q, sizeof(q), 1469598103934665603ull);
+  key = fnv1a(gates, sizeof(ccut_gate_t) * (size_t)n_gates, key);
+  int dev = 0;
+  CCUT_HIP(hipGetDevice(&dev));
+  key = fnv1a(&dev, sizeof(dev), key);
+  std::lock_guard<std::mutex> lk(g_uncut_mu);
+  UncutProg* U = nullptr;
+  auto it = g_uncut.find(key);
+  if (it != g_uncut.end() && it->second->q == q && it->second->gates.size() == (size_t)n_gates &&
+      std::memcmp(it->second->gates.data(), gates, sizeof(ccut_gate_t) * (size_t)n_gates) == 0) {
+    U = it->second.get();
+  } else {
+    auto fresh = std::make_unique<UncutProg>();
+    fresh->key = key;
+    fresh->q = q;
+    fresh->gates.assign(gates, gates + n_gates);
+    if (int rc = compile_uncut(q, gates, n_gates, *fresh)) return rc;
+    if (int rc = upload_tables(fresh->dev, fresh->kops, fresh->descs, fresh->jobs, std::vector<float>())) return rc;
+    if (g_uncut.size() >= UNCUT_CACHE) {
+      auto oldest = g_uncut.begin();
+      for (auto i = g_uncut.begin(); i != g_uncut.end(); ++i)
+        if (i->second->stamp < oldest->second->stamp) oldest = i;
+      release_device(oldest->second->dev);
+      g_uncut.erase(oldest);
+    }
+    U = fresh.get();
+    g_uncut[key] = std::move(fresh);
+  }
+  U->stamp = ++g_uncut_clock;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (size_t p = 0; p < U->jobs.size(); ++p) {
+    if (int rc = launch_sim(U->dev.jobs + p, 1, U->descs[p].n_blocks, U->dev.passes, U->dev.ops,
+                            static_cast<float*>(d_psi), PASS_MAX_B, 256, s))
+      return rc;
+  }
+  return CCUT_OK;
+}
+
+extern "C" int ccut_norm_fidelity(const void* d_psi, const void* d_ref, int32_t q, double out[5], void* stream) {
+  clear_error();
+  if (!d_psi || !out) return fail(CCUT_EINVAL, "NULL argument");
+  if (q < 0 || q > CCUT_MAX_Q) return fail(CCUT_EINVAL, "q=%d out of range", q);
+  double* buf = nullptr;
+  if (int rc = reduction_buffer(&buf)) return rc;
+  std::lock_guard<std::mutex> lk(g_red_mu);  // one partials buffer per device
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint64_t n = (uint64_t)1 << q;
+  int blocks = (int)std::min<uint64_t>(RED_BLOCKS, (n + 255) / 256);
+  if (int rc = launch_reduce(static_cast<const float*>(d_psi), static_cast<const float*>(d_ref), n, buf, blocks,
+                             buf + RED_BLOCKS * 5, s))
+    return rc;
+  CCUT_HIP(hipMemcpyAsync(out, buf + RED_BLOCKS * 5, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+  CCUT_HIP(hipStreamSynchronize(s));
+  return CCUT_OK;
+}

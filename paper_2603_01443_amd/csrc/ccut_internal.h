@@ -1,0 +1,144 @@
+// Internal definitions shared by the host planner and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ccut.h"
+
+namespace ccut {
+
+// ----------------------------------------------------------------- errors
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+int hip_fail(hipError_t e, const char* what);
+
+#define CCUT_HIP(call)                                   \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return ::ccut::hip_fail(e_, #call); \
+  } while (0)
+
+using cd = std::complex<double>;
+
+// ------------------------------------------------------- register-level ops
+// A gate program on an m-qubit register after single-qubit fusion.
+enum HOpKind : int32_t { HOP_1Q = 0, HOP_CZ = 1, HOP_CX = 2 };
+
+struct HOp {
+  int32_t kind;
+  int32_t q0, q1;  // 1Q: q0 only.  CX: q0 = control, q1 = target
+  bool diag;       // 1Q matrix is diagonal
+  int32_t slot;    // -1, or the variant bit choosing m[1] over m[0]
+  cd m[2][4];      // row-major 2x2 (m00, m01, m10, m11) for slot bit 0 / 1
+};
+
+struct Program {
+  int32_t nq = 0;
+  std::vector<HOp> ops;
+};
+
+// Append a single-qubit matrix, fusing it into the previous single-qubit op on
+// that qubit when every op in between on the qubit commutes with it.
+struct ProgramBuilder {
+  Program prog;
+  std::vector<int32_t> last1q;   // index of the last 1Q op per qubit, -1 if none
+  std::vector<uint8_t> any_since, nondiag_since;
+  explicit ProgramBuilder(int nq);
+  void one_qubit(int t, const cd m0[4], const cd m1[4], int slot);
+  void cz(int a, int b);
+  void cx(int c, int t);
+};
+
+// --------------------------------------------------------- device op format
+enum KOpType : int32_t {
+  KOP_DENSE = 0,   // 2x2 on local bit a
+  KOP_DIAG = 1,    // diag(m0, m3) on local bit a
+  KOP_CZL = 2,     // sign flip where sum_t popcount(i & (i >> shift_t) & mask_t) is odd
+  KOP_SCALAR = 3,  // multiply the block by m0 (bit a of the block base is 0) or m3 (it is 1)
+  KOP_CXL = 4,     // CX with local control a, local target b
+};
+
+constexpr int KOP_MAX_TERMS = 8;
+
+struct KOp {
+  int32_t type;
+  int32_t a, b;
+  int32_t slot;   // -1 or variant bit selecting m[8..15] over m[0..7]
+  int32_t cond;   // -1, or register qubit whose bit in the block base must be 1
+  int32_t nterms; // KOP_CZL term count
+  int32_t pad[2];
+  float m[16];    // (re, im) of m00, m01, m10, m11 per slot; KOP_CZL: uint32 (shift, mask) pairs
+};
+static_assert(sizeof(KOp) == 96, "KOp layout");
+
+constexpr int PASS_MAX_B = 14;   // 2^14 complex64 = 128 KiB of LDS per block
+
+// One LDS-blocked pass over a state: blocks of 2^b amplitudes spanning the
+// register qubits group[0..b); the other qubits are fixed per block.
+struct PassDesc {
+  int32_t b;         // local bits
+  int32_t nq;        // register qubits
+  int32_t op_begin;  // into the op table
+  int32_t op_count;
+  int32_t init;      // 1: the state is |0...0> before this pass (nothing is read)
+  int32_t n_blocks;  // 2^(nq - b)
+  int32_t group[24]; // local bit j -> register qubit
+  int32_t fixed[24]; // j-th non-group qubit (ascending), takes bit j of the block id
+};
+
+struct Pass {
+  std::vector<int32_t> group;  // size b, low qubits first
+  std::vector<KOp> kops;
+  bool init = false;
+};
+
+// Schedule a program into LDS-blocked passes of at most 2^bmax amplitudes.
+// Low qubits [0, low_bits) sit in every block (coalesced runs).
+int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out);
+
+// A launch entry: one state (or a batch position) processed by one pass.
+struct SimJob {
+  uint64_t state_off;  // complex64 elements from the launch base pointer
+  int32_t pass_id;     // into the PassDesc table
+  int32_t variant;
+  int32_t wg_begin;    // first workgroup of this job in the launch
+  int32_t pad;
+};
+
+// ------------------------------------------------------------- merge stage
+// out[beta][y * NX + x] = sum_k w_k A(beta, k)[x] B(beta, k)[y]
+struct MergeStage {
+  int32_t K;             // terms
+  int32_t batch;         // independent outputs
+  int32_t qx, qy;        // log2 NX, log2 NY
+  int32_t a_src, b_src;  // buffer ids: 0 = arena states, 1 = temp ping, 2 = temp pong, 3 = psi
+  int32_t out_dst;
+  int32_t weight_off;    // into the weight table (K entries)
+  uint64_t a_off, b_off, out_off;          // complex64 elements from the buffer base
+  uint64_t a_kstride, a_bstride, b_kstride, b_bstride, out_bstride;  // complex64 elements
+};
+
+// --------------------------------------------------------- device launches
+struct DeviceTables {
+  int device = -1;
+  KOp* ops = nullptr;
+  PassDesc* passes = nullptr;
+  SimJob* jobs = nullptr;
+  float* weights = nullptr;    // complex64 merge weights
+};
+
+int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, const PassDesc* d_passes,
+               const KOp* d_ops, float* base, int bmax, int threads, hipStream_t s);
+
+int launch_merge_f32(const MergeStage& st, const float* A, const float* B, float* out,
+                     const float* d_weights, hipStream_t s);
+
+int launch_reduce(const float* psi, const float* ref, uint64_t n, double* d_partials, int n_blocks,
+                  double* d_out, hipStream_t s);
+
+}  // namespace ccut

@@ -1,0 +1,318 @@
+// Preprocessing (Algorithm 1, Appendix B): find the cut gates, build one gate
+// program per segment with an S / S^dag slot per adjacent cut, size the arena,
+// and lay out the merge stages of Algorithm 3.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+namespace ccut {
+
+int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<KOp>& kops) {
+  PassDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.b = (int32_t)p.group.size();
+  d.nq = nq;
+  d.op_begin = (int32_t)kops.size();
+  d.op_count = (int32_t)p.kops.size();
+  d.init = p.init ? 1 : 0;
+  d.n_blocks = 1 << (nq - d.b);
+  std::vector<uint8_t> in(nq, 0);
+  for (int j = 0; j < d.b; ++j) {
+    d.group[j] = p.group[j];
+    in[p.group[j]] = 1;
+  }
+  int f = 0;
+  for (int t = 0; t < nq; ++t)
+    if (!in[t]) d.fixed[f++] = t;
+  kops.insert(kops.end(), p.kops.begin(), p.kops.end());
+  descs.push_back(d);
+  return (int)descs.size() - 1;
+}
+
+}  // namespace ccut
+
+using namespace ccut;
+
+namespace {
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// Per-cut weight of Eq. (CZ): s_0 = 1/(1+i), s_1 = i/(1+i).
+cd cut_weight(int bit) { return bit ? cd(0.5, 0.5) : cd(0.5, -0.5); }
+
+int validate_gate(const ccut_gate_t& g, int q, int64_t k) {
+  const bool two = g.kind == CCUT_GATE_CZ || g.kind == CCUT_GATE_CX;
+  const bool one = g.kind >= CCUT_GATE_H && g.kind <= CCUT_GATE_RYRZ;
+  if (!one && !two) return fail(CCUT_EINVAL, "gate %lld: unknown kind %d", (long long)k, g.kind);
+  if (g.q0 < 0 || g.q0 >= q) return fail(CCUT_EINVAL, "gate %lld: qubit %d out of range", (long long)k, g.q0);
+  if (two && (g.q1 < 0 || g.q1 >= q || g.q1 == g.q0))
+    return fail(CCUT_EINVAL, "gate %lld: bad second qubit %d", (long long)k, g.q1);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gates, int32_t n_seg,
+                             const int32_t* seg_sizes, ccut_plan_t** plan_out) {
+  clear_error();
+  if (!plan_out) return fail(CCUT_EINVAL, "plan_out is NULL");
+  *plan_out = nullptr;
+  if (q < 1 || q > CCUT_MAX_Q) return fail(CCUT_EINVAL, "q=%d outside [1, %d]", q, CCUT_MAX_Q);
+  if (n_seg < 1 || n_seg > CCUT_MAX_SEG || n_seg > q)
+    return fail(CCUT_EINVAL, "n_seg=%d outside [1, min(q, %d)]", n_seg, CCUT_MAX_SEG);
+  if (n_gates < 0 || (n_gates > 0 && !gates)) return fail(CCUT_EINVAL, "bad gate array");
+  if (n_gates > (int64_t)1 << 30) return fail(CCUT_EINVAL, "too many gates");
+
+  ccut_plan* P = new (std::nothrow) ccut_plan();
+  if (!P) return fail(CCUT_ENOMEM, "host allocation failed");
+  std::unique_ptr<ccut_plan> guard(P);
+  P->q = q;
+  P->n_seg = n_seg;
+  P->n_gates = (int32_t)n_gates;
+  P->segs.resize(n_seg);
+  int acc = 0;
+  for (int i = 0; i < n_seg; ++i) {
+    int s = seg_sizes ? seg_sizes[i] : q / n_seg + (i >= n_seg - q % n_seg ? 1 : 0);
+    if (s < 1) return fail(CCUT_EINVAL, "segment %d has size %d", i, s);
+    P->segs[i].q = s;
+    P->segs[i].off = acc;
+    acc += s;
+  }
+  if (acc != q) return fail(CCUT_EINVAL, "segment sizes add up to %d, not q=%d", acc, q);
+  std::vector<int> seg_of(q);
+  for (int i = 0; i < n_seg; ++i)
+    for (int t = 0; t < P->segs[i].q; ++t) seg_of[P->segs[i].off + t] = i;
+
+  // Algorithm 1: scan for boundary gates.
+  std::vector<std::vector<int64_t>> on_boundary(std::max(0, n_seg - 1));
+  for (int64_t k = 0; k < n_gates; ++k) {
+    const ccut_gate_t& g = gates[k];
+    if (int rc = validate_gate(g, q, k)) return rc;
+    if (g.kind != CCUT_GATE_CZ && g.kind != CCUT_GATE_CX) continue;
+    int sa = seg_of[g.q0], sb = seg_of[g.q1];
+    if (sa == sb) continue;
+    if (std::abs(sa - sb) != 1)
+      return fail(CCUT_EUNCUTTABLE, "gate %lld joins non-adjacent segments %d and %d", (long long)k, sa, sb);
+    on_boundary[std::min(sa, sb)].push_back(k);
+  }
+  P->c_b.assign(std::max(0, n_seg - 1), 0);
+  for (int b = 0; b + 1 < n_seg; ++b) P->c_b[b] = (int32_t)on_boundary[b].size();
+  for (int i = 0; i < n_seg; ++i) {
+    auto& S = P->segs[i];
+    S.c_lo = i > 0 ? P->c_b[i - 1] : 0;
+    S.c_hi = i + 1 < n_seg ? P->c_b[i] : 0;
+    S.c = S.c_lo + S.c_hi;
+    if (S.c > CCUT_MAX_CUTS_PER_SEG)
+      return fail(CCUT_EUNSUPPORTED, "segment %d has %d adjacent cuts (max %d)", i, S.c, CCUT_MAX_CUTS_PER_SEG);
+  }
+  // Cut numbering: boundary-major, gate order within a boundary.
+  std::vector<int> cut_of_gate(n_gates, -1);
+  for (int b = 0; b + 1 < n_seg; ++b) {
+    for (size_t j = 0; j < on_boundary[b].size(); ++j) {
+      int64_t k = on_boundary[b][j];
+      const ccut_gate_t& g = gates[k];
+      ccut_cut_info_t c;
+      std::memset(&c, 0, sizeof(c));
+      c.gate_index = (int32_t)k;
+      c.kind = g.kind;
+      c.boundary = b;
+      bool q0_low = seg_of[g.q0] == b;
+      c.q_low = q0_low ? g.q0 : g.q1;
+      c.q_high = q0_low ? g.q1 : g.q0;
+      c.target_high = (g.kind == CCUT_GATE_CX && q0_low) ? 1 : 0;
+      // segment b sees this boundary as its upper one; segment b+1 as its lower one
+      c.bit_low = P->segs[b].c_lo + (int32_t)j;
+      c.bit_high = (int32_t)j;
+      cut_of_gate[k] = (int)P->cuts.size();
+      P->cuts.push_back(c);
+    }
+  }
+
+  // Per-segment programs: the segment's own gates, plus a slot per adjacent cut.
+  for (int i = 0; i < n_seg; ++i) {
+    auto& S = P->segs[i];
+    ProgramBuilder pb(S.q);
+    for (int64_t k = 0; k < n_gates; ++k) {
+      const ccut_gate_t& g = gates[k];
+      int cj = cut_of_gate[k];
+      if (cj >= 0) {
+        const ccut_cut_info_t& c = P->cuts[cj];
+        int side;  // 0: this segment holds q_low, 1: q_high
+        if (c.boundary == i) side = 0;
+        else if (c.boundary + 1 == i) side = 1;
+        else continue;
+        int local = (side == 0 ? c.q_low : c.q_high) - S.off;
+        int slot = side == 0 ? c.bit_low : c.bit_high;
+        cd s0[4] = {1, 0, 0, cd(0, 1)}, s1[4] = {1, 0, 0, cd(0, -1)};
+        bool is_target = c.kind == CCUT_GATE_CX && ((side == 1) == (c.target_high == 1));
+        if (is_target) {  // H S H and H S^dag H
+          const double r2 = 1.0 / std::sqrt(2.0);
+          cd h[4] = {r2, r2, r2, -r2}, t0[4], t1[4];
+          auto mm = [](const cd* a, const cd* b, cd* o) {
+            cd r[4] = {a[0] * b[0] + a[1] * b[2], a[0] * b[1] + a[1] * b[3],
+                       a[2] * b[0] + a[3] * b[2], a[2] * b[1] + a[3] * b[3]};
+            for (int z = 0; z < 4; ++z) o[z] = r[z];
+          };
+          mm(s0, h, t0); mm(h, t0, s0);
+          mm(s1, h, t1); mm(h, t1, s1);
+        }
+        pb.one_qubit(local, s0, s1, slot);
+        continue;
+      }
+      if (seg_of[g.q0] != i) continue;
+      if (g.kind == CCUT_GATE_CZ) pb.cz(g.q0 - S.off, g.q1 - S.off);
+      else if (g.kind == CCUT_GATE_CX) pb.cx(g.q0 - S.off, g.q1 - S.off);
+      else {
+        cd m[4];
+        gate_matrix(g, m);
+        pb.one_qubit(g.q0 - S.off, m, m, -1);
+      }
+    }
+    S.prog = std::move(pb.prog);
+    if (int rc = schedule_passes(S.prog, P->bmax, P->low_bits, S.passes)) return rc;
+  }
+
+  // Arena: segment-major, variant-minor, 256-byte aligned bases.
+  uint64_t off = 0;
+  for (auto& S : P->segs) {
+    S.arena_off = off;
+    off = align256(off + ((uint64_t)8 << S.q) * ((uint64_t)1 << S.c));
+  }
+  P->state_bytes = off;
+  P->psi_bytes = (uint64_t)8 << q;
+
+  // Merge stages (Algorithm 3 contracted boundary by boundary).
+  uint64_t ping = 0, pong = 0;
+  int qacc = P->segs[0].q;
+  for (int k = 0; k + 1 < n_seg; ++k) {
+    const auto& Sn = P->segs[k + 1];
+    MergeStage st;
+    std::memset(&st, 0, sizeof(st));
+    st.K = 1 << P->c_b[k];
+    bool last = (k + 2 == n_seg);
+    st.batch = last ? 1 : (1 << P->c_b[k + 1]);
+    st.qx = qacc;
+    st.qy = Sn.q;
+    if (k == 0) {
+      st.a_src = 0;
+      st.a_off = P->segs[0].arena_off / 8;
+      st.a_kstride = (uint64_t)1 << P->segs[0].q;
+    } else {
+      st.a_src = (k - 1) % 2 == 0 ? 1 : 2;
+      st.a_off = 0;
+      st.a_kstride = (uint64_t)1 << qacc;
+    }
+    st.a_bstride = 0;
+    st.b_src = 0;
+    st.b_off = Sn.arena_off / 8;
+    st.b_kstride = (uint64_t)1 << Sn.q;
+    st.b_bstride = (uint64_t)st.K << Sn.q;
+    st.out_dst = last ? 3 : (k % 2 == 0 ? 1 : 2);
+    st.out_off = 0;
+    st.out_bstride = (uint64_t)1 << (qacc + Sn.q);
+    st.weight_off = (int32_t)(P->weights.size() / 2);
+    for (int m = 0; m < st.K; ++m) {
+      cd w = 1.0;
+      for (int j = 0; j < P->c_b[k]; ++j) w *= cut_weight((m >> j) & 1);
+      P->weights.push_back((float)w.real());
+      P->weights.push_back((float)w.imag());
+    }
+    if (!last) {
+      uint64_t bytes = ((uint64_t)8 << (qacc + Sn.q)) * (uint64_t)st.batch;
+      if (k % 2 == 0) ping = std::max(ping, bytes); else pong = std::max(pong, bytes);
+    }
+    qacc += Sn.q;
+    P->stages.push_back(st);
+  }
+  P->temp_off[0] = P->state_bytes;
+  P->temp_off[1] = align256(P->temp_off[0] + ping);
+  P->arena_bytes = align256(P->temp_off[1] + pong);
+  P->split_off = P->arena_bytes;
+  P->split_bytes = 0;
+
+  // Simulation launches: pass p of every segment that has one, all variants.
+  size_t max_passes = 0;
+  for (auto& S : P->segs) max_passes = std::max(max_passes, S.passes.size());
+  for (size_t p = 0; p < max_passes; ++p) {
+    ccut_plan::Launch L{(int)P->jobs.size(), 0, 0};
+    // largest states first so a persistent grid drains evenly
+    std::vector<int> order;
+    for (int i = 0; i < n_seg; ++i)
+      if (P->segs[i].passes.size() > p) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P->segs[a].q > P->segs[b].q; });
+    for (int i : order) {
+      auto& S = P->segs[i];
+      int pid = append_pass(S.passes[p], S.q, P->pass_descs, P->kops);
+      int nb = P->pass_descs[pid].n_blocks;
+      for (int64_t r = 0; r < ((int64_t)1 << S.c); ++r) {
+        SimJob j;
+        std::memset(&j, 0, sizeof(j));
+        j.state_off = S.arena_off / 8 + ((uint64_t)r << S.q);
+        j.pass_id = pid;
+        j.variant = (int32_t)r;
+        j.wg_begin = L.total_wg;
+        if ((int64_t)L.total_wg + nb > ((int64_t)1 << 31) - 1)
+          return fail(CCUT_EUNSUPPORTED, "simulation launch exceeds 2^31 workgroups");
+        L.total_wg += nb;
+        P->jobs.push_back(j);
+        L.n_jobs++;
+      }
+    }
+    P->launches.push_back(L);
+  }
+
+  *plan_out = guard.release();
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_info(const ccut_plan_t* plan, ccut_plan_info_t* info) {
+  clear_error();
+  if (!plan || !info) return fail(CCUT_EINVAL, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->q = plan->q;
+  info->n_seg = plan->n_seg;
+  info->c_total = (int32_t)plan->cuts.size();
+  info->n_gates = plan->n_gates;
+  info->n_sub = 0;
+  for (int i = 0; i < plan->n_seg; ++i) {
+    const auto& S = plan->segs[i];
+    info->seg_size[i] = S.q;
+    info->seg_offset[i] = S.off;
+    info->c_seg[i] = S.c;
+    info->seg_state_offset[i] = S.arena_off;
+    info->n_sub += (int64_t)1 << S.c;
+  }
+  for (size_t b = 0; b < plan->c_b.size(); ++b) info->c_boundary[b] = plan->c_b[b];
+  info->n_terms = (int64_t)1 << info->c_total;
+  info->state_bytes = plan->state_bytes;
+  info->arena_bytes = plan->arena_bytes + plan->split_bytes;
+  info->psi_bytes = plan->psi_bytes;
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_cut(const ccut_plan_t* plan, int32_t j, ccut_cut_info_t* out) {
+  clear_error();
+  if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
+  if (j < 0 || j >= (int32_t)plan->cuts.size()) return fail(CCUT_EINVAL, "cut %d out of range", j);
+  *out = plan->cuts[j];
+  return CCUT_OK;
+}
+
+extern "C" int ccut_cut_weight(int32_t bit, double out[2]) {
+  clear_error();
+  if (!out || (bit != 0 && bit != 1)) return fail(CCUT_EINVAL, "bit must be 0 or 1");
+  cd w = cut_weight(bit);
+  out[0] = w.real();
+  out[1] = w.imag();
+  return CCUT_OK;
+}
+
+extern "C" void ccut_plan_free(ccut_plan_t* plan) {
+  if (!plan) return;
+  release_device(plan->dev);
+  delete plan;
+}

@@ -1,0 +1,41 @@
+// The cut plan: preprocessing output (Algorithm 1) plus its device tables.
+#pragma once
+
+#include "ccut_internal.h"
+
+struct ccut_plan {
+  struct Seg {
+    int32_t q = 0, off = 0;       // size, first qubit
+    int32_t c_lo = 0, c_hi = 0;   // cuts on the boundary below / above
+    int32_t c = 0;                // c_i
+    uint64_t arena_off = 0;       // bytes
+    ccut::Program prog;
+    std::vector<ccut::Pass> passes;
+  };
+  int32_t q = 0, n_seg = 0, n_gates = 0;
+  std::vector<Seg> segs;
+  std::vector<ccut_cut_info_t> cuts;
+  std::vector<int32_t> c_b;
+  uint64_t state_bytes = 0, arena_bytes = 0, psi_bytes = 0;
+  uint64_t temp_off[2] = {0, 0};  // ping / pong temp regions of the chain merge (bytes)
+  uint64_t split_off = 0, split_bytes = 0;  // split-precision planes of the last merge stage
+  std::vector<ccut::MergeStage> stages;
+  std::vector<float> weights;     // complex64 merge weights, per stage
+
+  // simulation launches: one per pass index, jobs for every (segment, variant)
+  int bmax = ccut::PASS_MAX_B, low_bits = 4;
+  std::vector<ccut::PassDesc> pass_descs;
+  std::vector<ccut::KOp> kops;
+  std::vector<ccut::SimJob> jobs;
+  struct Launch { int job_begin, n_jobs, total_wg; };
+  std::vector<Launch> launches;
+
+  ccut::DeviceTables dev;
+};
+
+namespace ccut {
+// Appends a pass to the device tables; returns its PassDesc index.
+int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<KOp>& kops);
+int gate_matrix(const ccut_gate_t& g, cd m[4]);
+void release_device(DeviceTables& t);
+}  // namespace ccut

@@ -1,0 +1,302 @@
+// Host side: gate matrices, single-qubit fusion and LDS-pass scheduling.
+//
+// A segment's subcircuit (or the whole circuit, for the uncut baseline) is
+// turned into a register-level program.  Consecutive single-qubit gates on a
+// qubit are multiplied into one 2x2 matrix when nothing in between acts on
+// the qubit non-commutingly (a diagonal gate may move back past CZs and CX
+// controls, which are diagonal on that qubit).  The program is then cut into
+// passes: each pass loads blocks of 2^b amplitudes spanning b qubits into LDS
+// and applies every op it can without violating gate order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "ccut_internal.h"
+
+namespace ccut {
+
+namespace {
+
+void matmul2(const cd a[4], const cd b[4], cd out[4]) {  // out = a . b
+  cd r[4] = {a[0] * b[0] + a[1] * b[2], a[0] * b[1] + a[1] * b[3],
+             a[2] * b[0] + a[3] * b[2], a[2] * b[1] + a[3] * b[3]};
+  for (int i = 0; i < 4; ++i) out[i] = r[i];
+}
+
+bool is_diag(const cd m[4]) { return m[1] == cd(0) && m[2] == cd(0); }
+
+}  // namespace
+
+// Qiskit conventions: Rx/Ry/Rz(t) = exp(-i t P / 2); S = diag(1, i); T = diag(1, e^{i pi/4}).
+int gate_matrix(const ccut_gate_t& g, cd m[4]) {
+  const double r2 = 1.0 / std::sqrt(2.0);
+  const cd I(0, 1);
+  switch (g.kind) {
+    case CCUT_GATE_H: m[0] = r2; m[1] = r2; m[2] = r2; m[3] = -r2; return 0;
+    case CCUT_GATE_X: m[0] = 0; m[1] = 1; m[2] = 1; m[3] = 0; return 0;
+    case CCUT_GATE_Y: m[0] = 0; m[1] = -I; m[2] = I; m[3] = 0; return 0;
+    case CCUT_GATE_Z: m[0] = 1; m[1] = 0; m[2] = 0; m[3] = -1; return 0;
+    case CCUT_GATE_S: m[0] = 1; m[1] = 0; m[2] = 0; m[3] = I; return 0;
+    case CCUT_GATE_SDG: m[0] = 1; m[1] = 0; m[2] = 0; m[3] = -I; return 0;
+    case CCUT_GATE_T: m[0] = 1; m[1] = 0; m[2] = 0; m[3] = std::polar(1.0, M_PI / 4); return 0;
+    case CCUT_GATE_TDG: m[0] = 1; m[1] = 0; m[2] = 0; m[3] = std::polar(1.0, -M_PI / 4); return 0;
+    case CCUT_GATE_RX: {
+      double c = std::cos(g.p0 / 2), s = std::sin(g.p0 / 2);
+      m[0] = c; m[1] = -I * s; m[2] = -I * s; m[3] = c; return 0;
+    }
+    case CCUT_GATE_RY: {
+      double c = std::cos(g.p0 / 2), s = std::sin(g.p0 / 2);
+      m[0] = c; m[1] = -s; m[2] = s; m[3] = c; return 0;
+    }
+    case CCUT_GATE_RZ:
+      m[0] = std::polar(1.0, -g.p0 / 2); m[1] = 0; m[2] = 0; m[3] = std::polar(1.0, g.p0 / 2);
+      return 0;
+    case CCUT_GATE_RYRZ: {  // Ry(p0) . Rz(p1)
+      double c = std::cos(g.p0 / 2), s = std::sin(g.p0 / 2);
+      cd e0 = std::polar(1.0, -g.p1 / 2), e1 = std::polar(1.0, g.p1 / 2);
+      m[0] = c * e0; m[1] = -s * e1; m[2] = s * e0; m[3] = c * e1; return 0;
+    }
+    default: return -1;
+  }
+}
+
+ProgramBuilder::ProgramBuilder(int nq)
+    : last1q(nq, -1), any_since(nq, 0), nondiag_since(nq, 0) {
+  prog.nq = nq;
+}
+
+void ProgramBuilder::one_qubit(int t, const cd m0[4], const cd m1[4], int slot) {
+  const bool diag = is_diag(m0) && is_diag(m1);
+  const int li = last1q[t];
+  if (li >= 0) {
+    HOp& p = prog.ops[li];
+    const bool order_ok = !any_since[t] || (diag && !nondiag_since[t]);
+    const bool slot_ok = slot < 0 || p.slot < 0 || p.slot == slot;
+    if (order_ok && slot_ok) {
+      // fused = new . previous, for each slot bit
+      cd f0[4], f1[4];
+      matmul2(m0, p.m[0], f0);
+      matmul2(slot >= 0 ? m1 : m0, p.slot >= 0 ? p.m[1] : p.m[0], f1);
+      for (int i = 0; i < 4; ++i) { p.m[0][i] = f0[i]; p.m[1][i] = f1[i]; }
+      if (slot >= 0) p.slot = slot;
+      p.diag = is_diag(p.m[0]) && is_diag(p.m[1]);
+      return;
+    }
+  }
+  HOp op{};
+  op.kind = HOP_1Q;
+  op.q0 = t;
+  op.q1 = -1;
+  op.slot = slot;
+  for (int i = 0; i < 4; ++i) { op.m[0][i] = m0[i]; op.m[1][i] = m1[i]; }
+  op.diag = diag;
+  last1q[t] = (int32_t)prog.ops.size();
+  any_since[t] = nondiag_since[t] = 0;
+  prog.ops.push_back(op);
+}
+
+void ProgramBuilder::cz(int a, int b) {
+  HOp op{};
+  op.kind = HOP_CZ;
+  op.q0 = a;
+  op.q1 = b;
+  op.diag = true;
+  op.slot = -1;
+  prog.ops.push_back(op);
+  any_since[a] = any_since[b] = 1;
+}
+
+void ProgramBuilder::cx(int c, int t) {
+  HOp op{};
+  op.kind = HOP_CX;
+  op.q0 = c;
+  op.q1 = t;
+  op.diag = false;
+  op.slot = -1;
+  prog.ops.push_back(op);
+  any_since[c] = 1;
+  any_since[t] = nondiag_since[t] = 1;
+  last1q[t] = -1;  // nothing may fuse backwards past a CX target
+}
+
+// ----------------------------------------------------------------- passes
+
+namespace {
+
+// Which qubits an op needs local (acted on non-diagonally), and which it touches diagonally.
+void op_roles(const HOp& op, int* nondiag, int* n_nd, int* diagq, int* n_d) {
+  *n_nd = *n_d = 0;
+  if (op.kind == HOP_1Q) {
+    if (op.diag) diagq[(*n_d)++] = op.q0; else nondiag[(*n_nd)++] = op.q0;
+  } else if (op.kind == HOP_CZ) {
+    diagq[(*n_d)++] = op.q0;
+    diagq[(*n_d)++] = op.q1;
+  } else {  // CX: control is diagonal, target is not
+    diagq[(*n_d)++] = op.q0;
+    nondiag[(*n_nd)++] = op.q1;
+  }
+}
+
+void put_matrix(KOp& k, const HOp& op, bool diag_form) {
+  for (int s = 0; s < 2; ++s) {
+    const cd* m = op.m[s];
+    float* o = k.m + 8 * s;
+    for (int i = 0; i < 4; ++i) { o[2 * i] = (float)m[i].real(); o[2 * i + 1] = (float)m[i].imag(); }
+  }
+  (void)diag_form;
+}
+
+KOp blank(int type) {
+  KOp k;
+  std::memset(&k, 0, sizeof(k));
+  k.type = type;
+  k.slot = -1;
+  k.cond = -1;
+  return k;
+}
+
+void set_phase_pair(KOp& k, cd p0, cd p1) {  // for both slots
+  for (int s = 0; s < 2; ++s) {
+    k.m[8 * s + 0] = (float)p0.real(); k.m[8 * s + 1] = (float)p0.imag();
+    k.m[8 * s + 6] = (float)p1.real(); k.m[8 * s + 7] = (float)p1.imag();
+  }
+}
+
+// Translate register-level ops to block-local device ops for one pass.
+void localize(const Program& prog, const std::vector<int>& take, const std::vector<int32_t>& group,
+              std::vector<KOp>& out) {
+  std::vector<int> loc(prog.nq, -1);
+  for (size_t j = 0; j < group.size(); ++j) loc[group[j]] = (int)j;
+  KOp czl = blank(KOP_CZL);
+  auto flush_czl = [&]() {
+    if (czl.nterms > 0) out.push_back(czl);
+    czl = blank(KOP_CZL);
+  };
+  for (int idx : take) {
+    const HOp& op = prog.ops[idx];
+    if (op.kind == HOP_CZ) {
+      int la = loc[op.q0], lb = loc[op.q1];
+      if (la >= 0 && lb >= 0) {
+        int lo = std::min(la, lb), hi = std::max(la, lb);
+        uint32_t shift = (uint32_t)(hi - lo);
+        uint32_t* t = reinterpret_cast<uint32_t*>(czl.m);
+        int found = -1;
+        for (int i = 0; i < czl.nterms; ++i) if (t[2 * i] == shift) found = i;
+        if (found < 0) {
+          if (czl.nterms == KOP_MAX_TERMS) { flush_czl(); t = reinterpret_cast<uint32_t*>(czl.m); }
+          found = czl.nterms++;
+          t[2 * found] = shift;
+          t[2 * found + 1] = 0;
+        }
+        t[2 * found + 1] ^= (1u << lo);
+        continue;
+      }
+      flush_czl();
+      if (la >= 0 || lb >= 0) {  // Z on the local qubit when the fixed one is 1
+        KOp k = blank(KOP_DIAG);
+        k.a = la >= 0 ? la : lb;
+        k.cond = la >= 0 ? op.q1 : op.q0;
+        set_phase_pair(k, 1.0, -1.0);
+        out.push_back(k);
+      } else {                   // both fixed: -1 on blocks where both bits are 1
+        KOp k = blank(KOP_SCALAR);
+        k.a = op.q0;
+        k.cond = op.q1;
+        set_phase_pair(k, 1.0, -1.0);
+        out.push_back(k);
+      }
+      continue;
+    }
+    flush_czl();
+    if (op.kind == HOP_CX) {
+      int lc = loc[op.q0], lt = loc[op.q1];
+      if (lc >= 0) {
+        KOp k = blank(KOP_CXL);
+        k.a = lc;
+        k.b = lt;
+        out.push_back(k);
+      } else {
+        KOp k = blank(KOP_DENSE);
+        k.a = lt;
+        k.cond = op.q0;
+        k.m[2] = 1; k.m[4] = 1; k.m[10] = 1; k.m[12] = 1;  // X for both slots
+        out.push_back(k);
+      }
+      continue;
+    }
+    // single-qubit
+    int lt = loc[op.q0];
+    KOp k = blank(op.diag ? (lt >= 0 ? KOP_DIAG : KOP_SCALAR) : KOP_DENSE);
+    k.a = lt >= 0 ? lt : op.q0;
+    k.slot = op.slot;
+    put_matrix(k, op, op.diag);
+    out.push_back(k);
+  }
+  flush_czl();
+}
+
+}  // namespace
+
+int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out) {
+  out.clear();
+  const int nq = prog.nq;
+  std::vector<int> pending(prog.ops.size());
+  for (size_t i = 0; i < pending.size(); ++i) pending[i] = (int)i;
+  if (nq <= bmax) {
+    Pass p;
+    for (int j = 0; j < nq; ++j) p.group.push_back(j);
+    p.init = true;
+    localize(prog, pending, p.group, p.kops);
+    out.push_back(std::move(p));
+    return 0;
+  }
+  const int L = std::min(low_bits, bmax);
+  bool first = true;
+  int guard = 0;
+  while (first || !pending.empty()) {
+    if (++guard > 1000000) return fail(CCUT_EINVAL, "pass scheduler made no progress");
+    // qubits ordered by the position of their first pending non-diagonal use
+    std::vector<long> need(nq, (long)1 << 40);
+    for (size_t pos = 0; pos < pending.size(); ++pos) {
+      int nd[2], dq[2], n_nd, n_d;
+      op_roles(prog.ops[pending[pos]], nd, &n_nd, dq, &n_d);
+      for (int i = 0; i < n_nd; ++i) need[nd[i]] = std::min(need[nd[i]], (long)pos);
+    }
+    std::vector<int> cand;
+    for (int t = L; t < nq; ++t) cand.push_back(t);
+    std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) { return need[a] < need[b]; });
+    std::vector<int32_t> group;
+    for (int t = 0; t < L; ++t) group.push_back(t);
+    for (int i = 0; i < bmax - L; ++i) group.push_back(cand[i]);
+    std::sort(group.begin() + L, group.end());
+    std::vector<uint8_t> in_group(nq, 0);
+    for (int t : group) in_group[t] = 1;
+    std::vector<uint8_t> sk_any(nq, 0), sk_nd(nq, 0);
+    std::vector<int> take, keep;
+    for (int idx : pending) {
+      int nd[2], dq[2], n_nd, n_d;
+      op_roles(prog.ops[idx], nd, &n_nd, dq, &n_d);
+      bool ok = true;
+      for (int i = 0; i < n_nd; ++i) ok = ok && in_group[nd[i]] && !sk_any[nd[i]];
+      for (int i = 0; i < n_d; ++i) ok = ok && !sk_nd[dq[i]];
+      if (ok) {
+        take.push_back(idx);
+      } else {
+        keep.push_back(idx);
+        for (int i = 0; i < n_nd; ++i) sk_any[nd[i]] = sk_nd[nd[i]] = 1;
+        for (int i = 0; i < n_d; ++i) sk_any[dq[i]] = 1;
+      }
+    }
+    if (take.empty() && !first) return fail(CCUT_EINVAL, "pass scheduler made no progress");
+    Pass p;
+    p.group = group;
+    p.init = first;
+    localize(prog, take, group, p.kops);
+    out.push_back(std::move(p));
+    pending.swap(keep);
+    first = false;
+  }
+  return 0;
+}
+
+}  // namespace ccut

@@ -1,0 +1,205 @@
+"""GPU parity of the HIP path against the complex128 oracle, through the C-ABI.
+
+Tolerances for the float32 path (complex64 states, float32 arithmetic): every
+fused gate adds a relative rounding error of a few units of 2^-24 to each
+amplitude, so after the ~10^2-10^3 gates of these circuits the relative error
+of an amplitude is ~1e-6; the merge adds K float32 products of such values.
+We require 1 - F <= 1e-9 against the oracle and max-abs <= 1e-4 * 2^{-q/2}
+(2^{-q/2} is the size of a typical amplitude).
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from inputs import Gate, brickwork, equal_blocks, staircase  # noqa: E402
+from oracle import cutting, metrics, statevector  # noqa: E402
+
+from .gpu_util import oracle_key, to_np  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_01443_amd import ccut, pipeline
+    return ccut, pipeline
+
+
+def fp32_tol(q):
+    return 1e-4 * 2 ** (-q / 2)
+
+
+def check_state(ref, got, q, label):
+    err = metrics.max_abs_error(ref, got)
+    inf = metrics.one_minus_fidelity(ref, got)
+    print(f"{label}: max-abs {err:.3e} (tol {fp32_tol(q):.1e}), 1-F {inf:.3e}", flush=True)
+    assert err <= fp32_tol(q), label
+    assert inf <= 1e-9, label
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_small_config_variants_merge_uncut(lib, seed):
+    ccut, pipeline = lib
+    q, d, n, c = 12, 10, 2, 2
+    g = brickwork(q, d, n, c, seed)
+    run = pipeline.CutRun(q, g, n)
+    run.simulate_subcircuits()
+    torch.cuda.synchronize()
+    sizes = [6, 6]
+    ocuts = cutting.find_cuts(q, g, sizes)
+    ostates = cutting.variant_states(q, g, sizes, ocuts)
+    pcuts = run.plan.cuts()
+    for i in range(n):
+        for r in range(2 ** run.info["c_seg"][i]):
+            ref = ostates[oracle_key(pcuts, ocuts, i, r)]
+            got = to_np(run.variant_state(i, r))
+            assert metrics.max_abs_error(ref, got) < 1e-5 * 2 ** (-6 / 2), (i, r)
+    psi = to_np(run.merge("fp32"))
+    check_state(cutting.merge(sizes, ocuts, ostates), psi, q, f"C1 seed {seed} cut")
+    uncut = to_np(pipeline.uncut(q, g))
+    check_state(statevector.simulate(q, g), uncut, q, f"C1 seed {seed} uncut")
+
+
+@pytest.mark.parametrize("c", [2, 4, 6, 8])
+def test_q20_fp32_merge(lib, c):
+    ccut, pipeline = lib
+    q, d, n = 20, 20, 2
+    g = brickwork(q, d, n, c, seed=c)
+    run = pipeline.CutRun(q, g, n)
+    psi = to_np(run.run("fp32"))
+    ref = cutting.cut_simulate(q, g, [10, 10])
+    check_state(ref, psi, q, f"q20 c{c} fp32")
+
+
+def test_q20_uncut_multipass(lib):
+    ccut, pipeline = lib
+    q = 20
+    g = brickwork(q, 12, 2, 3, seed=11)
+    got = to_np(pipeline.uncut(q, g))
+    check_state(statevector.simulate(q, g), got, q, "q20 uncut")
+
+
+@pytest.mark.parametrize("q,n,cuts,sizes,d", [
+    (12, 3, [2, 2], [4, 4, 4], 8),
+    (16, 4, [1, 2, 1], [4, 4, 4, 4], 6),
+    (15, 2, [3], [7, 8], 6),
+    (13, 3, [1, 2], [4, 4, 5], 5),
+    (10, 2, [0], [5, 5], 6),
+    (2, 2, [1], [1, 1], 3),
+    (9, 1, [], [9], 4),
+])
+def test_partitions(lib, q, n, cuts, sizes, d):
+    ccut, pipeline = lib
+    g = brickwork(q, d, n, sum(cuts), seed=q + n, seg_sizes=sizes, cuts_per_boundary=cuts)
+    run = pipeline.CutRun(q, g, n, sizes)
+    psi = to_np(run.run("fp32"))
+    ref = statevector.simulate(q, g)
+    check_state(ref, psi, q, f"q{q} n{n} cuts{cuts}")
+
+
+@pytest.mark.parametrize("q,n,copies", [(6, 2, 1), (8, 2, 3), (9, 3, 2)])
+def test_cx_staircase(lib, q, n, copies):
+    ccut, pipeline = lib
+    g = staircase(q, copies)
+    run = pipeline.CutRun(q, g, n)
+    psi = to_np(run.run("fp32"))
+    check_state(statevector.simulate(q, g), psi, q, f"staircase q{q} n{n}")
+    check_state(statevector.simulate(q, g), to_np(pipeline.uncut(q, g)), q, "staircase uncut")
+
+
+def test_multipass_subcircuits_q30(lib):
+    """15-qubit segments exceed one LDS block: variants run as multi-pass HBM states."""
+    ccut, pipeline = lib
+    q, d, n, c = 30, 6, 2, 2
+    g = brickwork(q, d, n, c, seed=5)
+    run = pipeline.CutRun(q, g, n)
+    run.simulate_subcircuits()
+    torch.cuda.synchronize()
+    sizes = [15, 15]
+    ocuts = cutting.find_cuts(q, g, sizes)
+    ostates = cutting.variant_states(q, g, sizes, ocuts)
+    pcuts = run.plan.cuts()
+    for i in range(n):
+        for r in range(4):
+            ref = ostates[oracle_key(pcuts, ocuts, i, r)]
+            assert metrics.max_abs_error(ref, to_np(run.variant_state(i, r))) < fp32_tol(15), (i, r)
+    psi = run.merge("fp32")
+    rng = np.random.default_rng(0)
+    xs = sorted(set(int(x) for x in rng.integers(0, 2 ** q, size=300)) | {0, 2 ** q - 1, 2 ** 15, 2 ** 15 - 1})
+    want = cutting.amplitudes(xs, sizes, ocuts, ostates)
+    got = to_np(psi[torch.tensor(xs, device=psi.device)])
+    assert np.max(np.abs(got - want)) < fp32_tol(q)
+
+
+def test_bench_config_sampled(lib):
+    """The measured workload (q=28, 14+14, d=20, c_total=6): sampled amplitudes vs the oracle,
+    unit norm, and the full cut state against the full uncut state on the GPU."""
+    ccut, pipeline = lib
+    q, d, n, c = 28, 20, 2, 6
+    g = brickwork(q, d, n, c, seed=0)
+    run = pipeline.CutRun(q, g, n)
+    psi = run.run("fp32")
+    sizes = [14, 14]
+    ocuts = cutting.find_cuts(q, g, sizes)
+    ostates = cutting.variant_states(q, g, sizes, ocuts)
+    rng = np.random.default_rng(1)
+    xs = sorted(set(int(x) for x in rng.integers(0, 2 ** q, size=400)) | {0, 2 ** q - 1})
+    want = cutting.amplitudes(xs, sizes, ocuts, ostates)
+    got = to_np(psi[torch.tensor(xs, device=psi.device)])
+    assert np.max(np.abs(got - want)) < fp32_tol(q)
+    ref = pipeline.uncut(q, g)
+    stats = ccut.norm_fidelity(psi, ref, q, stream=torch.cuda.current_stream())
+    print("q28 cut vs uncut:", stats, flush=True)
+    assert abs(stats["norm2"] - 1) < 1e-5
+    assert 1 - stats["fidelity"] < 1e-9
+    assert stats["max_abs"] < 2 * fp32_tol(q)
+
+
+def test_norm_fidelity_matches_numpy(lib):
+    ccut, pipeline = lib
+    q = 16
+    rng = np.random.default_rng(3)
+    a = (rng.normal(size=2 ** q) + 1j * rng.normal(size=2 ** q)).astype(np.complex64)
+    b = (a + 1e-3 * (rng.normal(size=2 ** q) + 1j * rng.normal(size=2 ** q))).astype(np.complex64)
+    ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    s = ccut.norm_fidelity(ta, tb, q)
+    a64, b64 = a.astype(np.complex128), b.astype(np.complex128)
+    assert abs(s["norm2"] - np.vdot(a64, a64).real) < 1e-9 * s["norm2"]
+    assert abs(s["ref_norm2"] - np.vdot(b64, b64).real) < 1e-9 * s["ref_norm2"]
+    assert abs(s["overlap"] - np.vdot(b64, a64)) < 1e-9 * abs(s["overlap"])
+    assert s["max_abs"] == pytest.approx(np.max(np.abs(a64 - b64)), rel=1e-12)
+    s0 = ccut.norm_fidelity(ta, None, q)
+    assert s0["ref_norm2"] == 0 and s0["max_abs"] == pytest.approx(np.max(np.abs(a64)), rel=1e-12)
+
+
+def test_deterministic_repeat(lib):
+    ccut, pipeline = lib
+    q = 16
+    g = brickwork(q, 10, 2, 4, seed=9)
+    run = pipeline.CutRun(q, g, 2)
+    a = run.run("fp32").clone()
+    b = run.run("fp32").clone()
+    assert torch.equal(torch.view_as_real(a), torch.view_as_real(b))
+
+
+def test_gpu_error_paths(lib):
+    ccut, pipeline = lib
+    q = 10
+    g = brickwork(q, 4, 2, 2, seed=0)
+    plan = ccut.cut_plan(q, g, 2)
+    info = plan.info()
+    small = torch.empty(info["arena_bytes"] - 8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ccut.CcutError) as e:
+        ccut.simulate_subcircuits(plan, small)
+    assert e.value.code == ccut.ENOSPC
+    arena = torch.empty(info["arena_bytes"], dtype=torch.uint8, device="cuda")
+    psi = torch.empty(2 ** q - 1, dtype=torch.complex64, device="cuda")
+    with pytest.raises(ccut.CcutError) as e:
+        ccut.merge_full_state(plan, arena, psi, "fp32")
+    assert e.value.code == ccut.ENOSPC
+    with pytest.raises(ccut.CcutError) as e:
+        ccut.merge_full_state(plan, arena, torch.empty(2 ** q, dtype=torch.complex64, device="cuda"), 7)
+    assert e.value.code == ccut.EINVAL
