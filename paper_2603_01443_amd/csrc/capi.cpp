@@ -7,9 +7,13 @@
 #include <memory>
 #include <mutex>
 
+#include "merge_mfma.h"
 #include "plan.h"
 
 namespace ccut {
+
+// Term count from which CCUT_PREC_AUTO merges on MFMA.
+constexpr int MFMA_MIN_TERMS = 8;
 
 namespace {
 thread_local char g_err[512] = "";
@@ -33,36 +37,54 @@ void release_device(DeviceTables& t) {
   if (t.device < 0) return;
   int cur = 0;
   if (hipGetDevice(&cur) == hipSuccess && cur != t.device) (void)hipSetDevice(t.device);
-  if (t.ops) (void)hipFree(t.ops);
-  if (t.passes) (void)hipFree(t.passes);
-  if (t.jobs) (void)hipFree(t.jobs);
-  if (t.weights) (void)hipFree(t.weights);
+  if (t.blob) (void)hipFree(t.blob);
   if (cur != t.device) (void)hipSetDevice(cur);
   t = DeviceTables();
 }
 
-template <class T>
-static int upload(const std::vector<T>& v, T** dst) {
-  *dst = nullptr;
-  if (v.empty()) return 0;
-  CCUT_HIP(hipMalloc((void**)dst, v.size() * sizeof(T)));
-  CCUT_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-  return 0;
-}
+namespace {
+uint64_t pad256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
+template <class T>
+void pack(std::vector<unsigned char>& img, const std::vector<T>& v, uint64_t& off) {
+  off = img.size();
+  const uint64_t bytes = v.size() * sizeof(T);
+  img.resize(pad256(off + bytes));
+  if (bytes) std::memcpy(img.data() + off, v.data(), bytes);
+}
+}  // namespace
+
+// Copies a plan's tables to the current device in one allocation.  With a
+// stream the copy is enqueued on it; without one the call is synchronous.
 int upload_tables(DeviceTables& t, const std::vector<KOp>& ops, const std::vector<PassDesc>& passes,
-                  const std::vector<SimJob>& jobs, const std::vector<float>& weights) {
+                  const std::vector<SimJob>& jobs, const std::vector<float>& weights, hipStream_t s,
+                  bool async) {
   int dev = 0;
   CCUT_HIP(hipGetDevice(&dev));
   if (t.device == dev) return 0;
   release_device(t);
-  int rc;
-  if ((rc = upload(ops, &t.ops)) || (rc = upload(passes, &t.passes)) || (rc = upload(jobs, &t.jobs)) ||
-      (rc = upload(weights, &t.weights))) {
-    t.device = dev;
-    release_device(t);
-    return rc;
+  std::vector<unsigned char> img;
+  uint64_t o_ops, o_pass, o_jobs, o_w;
+  pack(img, ops, o_ops);
+  pack(img, passes, o_pass);
+  pack(img, jobs, o_jobs);
+  pack(img, weights, o_w);
+  if (img.empty()) img.resize(256);
+  void* blob = nullptr;
+  CCUT_HIP(hipMalloc(&blob, img.size()));
+  t.host.swap(img);
+  hipError_t e = async ? hipMemcpyAsync(blob, t.host.data(), t.host.size(), hipMemcpyHostToDevice, s)
+                       : hipMemcpy(blob, t.host.data(), t.host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(blob);
+    return hip_fail(e, "table upload");
   }
+  unsigned char* b = static_cast<unsigned char*>(blob);
+  t.blob = blob;
+  t.ops = reinterpret_cast<KOp*>(b + o_ops);
+  t.passes = reinterpret_cast<PassDesc*>(b + o_pass);
+  t.jobs = reinterpret_cast<SimJob*>(b + o_jobs);
+  t.weights = reinterpret_cast<float*>(b + o_w);
   t.device = dev;
   return 0;
 }
@@ -145,7 +167,11 @@ extern "C" const char* ccut_version(void) { return "ccut 0.1 gfx950"; }
 extern "C" int ccut_plan_prepare(ccut_plan_t* plan) {
   clear_error();
   if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
-  return upload_tables(plan->dev, plan->kops, plan->pass_descs, plan->jobs, plan->weights);
+  return upload_tables(plan->dev, plan->kops, plan->pass_descs, plan->jobs, plan->weights, nullptr, false);
+}
+
+static int prepare_on(ccut_plan_t* plan, hipStream_t s) {
+  return upload_tables(plan->dev, plan->kops, plan->pass_descs, plan->jobs, plan->weights, s, true);
 }
 
 extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* stream) {
@@ -154,8 +180,8 @@ extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint6
   if (arena_bytes < plan->arena_bytes + plan->split_bytes)
     return fail(CCUT_ENOSPC, "arena has %llu bytes, plan needs %llu", (unsigned long long)arena_bytes,
                 (unsigned long long)(plan->arena_bytes + plan->split_bytes));
-  if (int rc = ccut_plan_prepare(plan)) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (int rc = prepare_on(plan, s)) return rc;
   for (const auto& L : plan->launches) {
     if (int rc = launch_sim(plan->dev.jobs + L.job_begin, L.n_jobs, L.total_wg, plan->dev.passes, plan->dev.ops,
                             static_cast<float*>(d_arena), plan->bmax, 256, s))
@@ -174,10 +200,8 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
                 (unsigned long long)plan->psi_bytes);
   if (precision < CCUT_PREC_AUTO || precision > CCUT_PREC_BF16)
     return fail(CCUT_EINVAL, "unknown precision %d", precision);
-  if (precision != CCUT_PREC_AUTO && precision != CCUT_PREC_FP32)
-    return fail(CCUT_EUNSUPPORTED, "precision %d not built yet", precision);
-  if (int rc = ccut_plan_prepare(plan)) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (int rc = prepare_on(plan, s)) return rc;
   char* arena = static_cast<char*>(d_arena);
   if (plan->n_seg == 1) {
     CCUT_HIP(hipMemcpyAsync(d_psi, arena + plan->segs[0].arena_off, plan->psi_bytes, hipMemcpyDeviceToDevice, s));
@@ -190,7 +214,38 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
     return static_cast<float*>(d_psi);
   };
   for (const MergeStage& st : plan->stages) {
-    if (int rc = launch_merge_f32(st, buf(st.a_src), buf(st.b_src), buf(st.out_dst), plan->dev.weights, s)) return rc;
+    int mode = precision;
+    if (mode == CCUT_PREC_AUTO) mode = st.K >= MFMA_MIN_TERMS ? CCUT_PREC_BF16X3 : CCUT_PREC_FP32;
+    if (mode == CCUT_PREC_FP32 || !merge_mfma_supported(st.qx, st.qy)) {
+      // shapes below one MFMA tile take the float32 kernel, which is at least as accurate
+      if (int rc = launch_merge_f32(st, buf(st.a_src), buf(st.b_src), buf(st.out_dst), plan->dev.weights, s))
+        return rc;
+      continue;
+    }
+    MergeMfmaArgs a;
+    a.A = reinterpret_cast<const float2*>(buf(st.a_src)) + st.a_off;
+    a.a_kstride = st.a_kstride;
+    a.a_bstride = st.a_bstride;
+    a.B = reinterpret_cast<const float2*>(buf(st.b_src)) + st.b_off;
+    a.b_kstride = st.b_kstride;
+    a.b_bstride = st.b_bstride;
+    a.w = reinterpret_cast<const float2*>(plan->dev.weights) + st.weight_off;
+    a.K = st.K;
+    a.qx = st.qx;
+    a.qy = st.qy;
+    a.S = mfma_steps(st.K);
+    a.batch = st.batch;
+    a.r_batch = st.a_bstride ? st.batch : 1;
+    a.l_plane_stride = mfma_l_plane(st.qy, a.S);
+    a.r_plane_stride = mfma_r_plane(st.qx, a.S);
+    uint4* ws = reinterpret_cast<uint4*>(arena + plan->split_off);
+    a.Lhi = ws;
+    a.Llo = a.Lhi + (uint64_t)a.batch * a.l_plane_stride;
+    a.Rhi = a.Llo + (uint64_t)a.batch * a.l_plane_stride;
+    a.Rlo = a.Rhi + (uint64_t)a.r_batch * a.r_plane_stride;
+    a.out = buf(st.out_dst) + 2 * st.out_off;
+    a.out_bstride = st.out_bstride;
+    if (int rc = launch_merge_mfma(a, mode, s)) return rc;
   }
   return CCUT_OK;
 }
@@ -218,7 +273,9 @@ extern "C" int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t 
     fresh->q = q;
     fresh->gates.assign(gates, gates + n_gates);
     if (int rc = compile_uncut(q, gates, n_gates, *fresh)) return rc;
-    if (int rc = upload_tables(fresh->dev, fresh->kops, fresh->descs, fresh->jobs, std::vector<float>())) return rc;
+    if (int rc = upload_tables(fresh->dev, fresh->kops, fresh->descs, fresh->jobs, std::vector<float>(), nullptr,
+                               false))
+      return rc;
     if (g_uncut.size() >= UNCUT_CACHE) {
       auto oldest = g_uncut.begin();
       for (auto i = g_uncut.begin(); i != g_uncut.end(); ++i)

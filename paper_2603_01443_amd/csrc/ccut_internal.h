@@ -124,12 +124,15 @@ struct MergeStage {
 };
 
 // --------------------------------------------------------- device launches
+// Device copies of a plan's tables, packed into one allocation.
 struct DeviceTables {
   int device = -1;
+  void* blob = nullptr;
   KOp* ops = nullptr;
   PassDesc* passes = nullptr;
   SimJob* jobs = nullptr;
   float* weights = nullptr;    // complex64 merge weights
+  std::vector<unsigned char> host;  // staging image (kept alive while copies may be in flight)
 };
 
 int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, const PassDesc* d_passes,

@@ -2,12 +2,13 @@
 //
 // One stage computes, for every batch entry beta,
 //   out[beta][y * NX + x] = sum_k w_k A(beta, k)[x] B(beta, k)[y],
-// i.e. the sum of weighted Kronecker products psi_B^(k) (x) psi_A^(k) with the
-// A factor on the low qubits.  Each thread owns one column x and RB rows: its
-// A values stream through registers once per k while the B values of the
-// workgroup's rows are uniform across the wavefront (scalar loads when a
-// whole workgroup shares its rows).  Every output amplitude is written once,
-// with consecutive lanes on consecutive addresses.
+// the sum of weighted Kronecker products psi_B^(k) (x) psi_A^(k) with the A
+// factor on the low qubits.  Each thread owns one column x and RB rows.  The
+// workgroup stages the B values of its rows for a chunk of KC terms in LDS
+// (read back as wavefront-wide broadcasts) and each thread keeps the KC
+// weighted A values of its column in registers, so the inner loop is pure
+// FMA.  Every output amplitude is written once, consecutive lanes on
+// consecutive addresses.  Columns narrower than 64 use a plain loop.
 #include "ccut_internal.h"
 
 namespace ccut {
@@ -15,6 +16,8 @@ namespace ccut {
 namespace {
 
 constexpr int MT = 256;
+constexpr int RB = 16;
+constexpr int KC = 16;
 
 struct MergeArgs {
   const float2* A;
@@ -25,56 +28,79 @@ struct MergeArgs {
   int K, qx, qy;
 };
 
-template <int RB>
-__global__ __launch_bounds__(MT) void k_merge_f32(MergeArgs a) {
+__device__ __forceinline__ void cfma(float2& acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x));
+  acc.y = fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y));
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// NX >= 64: TX = min(NX, 256) columns, GY = 256 / TX row groups of RB rows.
+__global__ __launch_bounds__(MT) void k_merge_f32_tiled(MergeArgs a) {
+  __shared__ float2 Bs[KC * (MT / 64) * RB];
   const int NX = 1 << a.qx, NY = 1 << a.qy;
   const int TX = NX < MT ? NX : MT;
   const int GY = MT / TX;
+  const int TY = GY * RB;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int x = blockIdx.x * TX + tx;
-  const int y0 = (blockIdx.y * GY + ty) * RB;
+  const int x = blockIdx.y * TX + tx;
+  const int y0 = blockIdx.x * TY;
   const int beta = blockIdx.z;
-  if (y0 >= NY) return;
   const float2* A = a.A + beta * a.a_bstride + x;
   const float2* B = a.B + beta * a.b_bstride + y0;
   float2 acc[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) acc[r] = make_float2(0.f, 0.f);
-  const int nr = (NY - y0) < RB ? (NY - y0) : RB;
-  for (int k = 0; k < a.K; ++k) {
-    const float2 wk = a.w[k];
-    const float2 av = A[(uint64_t)k * a.a_kstride];
-    const float2 ak = make_float2(wk.x * av.x - wk.y * av.y, wk.x * av.y + wk.y * av.x);
-    const float2* Bk = B + (uint64_t)k * a.b_kstride;
-    if (nr == RB) {
+  for (int k0 = 0; k0 < a.K; k0 += KC) {
+    const int kn = (a.K - k0) < KC ? (a.K - k0) : KC;
+    __syncthreads();
+    for (int i = threadIdx.x; i < KC * TY; i += MT) {
+      const int kk = i / TY, row = i % TY;
+      float2 v = make_float2(0.f, 0.f);
+      if (kk < kn && y0 + row < NY) v = B[(uint64_t)(k0 + kk) * a.b_kstride + row];
+      Bs[i] = v;
+    }
+    __syncthreads();
+    float2 av[KC];
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const float2 bv = Bk[r];
-        acc[r].x = fmaf(ak.x, bv.x, fmaf(-ak.y, bv.y, acc[r].x));
-        acc[r].y = fmaf(ak.x, bv.y, fmaf(ak.y, bv.x, acc[r].y));
-      }
-    } else {
-      for (int r = 0; r < nr; ++r) {
-        const float2 bv = Bk[r];
-        acc[r].x = fmaf(ak.x, bv.x, fmaf(-ak.y, bv.y, acc[r].x));
-        acc[r].y = fmaf(ak.x, bv.y, fmaf(ak.y, bv.x, acc[r].y));
-      }
+    for (int kk = 0; kk < KC; ++kk)
+      av[kk] = kk < kn ? cmul(a.w[k0 + kk], A[(uint64_t)(k0 + kk) * a.a_kstride]) : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const float2* bk = Bs + kk * TY + ty * RB;
+#pragma unroll
+      for (int r = 0; r < RB; ++r) cfma(acc[r], av[kk], bk[r]);
     }
   }
-  float2* o = a.out + beta * a.out_bstride + (uint64_t)y0 * NX + x;
-  if (nr == RB) {
+  const int yb = y0 + ty * RB;
+  float2* o = a.out + beta * a.out_bstride + (uint64_t)yb * NX + x;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) o[(uint64_t)r * NX] = acc[r];
-  } else {
-    for (int r = 0; r < nr; ++r) o[(uint64_t)r * NX] = acc[r];
+  for (int r = 0; r < RB; ++r)
+    if (yb + r < NY) o[(uint64_t)r * NX] = acc[r];
+}
+
+// NX < 64: one thread per (x, row group), plain loop over terms.
+__global__ __launch_bounds__(MT) void k_merge_f32_small(MergeArgs a) {
+  const int NX = 1 << a.qx, NY = 1 << a.qy;
+  const uint64_t id = (uint64_t)blockIdx.x * MT + threadIdx.x;
+  const uint64_t total = (uint64_t)NX * NY;
+  const int beta = blockIdx.z;
+  if (id >= total) return;
+  const uint64_t x = id % NX, y = id / NX;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int k = 0; k < a.K; ++k) {
+    const float2 av = cmul(a.w[k], a.A[beta * a.a_bstride + (uint64_t)k * a.a_kstride + x]);
+    cfma(acc, av, a.B[beta * a.b_bstride + (uint64_t)k * a.b_kstride + y]);
   }
+  a.out[beta * a.out_bstride + y * NX + x] = acc;
 }
 
 }  // namespace
 
 int launch_merge_f32(const MergeStage& st, const float* A, const float* B, float* out, const float* d_weights,
                      hipStream_t s) {
-  constexpr int RB = 16;
   MergeArgs a;
   a.A = reinterpret_cast<const float2*>(A) + st.a_off;
   a.B = reinterpret_cast<const float2*>(B) + st.b_off;
@@ -88,13 +114,19 @@ int launch_merge_f32(const MergeStage& st, const float* A, const float* B, float
   a.K = st.K;
   a.qx = st.qx;
   a.qy = st.qy;
-  const int NX = 1 << st.qx, NY = 1 << st.qy;
-  const int TX = NX < MT ? NX : MT;
-  const int GY = MT / TX;
-  const int rows_per_wg = GY * RB;
-  dim3 grid((NX + TX - 1) / TX, (NY + rows_per_wg - 1) / rows_per_wg, st.batch);
-  if (grid.y > 65535u || grid.z > 65535u) return fail(CCUT_EUNSUPPORTED, "merge grid too large");
-  hipLaunchKernelGGL(k_merge_f32<RB>, grid, dim3(MT), 0, s, a);
+  if (st.batch > 65535) return fail(CCUT_EUNSUPPORTED, "merge batch too large");
+  const uint64_t NX = (uint64_t)1 << st.qx, NY = (uint64_t)1 << st.qy;
+  if (NX >= 64) {
+    const uint64_t TX = NX < MT ? NX : MT;
+    const uint64_t TY = (MT / TX) * RB;
+    dim3 grid((unsigned)((NY + TY - 1) / TY), (unsigned)(NX / TX), st.batch);
+    if (grid.y > 65535u) return fail(CCUT_EUNSUPPORTED, "merge grid too large");
+    hipLaunchKernelGGL(k_merge_f32_tiled, grid, dim3(MT), 0, s, a);
+  } else {
+    const uint64_t blocks = (NX * NY + MT - 1) / MT;
+    if (blocks > 0x7fffffffu) return fail(CCUT_EUNSUPPORTED, "merge grid too large");
+    hipLaunchKernelGGL(k_merge_f32_small, dim3((unsigned)blocks, 1, st.batch), dim3(MT), 0, s, a);
+  }
   CCUT_HIP(hipGetLastError());
   return 0;
 }

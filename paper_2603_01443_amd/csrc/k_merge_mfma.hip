@@ -1,0 +1,267 @@
+// Merging (Algorithm 3 of the paper) as a split-precision GEMM on gfx950 MFMA.
+//
+// One merge stage  Psi[y][x] = sum_k w_k A_k[x] B_k[y]  (complex) is the real GEMM
+//   C (M x 2N) = L (M x 2K) . R (2K x 2N),   M = 2^qy rows, N = 2^qx columns,
+// with L[y][2k] = Re B_k[y], L[y][2k+1] = Im B_k[y] and, for A'_k = w_k A_k,
+//   R[2k][2x] =  Re A'_k[x]   R[2k][2x+1]   = Im A'_k[x]
+//   R[2k+1][2x] = -Im A'_k[x] R[2k+1][2x+1] = Re A'_k[x],
+// so row y of C is exactly the interleaved complex64 row of Psi (no permute).
+//
+// Float32 accuracy from 16-bit MFMA inputs: every factor value v is split into
+// hi = round16(v) and lo = round16(v - hi), and C = Lhi.Rhi + Lhi.Rlo + Llo.Rhi
+// with float32 accumulation (the lo.lo term, ~2^-16 relative for bfloat16, is
+// dropped).  For float16 both factors are scaled by 2^14 first so that lo parts
+// stay normal, and the result is scaled back by 2^-28 (exact).
+//
+// Layout: L and R are stored in MFMA fragment order, so that each wavefront's
+// operand load for one 32x32x16 step is one contiguous 1 KiB:
+//   Lf[(rb * S + s) * 64 + lane][e] = L[32 rb + lane % 32][16 s + 8 (lane / 32) + e]
+//   Rf[(cb * S + s) * 64 + lane][e] = R[16 s + 8 (lane / 32) + e][32 cb + lane % 32]
+// with S = ceil(2K / 16) steps (the inner dimension is zero-padded).
+//
+// Tiles: a workgroup (4 wavefronts, 2 x 2) owns 128 rows x 256 real columns;
+// each wavefront 64 x 128 = 2 x 4 blocks of 32 x 32.  Consecutive workgroups
+// land on consecutive XCDs; each XCD is given one band of columns so that the
+// R fragments of its band stay in its L2 while rows stream through.
+#include "ccut_internal.h"
+#include "merge_mfma.h"
+
+namespace ccut {
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <int MODE>
+__device__ __forceinline__ void split_value(float v, uint16_t& hi, uint16_t& lo) {
+  if (MODE == MERGE_FP16X3) {
+    const float s = v * 16384.0f;  // 2^14
+    const _Float16 h = (_Float16)s;
+    const _Float16 l = (_Float16)(s - (float)h);
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = __builtin_bit_cast(uint16_t, l);
+  } else {
+    hi = bf16_rne(v);
+    lo = bf16_rne(v - bf16_to_f(hi));
+  }
+}
+
+// ------------------------------------------------------------ split kernels
+// R fragments: one thread per (cb, s, lane) for one batch entry.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_split_R(const float2* __restrict__ A, uint64_t a_kstride,
+                                                 uint64_t a_bstride, const float2* __restrict__ w, int K, int qx,
+                                                 int S, uint4* __restrict__ hi, uint4* __restrict__ lo,
+                                                 uint64_t plane_stride) {
+  const int beta = blockIdx.y;
+  const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t ncb = (uint64_t)1 << (qx + 1 - 5);  // 2N / 32 column blocks
+  if (t >= ncb * S * 64) return;
+  const int lane = (int)(t & 63);
+  const uint64_t cs = t >> 6;
+  const int s = (int)(cs % S);
+  const uint64_t cb = cs / S;
+  const uint64_t c = cb * 32 + (lane & 31);
+  const uint64_t x = c >> 1;
+  const int part = (int)(c & 1);
+  const float2* Ab = A + beta * a_bstride + x;
+  uint16_t h[8], l[8];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int k = 8 * s + 4 * (lane >> 5) + p;  // kappa = 2k + comp
+    float2 av = make_float2(0.f, 0.f);
+    if (k < K) {
+      const float2 a = Ab[(uint64_t)k * a_kstride];
+      const float2 wk = w[k];
+      av = make_float2(wk.x * a.x - wk.y * a.y, wk.x * a.y + wk.y * a.x);
+    }
+    const float r0 = part == 0 ? av.x : av.y;   // comp 0
+    const float r1 = part == 0 ? -av.y : av.x;  // comp 1
+    split_value<MODE>(r0, h[2 * p], l[2 * p]);
+    split_value<MODE>(r1, h[2 * p + 1], l[2 * p + 1]);
+  }
+  uint4 H, Lo;
+  H.x = h[0] | ((uint32_t)h[1] << 16); H.y = h[2] | ((uint32_t)h[3] << 16);
+  H.z = h[4] | ((uint32_t)h[5] << 16); H.w = h[6] | ((uint32_t)h[7] << 16);
+  Lo.x = l[0] | ((uint32_t)l[1] << 16); Lo.y = l[2] | ((uint32_t)l[3] << 16);
+  Lo.z = l[4] | ((uint32_t)l[5] << 16); Lo.w = l[6] | ((uint32_t)l[7] << 16);
+  hi[beta * plane_stride + t] = H;
+  lo[beta * plane_stride + t] = Lo;
+}
+
+// L fragments: one thread per (rb, s, lane) for one batch entry.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_split_L(const float2* __restrict__ B, uint64_t b_kstride,
+                                                 uint64_t b_bstride, int K, int qy, int S,
+                                                 uint4* __restrict__ hi, uint4* __restrict__ lo,
+                                                 uint64_t plane_stride) {
+  const int beta = blockIdx.y;
+  const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t nrb = (uint64_t)1 << (qy - 5);
+  if (t >= nrb * S * 64) return;
+  const int lane = (int)(t & 63);
+  const uint64_t rs = t >> 6;
+  const int s = (int)(rs % S);
+  const uint64_t rb = rs / S;
+  const uint64_t y = rb * 32 + (lane & 31);
+  const float2* Bb = B + beta * b_bstride + y;
+  uint16_t h[8], l[8];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int k = 8 * s + 4 * (lane >> 5) + p;
+    const float2 b = k < K ? Bb[(uint64_t)k * b_kstride] : make_float2(0.f, 0.f);
+    split_value<MODE>(b.x, h[2 * p], l[2 * p]);
+    split_value<MODE>(b.y, h[2 * p + 1], l[2 * p + 1]);
+  }
+  uint4 H, Lo;
+  H.x = h[0] | ((uint32_t)h[1] << 16); H.y = h[2] | ((uint32_t)h[3] << 16);
+  H.z = h[4] | ((uint32_t)h[5] << 16); H.w = h[6] | ((uint32_t)h[7] << 16);
+  Lo.x = l[0] | ((uint32_t)l[1] << 16); Lo.y = l[2] | ((uint32_t)l[3] << 16);
+  Lo.z = l[4] | ((uint32_t)l[5] << 16); Lo.w = l[6] | ((uint32_t)l[7] << 16);
+  hi[beta * plane_stride + t] = H;
+  lo[beta * plane_stride + t] = Lo;
+}
+
+// ------------------------------------------------------------- GEMM kernel
+template <int MODE>
+__device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
+  if (MODE == MERGE_FP16X3) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                 0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                  c, 0, 0, 0);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lhi, const uint4* __restrict__ Llo,
+                                                    const uint4* __restrict__ Rhi, const uint4* __restrict__ Rlo,
+                                                    uint64_t l_bstride, uint64_t r_bstride, float* __restrict__ out,
+                                                    uint64_t out_bstride, int qx, int qy, int S, int col_tiles,
+                                                    int row_tiles) {
+  const int beta = blockIdx.y;
+  // XCD-aware tile order: workgroup b runs on XCD b % 8; give each XCD a band of columns.
+  const int b = blockIdx.x;
+  int trow, tcol;
+  if ((col_tiles & 7) == 0) {
+    const int band = col_tiles >> 3;
+    const int xcd = b & 7, i = b >> 3;
+    trow = i / band;
+    tcol = xcd * band + i % band;
+  } else {
+    trow = b / col_tiles;
+    tcol = b % col_tiles;
+  }
+  if (trow >= row_tiles) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rb0 = trow * 4 + (wave >> 1) * 2;  // 32-row blocks of this wave
+  const int cb0 = tcol * 8 + (wave & 1) * 4;   // 32-column blocks of this wave
+  const uint4* lh = Lhi + beta * l_bstride + ((uint64_t)rb0 * S) * 64 + lane;
+  const uint4* ll = Llo + beta * l_bstride + ((uint64_t)rb0 * S) * 64 + lane;
+  const uint4* rh = Rhi + beta * r_bstride + ((uint64_t)cb0 * S) * 64 + lane;
+  const uint4* rl = Rlo + beta * r_bstride + ((uint64_t)cb0 * S) * 64 + lane;
+  const uint64_t lstep = (uint64_t)S * 64;  // next 32-row (or column) block
+
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.f;
+
+  for (int s = 0; s < S; ++s) {
+    uint4 a_hi[2], a_lo[2], b_hi[4], b_lo[4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      a_hi[r] = lh[r * lstep + s * 64];
+      if (MODE != MERGE_BF16) a_lo[r] = ll[r * lstep + s * 64];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      b_hi[c] = rh[c * lstep + s * 64];
+      if (MODE != MERGE_BF16) b_lo[c] = rl[c * lstep + s * 64];
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (MODE != MERGE_BF16) {
+          acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
+          acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
+        }
+        acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
+      }
+  }
+
+  const float scale = MODE == MERGE_FP16X3 ? (1.0f / 268435456.0f) : 1.0f;  // 2^-28
+  const uint64_t ncols = (uint64_t)2 << qx;
+  float* ob = out + beta * out_bstride;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint64_t col = (uint64_t)(cb0 + c) * 32 + (lane & 31);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const uint64_t row = (uint64_t)(rb0 + r) * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+        __builtin_nontemporal_store(acc[r][c][v] * scale, ob + row * ncols + col);
+      }
+    }
+  (void)qy;
+}
+
+template <int MODE>
+int launch_mode(const MergeMfmaArgs& a, hipStream_t s) {
+  const int S = a.S;
+  // split R (the A side, weights folded in): per batch entry unless shared
+  {
+    const uint64_t n = ((uint64_t)1 << (a.qx + 1 - 5)) * S * 64;
+    dim3 grid((unsigned)((n + 255) / 256), a.r_batch);
+    hipLaunchKernelGGL(k_split_R<MODE>, grid, dim3(256), 0, s, a.A, a.a_kstride, a.a_bstride, a.w, a.K, a.qx, S,
+                       a.Rhi, a.Rlo, a.r_plane_stride);
+    CCUT_HIP(hipGetLastError());
+  }
+  {
+    const uint64_t n = ((uint64_t)1 << (a.qy - 5)) * S * 64;
+    dim3 grid((unsigned)((n + 255) / 256), a.batch);
+    hipLaunchKernelGGL(k_split_L<MODE>, grid, dim3(256), 0, s, a.B, a.b_kstride, a.b_bstride, a.K, a.qy, S, a.Lhi,
+                       a.Llo, a.l_plane_stride);
+    CCUT_HIP(hipGetLastError());
+  }
+  const int col_tiles = 1 << (a.qx + 1 - 8);  // 256 real columns per tile
+  const int row_tiles = 1 << (a.qy - 7);      // 128 rows per tile
+  dim3 grid((unsigned)(col_tiles * row_tiles), a.batch);
+  const uint64_t r_bstride = a.r_batch > 1 ? a.r_plane_stride : 0;
+  hipLaunchKernelGGL(k_merge_gemm<MODE>, grid, dim3(256), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo, a.l_plane_stride,
+                     r_bstride, a.out, a.out_bstride * 2, a.qx, a.qy, S, col_tiles, row_tiles);
+  CCUT_HIP(hipGetLastError());
+  return 0;
+}
+
+}  // namespace
+
+bool merge_mfma_supported(int qx, int qy) { return qx >= 7 && qy >= 7 && qx + 1 - 8 + qy - 7 <= 31; }
+
+int launch_merge_mfma(const MergeMfmaArgs& a, int mode, hipStream_t s) {
+  if (!merge_mfma_supported(a.qx, a.qy)) return fail(CCUT_EUNSUPPORTED, "MFMA merge needs qx, qy >= 7");
+  if (a.batch > 65535 || a.r_batch > 65535) return fail(CCUT_EUNSUPPORTED, "merge batch too large");
+  switch (mode) {
+    case MERGE_BF16X3: return launch_mode<MERGE_BF16X3>(a, s);
+    case MERGE_FP16X3: return launch_mode<MERGE_FP16X3>(a, s);
+    case MERGE_BF16: return launch_mode<MERGE_BF16>(a, s);
+    default: return fail(CCUT_EINVAL, "bad MFMA merge mode %d", mode);
+  }
+}
+
+}  // namespace ccut

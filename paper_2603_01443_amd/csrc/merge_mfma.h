@@ -1,0 +1,32 @@
+// Split-precision MFMA merge: launch interface.
+#pragma once
+
+#include "ccut_internal.h"
+
+namespace ccut {
+
+enum MergeMfmaMode : int { MERGE_BF16X3 = 1, MERGE_FP16X3 = 2, MERGE_BF16 = 3 };
+
+struct MergeMfmaArgs {
+  const float2* A;          // low-qubit factor (K terms of 2^qx), weights applied
+  uint64_t a_kstride, a_bstride;
+  const float2* B;          // high-qubit factor (K terms of 2^qy)
+  uint64_t b_kstride, b_bstride;
+  const float2* w;          // K complex weights
+  int K, qx, qy, S;         // S = ceil(2K / 16) MFMA steps
+  int batch, r_batch;       // output batch; R planes per batch (1 when the A side is shared)
+  uint4 *Lhi, *Llo, *Rhi, *Rlo;
+  uint64_t l_plane_stride, r_plane_stride;  // uint4 elements per batch entry
+  float* out;
+  uint64_t out_bstride;     // complex64 elements
+};
+
+bool merge_mfma_supported(int qx, int qy);
+int launch_merge_mfma(const MergeMfmaArgs& a, int mode, hipStream_t s);
+
+// uint4 elements of one L (rows) / R (columns) plane for a stage
+inline uint64_t mfma_l_plane(int qy, int S) { return ((uint64_t)1 << qy) / 32 * S * 64; }
+inline uint64_t mfma_r_plane(int qx, int S) { return ((uint64_t)2 << qx) / 32 * S * 64; }
+inline int mfma_steps(int K) { return (2 * K + 15) / 16; }
+
+}  // namespace ccut

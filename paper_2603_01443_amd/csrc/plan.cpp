@@ -2,6 +2,7 @@
 // program per segment with an S / S^dag slot per adjacent cut, size the arena,
 // and lay out the merge stages of Algorithm 3.
 #include "plan.h"
+#include "merge_mfma.h"
 
 #include <algorithm>
 #include <cmath>
@@ -231,8 +232,16 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
   P->temp_off[0] = P->state_bytes;
   P->temp_off[1] = align256(P->temp_off[0] + ping);
   P->arena_bytes = align256(P->temp_off[1] + pong);
+  // Split-precision planes of the MFMA merge (reused stage after stage).
   P->split_off = P->arena_bytes;
   P->split_bytes = 0;
+  for (const MergeStage& st : P->stages) {
+    if (!merge_mfma_supported(st.qx, st.qy)) continue;
+    const int S = mfma_steps(st.K);
+    const uint64_t r_batch = st.a_bstride ? (uint64_t)st.batch : 1;
+    const uint64_t u4 = (uint64_t)st.batch * mfma_l_plane(st.qy, S) + r_batch * mfma_r_plane(st.qx, S);
+    P->split_bytes = std::max(P->split_bytes, align256(2 * 16 * u4));
+  }
 
   // Simulation launches: pass p of every segment that has one, all variants.
   size_t max_passes = 0;

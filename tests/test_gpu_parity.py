@@ -203,3 +203,80 @@ def test_gpu_error_paths(lib):
     with pytest.raises(ccut.CcutError) as e:
         ccut.merge_full_state(plan, arena, torch.empty(2 ** q, dtype=torch.complex64, device="cuda"), 7)
     assert e.value.code == ccut.EINVAL
+
+
+# ------------------------------------------------------------ split-precision MFMA merge
+# Splitting a float32 value into hi + lo halves keeps ~16 (bfloat16) or ~22 (float16)
+# significant bits; dropping lo.lo leaves a relative error per product of ~2^-16 for
+# bfloat16, so an amplitude carries ~1e-5 relative error and 1 - F ~ 1e-9.  The bar is
+# the 1 - F <= 1e-6 of the metric and max-abs <= 1e-3 * 2^{-q/2}.
+
+def split_tol(q):
+    return 1e-3 * 2 ** (-q / 2)
+
+
+@pytest.mark.parametrize("c", [2, 4, 6, 8])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+def test_q20_split_precision_merge(lib, c, prec):
+    ccut, pipeline = lib
+    q, d, n = 20, 20, 2
+    g = brickwork(q, d, n, c, seed=c)
+    run = pipeline.CutRun(q, g, n)
+    psi = to_np(run.run(prec))
+    ref = cutting.cut_simulate(q, g, [10, 10])
+    err = metrics.max_abs_error(ref, psi)
+    inf = metrics.one_minus_fidelity(ref, psi)
+    print(f"q20 c{c} {prec}: max-abs {err:.3e} 1-F {inf:.3e}", flush=True)
+    assert inf <= 1e-6 and err <= split_tol(q)
+
+
+def test_unsplit_bf16_is_the_inaccurate_control(lib):
+    ccut, pipeline = lib
+    q, d, n, c = 20, 20, 2, 6
+    g = brickwork(q, d, n, c, seed=3)
+    run = pipeline.CutRun(q, g, n)
+    ref = cutting.cut_simulate(q, g, [10, 10])
+    inf_plain = metrics.one_minus_fidelity(ref, to_np(run.run("bf16")))
+    inf_split = metrics.one_minus_fidelity(ref, to_np(run.run("bf16x3")))
+    print(f"unsplit bf16 1-F {inf_plain:.3e}, split {inf_split:.3e}", flush=True)
+    assert inf_split * 100 < inf_plain
+
+
+@pytest.mark.parametrize("q,n,sizes,cuts", [
+    (14, 2, [7, 7], [6]),          # exactly one 128 x 256 MFMA tile
+    (22, 3, [7, 7, 8], [3, 3]),    # chain: stage 1 batched over the upper boundary
+    (17, 2, [7, 10], [3]),         # K = 8: inner dimension padded to one 16-step
+    (16, 2, [8, 8], [1]),          # K = 2, padded
+])
+def test_mfma_shapes(lib, q, n, sizes, cuts):
+    ccut, pipeline = lib
+    g = brickwork(q, 8, n, sum(cuts), seed=q, seg_sizes=sizes, cuts_per_boundary=cuts)
+    run = pipeline.CutRun(q, g, n, sizes)
+    ref = statevector.simulate(q, g)
+    for prec in ("bf16x3", "fp16x3"):
+        psi = to_np(run.run(prec))
+        err, inf = metrics.max_abs_error(ref, psi), metrics.one_minus_fidelity(ref, psi)
+        print(f"q{q} {sizes} {prec}: max-abs {err:.3e} 1-F {inf:.3e}", flush=True)
+        assert inf <= 1e-6 and err <= split_tol(q), prec
+
+
+def test_bench_config_split_precision(lib):
+    ccut, pipeline = lib
+    q, d, n, c = 28, 20, 2, 6
+    g = brickwork(q, d, n, c, seed=0)
+    run = pipeline.CutRun(q, g, n)
+    ref = pipeline.uncut(q, g)
+    sizes = [14, 14]
+    ocuts = cutting.find_cuts(q, g, sizes)
+    ostates = cutting.variant_states(q, g, sizes, ocuts)
+    rng = np.random.default_rng(2)
+    xs = sorted(set(int(x) for x in rng.integers(0, 2 ** q, size=400)))
+    want = cutting.amplitudes(xs, sizes, ocuts, ostates)
+    for prec in ("bf16x3", "fp16x3", "auto"):
+        psi = run.run(prec)
+        got = to_np(psi[torch.tensor(xs, device=psi.device)])
+        st = ccut.norm_fidelity(psi, ref, q)
+        print(f"q28 {prec}: sampled max-abs {np.max(np.abs(got - want)):.3e}, 1-F vs uncut "
+              f"{1 - st['fidelity']:.3e}", flush=True)
+        assert np.max(np.abs(got - want)) < split_tol(q)
+        assert 1 - st["fidelity"] <= 1e-6
