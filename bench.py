@@ -4,7 +4,8 @@
 Workload (the metric's configuration): random Ry.Rz + CZ brickwork, q = 28
 qubits, two equal segments of 14, depth d = 20, c_total = 6 cut CZs
 (K = 64 merge terms), seed 0.  One step is the whole cut pipeline of
-Eq. (runtime_decomp): cut_plan + device-table upload (T_pre), every
+Eq. (runtime_decomp): cut_plan on the host (T_pre; its tables are copied
+into the arena by the first device call), every
 subcircuit variant (T_sub) and the merge into the 2^28 complex64 state
 (T_merge).  value = 2^q amplitudes per step / seconds per step.
 
@@ -30,6 +31,10 @@ sys.path.insert(0, ROOT)
 
 Q, D, NSEG, CTOTAL, SEED = 28, 20, 2, 6, 0
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the merge GEMM from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by
+# a 1 GiB copy (2.0 x FETCH + 1.0 x WRITE); see profiles/.  Only valid for the kernel revision
+# it was measured on: set to None whenever that kernel changes.
+MEASURED_TRAFFIC = {"merge_gemm (bf16x3)": 2.232e9}
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
 
@@ -83,6 +88,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="auto")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and sampled check")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (for scaling PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of "
@@ -118,8 +125,7 @@ def main():
 
     def step(i=None):
         t0 = time.perf_counter()
-        plan = ccut.cut_plan(Q, garr, NSEG, sizes)
-        ccut.plan_prepare(plan)
+        plan = ccut.cut_plan(Q, garr, NSEG, sizes)   # tables reach the device with the first call
         t_pre.append(time.perf_counter() - t0)
         if i is not None:
             ev[i][0].record(stream)
@@ -137,12 +143,16 @@ def main():
     keep.clear()
     t_pre.clear()
     log(f"bench: warmup done, timing {args.steps} steps")
+    ccut.profile_reset()
+    ccut.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(i)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ccut.profile_enable(False)
+    kprof = ccut.profile_read()
     keep.clear()
     ms_step = 1e3 * wall / args.steps
     t_sub = [ev[i][0].elapsed_time(ev[i][1]) for i in range(args.steps)]
@@ -173,18 +183,38 @@ def main():
     merge_ms = float(np.mean(t_merge))
     merge_bytes = 8 * (1 << Q) + 8 * K * ((1 << sizes[0]) + (1 << sizes[1]))
     merge_flops = 8 * K * (1 << Q)
-    used = prec if prec != "auto" else ("fp32" if K < 64 else "fp32")
-    if used == "fp32" and K * 8 > FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9) * 8:
-        roof = {"bound": "alu", "achieved": merge_flops / (merge_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s"}
+    used = prec if prec != "auto" else ("bf16x3" if K >= 8 else "fp32")
+    kernels_ms = {k: v[1] / v[0] for k, v in kprof.items() if v[0] > 0}
+    kernel_launches = {k: v[0] // args.steps for k, v in kprof.items() if v[0] > 0}
+    if used == "fp32":
+        kname = "merge_f32"
+        k_ms = kernels_ms[kname]
+        if K * 8 > FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9) * 8:
+            roof = {"bound": "alu", "achieved": merge_flops / (k_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "hbm", "achieved": merge_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s"}
     else:
-        roof = {"bound": "hbm", "achieved": merge_bytes / (merge_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+        kname = "merge_gemm"
+        k_ms = kernels_ms[kname]
+        roof = {"bound": "hbm", "achieved": merge_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = f"merge ({used})"
+    roof["kernel"] = f"{kname} ({used})"
+    roof["traffic"] = MEASURED_TRAFFIC.get(roof["kernel"])
+    roof["avg_ms"] = k_ms
     roof["algorithmic_bytes"] = merge_bytes
     roof["algorithmic_flops"] = merge_flops
+    log(f"bench: kernels (avg ms per launch) {kernels_ms}")
+
+    if args.calibrate_copy:
+        src = torch.empty(1 << 27, dtype=torch.complex64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        src.zero_()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of 1073741824 bytes done")
 
     result = {
         "metric": "full-state amps/s merged; cut vs uncut wall-clock at q=28, 1-F<=1e-6",
@@ -201,6 +231,8 @@ def main():
         "cut_vs_uncut": {"speedup": t_orig / ms_step, "one_minus_F": one_minus_f,
                          "norm_drift": abs(stats["norm2"] - 1.0), "max_abs": stats["max_abs"]},
         "roofline": roof,
+        "kernels_ms": kernels_ms,
+        "kernel_launches_per_step": kernel_launches,
     }
 
     if not args.no_cpu:

@@ -218,6 +218,21 @@ int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, vo
  */
 int ccut_norm_fidelity(const void* d_psi, const void* d_ref, int32_t q, double out[5], void* stream);
 
+/*
+ * Kernel timing.  While enabled, every kernel this library launches is
+ * bracketed by HIP events recorded on the stream it runs on (a few
+ * microseconds of overhead per launch).  ccut_profile_read waits for the
+ * recorded events, folds them into per-family totals and returns, for kernel
+ * family `kernel` (0 <= kernel < CCUT_PROF_KERNELS), the number of launches
+ * and their summed device milliseconds since the last reset, plus the family
+ * name ("sim", "merge_f32", "split_R", "split_L", "merge_gemm", "reduce",
+ * "mlp"; a static string, pass NULL to skip).  Errors: CCUT_EINVAL, CCUT_EHIP.
+ */
+#define CCUT_PROF_KERNELS 7
+int ccut_profile_enable(int32_t on);
+int ccut_profile_read(int32_t kernel, int64_t* launches, double* total_ms, const char** name);
+int ccut_profile_reset(void);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* ccut_last_error(void);
 

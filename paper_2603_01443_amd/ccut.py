@@ -89,6 +89,13 @@ def _load():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.ccut_profile_enable.argtypes = [i32]
+    lib.ccut_profile_enable.restype = ctypes.c_int
+    lib.ccut_profile_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_char_p)]
+    lib.ccut_profile_read.restype = ctypes.c_int
+    lib.ccut_profile_reset.argtypes = []
+    lib.ccut_profile_reset.restype = ctypes.c_int
     lib.ccut_plan_free.argtypes = [vp]
     lib.ccut_plan_free.restype = None
     lib.ccut_last_error.restype = ctypes.c_char_p
@@ -236,6 +243,29 @@ def norm_fidelity(psi, ref, q: int, stream=None) -> dict:
     if ref is not None and n2p > 0 and n2r > 0:
         res["fidelity"] = (ore * ore + oim * oim) / (n2p * n2r)
     return res
+
+
+PROF_KERNELS = 7
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(_lib.ccut_profile_enable(1 if on else 0))
+
+
+def profile_reset() -> None:
+    _check(_lib.ccut_profile_reset())
+
+
+def profile_read() -> dict:
+    """{family: (launches, total_ms)} accumulated since the last reset."""
+    out = {}
+    for k in range(PROF_KERNELS):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        name = ctypes.c_char_p()
+        _check(_lib.ccut_profile_read(k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(name)))
+        out[name.value.decode()] = (n.value, ms.value)
+    return out
 
 
 def version() -> str:

@@ -52,29 +52,65 @@ void pack(std::vector<unsigned char>& img, const std::vector<T>& v, uint64_t& of
   img.resize(pad256(off + bytes));
   if (bytes) std::memcpy(img.data() + off, v.data(), bytes);
 }
+
+// Pinned staging ring: host images are copied into a slot, and the slot's
+// event (recorded after the device copy) gates its reuse.
+constexpr int RING_SLOTS = 32;
+constexpr uint64_t SLOT_BYTES = 256 << 10;
+struct StagingRing {
+  unsigned char* host = nullptr;
+  hipEvent_t ev[RING_SLOTS] = {};
+  bool used[RING_SLOTS] = {};
+  int next = 0;
+};
+std::mutex g_ring_mu;
+StagingRing g_ring[64];
 }  // namespace
 
-// Copies a plan's tables to the current device in one allocation.  With a
-// stream the copy is enqueued on it; without one the call is synchronous.
-int upload_tables(DeviceTables& t, const std::vector<KOp>& ops, const std::vector<PassDesc>& passes,
-                  const std::vector<SimJob>& jobs, const std::vector<float>& weights, hipStream_t s,
-                  bool async) {
+void pack_image(ccut_plan* P) {
+  P->image.clear();
+  pack(P->image, P->kops, P->img_ops);
+  pack(P->image, P->pass_descs, P->img_passes);
+  pack(P->image, P->jobs, P->img_jobs);
+  pack(P->image, P->weights, P->img_weights);
+  if (P->image.empty()) P->image.resize(256);
+}
+
+int staged_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s) {
+  if (bytes > SLOT_BYTES) {  // large images go directly (may wait for the stream)
+    CCUT_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    return 0;
+  }
+  int dev = 0;
+  CCUT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(CCUT_EUNSUPPORTED, "device id %d", dev);
+  std::lock_guard<std::mutex> lk(g_ring_mu);
+  StagingRing& R = g_ring[dev];
+  if (!R.host) {
+    CCUT_HIP(hipHostMalloc((void**)&R.host, SLOT_BYTES * RING_SLOTS, hipHostMallocDefault));
+    for (int i = 0; i < RING_SLOTS; ++i) CCUT_HIP(hipEventCreateWithFlags(&R.ev[i], hipEventDisableTiming));
+  }
+  const int slot = R.next;
+  R.next = (R.next + 1) % RING_SLOTS;
+  if (R.used[slot]) CCUT_HIP(hipEventSynchronize(R.ev[slot]));
+  unsigned char* h = R.host + (uint64_t)slot * SLOT_BYTES;
+  std::memcpy(h, src, bytes);
+  CCUT_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s));
+  CCUT_HIP(hipEventRecord(R.ev[slot], s));
+  R.used[slot] = true;
+  return 0;
+}
+
+// Copies a table image to a new device allocation (synchronous).
+int upload_tables(DeviceTables& t, const std::vector<unsigned char>& img, uint64_t o_ops, uint64_t o_pass,
+                  uint64_t o_jobs, uint64_t o_w) {
   int dev = 0;
   CCUT_HIP(hipGetDevice(&dev));
   if (t.device == dev) return 0;
   release_device(t);
-  std::vector<unsigned char> img;
-  uint64_t o_ops, o_pass, o_jobs, o_w;
-  pack(img, ops, o_ops);
-  pack(img, passes, o_pass);
-  pack(img, jobs, o_jobs);
-  pack(img, weights, o_w);
-  if (img.empty()) img.resize(256);
   void* blob = nullptr;
   CCUT_HIP(hipMalloc(&blob, img.size()));
-  t.host.swap(img);
-  hipError_t e = async ? hipMemcpyAsync(blob, t.host.data(), t.host.size(), hipMemcpyHostToDevice, s)
-                       : hipMemcpy(blob, t.host.data(), t.host.size(), hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(blob, img.data(), img.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(blob);
     return hip_fail(e, "table upload");
@@ -86,6 +122,29 @@ int upload_tables(DeviceTables& t, const std::vector<KOp>& ops, const std::vecto
   t.jobs = reinterpret_cast<SimJob*>(b + o_jobs);
   t.weights = reinterpret_cast<float*>(b + o_w);
   t.device = dev;
+  return 0;
+}
+
+// Device addresses of a plan's tables for a call on `arena`: the plan-owned
+// copy when prepared on this device, otherwise a fresh copy into the arena.
+int plan_tables(ccut_plan* P, char* arena, hipStream_t s, DeviceTables& out) {
+  int dev = 0;
+  CCUT_HIP(hipGetDevice(&dev));
+  if (P->dev.device == dev) {
+    out = DeviceTables();
+    out.ops = P->dev.ops;
+    out.passes = P->dev.passes;
+    out.jobs = P->dev.jobs;
+    out.weights = P->dev.weights;
+    return 0;
+  }
+  unsigned char* b = reinterpret_cast<unsigned char*>(arena + P->tables_off);
+  if (int rc = staged_copy(b, P->image.data(), P->image.size(), s)) return rc;
+  out = DeviceTables();
+  out.ops = reinterpret_cast<KOp*>(b + P->img_ops);
+  out.passes = reinterpret_cast<PassDesc*>(b + P->img_passes);
+  out.jobs = reinterpret_cast<SimJob*>(b + P->img_jobs);
+  out.weights = reinterpret_cast<float*>(b + P->img_weights);
   return 0;
 }
 
@@ -167,23 +226,20 @@ extern "C" const char* ccut_version(void) { return "ccut 0.1 gfx950"; }
 extern "C" int ccut_plan_prepare(ccut_plan_t* plan) {
   clear_error();
   if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
-  return upload_tables(plan->dev, plan->kops, plan->pass_descs, plan->jobs, plan->weights, nullptr, false);
-}
-
-static int prepare_on(ccut_plan_t* plan, hipStream_t s) {
-  return upload_tables(plan->dev, plan->kops, plan->pass_descs, plan->jobs, plan->weights, s, true);
+  return upload_tables(plan->dev, plan->image, plan->img_ops, plan->img_passes, plan->img_jobs, plan->img_weights);
 }
 
 extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* stream) {
   clear_error();
   if (!plan || !d_arena) return fail(CCUT_EINVAL, "NULL argument");
-  if (arena_bytes < plan->arena_bytes + plan->split_bytes)
+  if (arena_bytes < plan->total_arena)
     return fail(CCUT_ENOSPC, "arena has %llu bytes, plan needs %llu", (unsigned long long)arena_bytes,
-                (unsigned long long)(plan->arena_bytes + plan->split_bytes));
+                (unsigned long long)plan->total_arena);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (int rc = prepare_on(plan, s)) return rc;
+  DeviceTables T;
+  if (int rc = plan_tables(plan, static_cast<char*>(d_arena), s, T)) return rc;
   for (const auto& L : plan->launches) {
-    if (int rc = launch_sim(plan->dev.jobs + L.job_begin, L.n_jobs, L.total_wg, plan->dev.passes, plan->dev.ops,
+    if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, L.total_wg, T.passes, T.ops,
                             static_cast<float*>(d_arena), plan->bmax, 256, s))
       return rc;
   }
@@ -194,15 +250,16 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
                                      uint64_t psi_bytes, int32_t precision, void* stream) {
   clear_error();
   if (!plan || !d_arena || !d_psi) return fail(CCUT_EINVAL, "NULL argument");
-  if (arena_bytes < plan->arena_bytes + plan->split_bytes) return fail(CCUT_ENOSPC, "arena too small");
+  if (arena_bytes < plan->total_arena) return fail(CCUT_ENOSPC, "arena too small");
   if (psi_bytes < plan->psi_bytes)
     return fail(CCUT_ENOSPC, "psi has %llu bytes, needs %llu", (unsigned long long)psi_bytes,
                 (unsigned long long)plan->psi_bytes);
   if (precision < CCUT_PREC_AUTO || precision > CCUT_PREC_BF16)
     return fail(CCUT_EINVAL, "unknown precision %d", precision);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (int rc = prepare_on(plan, s)) return rc;
   char* arena = static_cast<char*>(d_arena);
+  DeviceTables T;
+  if (int rc = plan_tables(plan, arena, s, T)) return rc;
   if (plan->n_seg == 1) {
     CCUT_HIP(hipMemcpyAsync(d_psi, arena + plan->segs[0].arena_off, plan->psi_bytes, hipMemcpyDeviceToDevice, s));
     return CCUT_OK;
@@ -218,7 +275,7 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
     if (mode == CCUT_PREC_AUTO) mode = st.K >= MFMA_MIN_TERMS ? CCUT_PREC_BF16X3 : CCUT_PREC_FP32;
     if (mode == CCUT_PREC_FP32 || !merge_mfma_supported(st.qx, st.qy)) {
       // shapes below one MFMA tile take the float32 kernel, which is at least as accurate
-      if (int rc = launch_merge_f32(st, buf(st.a_src), buf(st.b_src), buf(st.out_dst), plan->dev.weights, s))
+      if (int rc = launch_merge_f32(st, buf(st.a_src), buf(st.b_src), buf(st.out_dst), T.weights, s))
         return rc;
       continue;
     }
@@ -229,7 +286,7 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
     a.B = reinterpret_cast<const float2*>(buf(st.b_src)) + st.b_off;
     a.b_kstride = st.b_kstride;
     a.b_bstride = st.b_bstride;
-    a.w = reinterpret_cast<const float2*>(plan->dev.weights) + st.weight_off;
+    a.w = reinterpret_cast<const float2*>(T.weights) + st.weight_off;
     a.K = st.K;
     a.qx = st.qx;
     a.qy = st.qy;
@@ -273,9 +330,13 @@ extern "C" int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t 
     fresh->q = q;
     fresh->gates.assign(gates, gates + n_gates);
     if (int rc = compile_uncut(q, gates, n_gates, *fresh)) return rc;
-    if (int rc = upload_tables(fresh->dev, fresh->kops, fresh->descs, fresh->jobs, std::vector<float>(), nullptr,
-                               false))
-      return rc;
+    std::vector<unsigned char> img;
+    uint64_t o_ops, o_pass, o_jobs, o_w;
+    pack(img, fresh->kops, o_ops);
+    pack(img, fresh->descs, o_pass);
+    pack(img, fresh->jobs, o_jobs);
+    o_w = img.size();
+    if (int rc = upload_tables(fresh->dev, img, o_ops, o_pass, o_jobs, o_w)) return rc;
     if (g_uncut.size() >= UNCUT_CACHE) {
       auto oldest = g_uncut.begin();
       for (auto i = g_uncut.begin(); i != g_uncut.end(); ++i)

@@ -132,7 +132,19 @@ struct DeviceTables {
   PassDesc* passes = nullptr;
   SimJob* jobs = nullptr;
   float* weights = nullptr;    // complex64 merge weights
-  std::vector<unsigned char> host;  // staging image (kept alive while copies may be in flight)
+};
+
+// ---------------------------------------------------------------- timing
+enum ProfKernel : int { PROF_SIM = 0, PROF_MERGE_F32, PROF_SPLIT_R, PROF_SPLIT_L, PROF_MERGE_GEMM, PROF_REDUCE,
+                        PROF_MLP, PROF_N };
+int prof_begin(int kernel, hipStream_t s);   // -1 when timing is off
+void prof_end(int token, hipStream_t s);
+
+struct ProfScope {
+  int tok;
+  hipStream_t s;
+  ProfScope(int kernel, hipStream_t st) : tok(prof_begin(kernel, st)), s(st) {}
+  ~ProfScope() { prof_end(tok, s); }
 };
 
 int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, const PassDesc* d_passes,

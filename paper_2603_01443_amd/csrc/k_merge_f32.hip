@@ -121,10 +121,12 @@ int launch_merge_f32(const MergeStage& st, const float* A, const float* B, float
     const uint64_t TY = (MT / TX) * RB;
     dim3 grid((unsigned)((NY + TY - 1) / TY), (unsigned)(NX / TX), st.batch);
     if (grid.y > 65535u) return fail(CCUT_EUNSUPPORTED, "merge grid too large");
+    ProfScope prof(PROF_MERGE_F32, s);
     hipLaunchKernelGGL(k_merge_f32_tiled, grid, dim3(MT), 0, s, a);
   } else {
     const uint64_t blocks = (NX * NY + MT - 1) / MT;
     if (blocks > 0x7fffffffu) return fail(CCUT_EUNSUPPORTED, "merge grid too large");
+    ProfScope prof(PROF_MERGE_F32, s);
     hipLaunchKernelGGL(k_merge_f32_small, dim3((unsigned)blocks, 1, st.batch), dim3(MT), 0, s, a);
   }
   CCUT_HIP(hipGetLastError());

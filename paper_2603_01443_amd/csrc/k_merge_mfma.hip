@@ -228,6 +228,7 @@ int launch_mode(const MergeMfmaArgs& a, hipStream_t s) {
   {
     const uint64_t n = ((uint64_t)1 << (a.qx + 1 - 5)) * S * 64;
     dim3 grid((unsigned)((n + 255) / 256), a.r_batch);
+    ProfScope prof(PROF_SPLIT_R, s);
     hipLaunchKernelGGL(k_split_R<MODE>, grid, dim3(256), 0, s, a.A, a.a_kstride, a.a_bstride, a.w, a.K, a.qx, S,
                        a.Rhi, a.Rlo, a.r_plane_stride);
     CCUT_HIP(hipGetLastError());
@@ -235,6 +236,7 @@ int launch_mode(const MergeMfmaArgs& a, hipStream_t s) {
   {
     const uint64_t n = ((uint64_t)1 << (a.qy - 5)) * S * 64;
     dim3 grid((unsigned)((n + 255) / 256), a.batch);
+    ProfScope prof(PROF_SPLIT_L, s);
     hipLaunchKernelGGL(k_split_L<MODE>, grid, dim3(256), 0, s, a.B, a.b_kstride, a.b_bstride, a.K, a.qy, S, a.Lhi,
                        a.Llo, a.l_plane_stride);
     CCUT_HIP(hipGetLastError());
@@ -243,6 +245,7 @@ int launch_mode(const MergeMfmaArgs& a, hipStream_t s) {
   const int row_tiles = 1 << (a.qy - 7);      // 128 rows per tile
   dim3 grid((unsigned)(col_tiles * row_tiles), a.batch);
   const uint64_t r_bstride = a.r_batch > 1 ? a.r_plane_stride : 0;
+  ProfScope prof(PROF_MERGE_GEMM, s);
   hipLaunchKernelGGL(k_merge_gemm<MODE>, grid, dim3(256), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo, a.l_plane_stride,
                      r_bstride, a.out, a.out_bstride * 2, a.qx, a.qy, S, col_tiles, row_tiles);
   CCUT_HIP(hipGetLastError());

@@ -66,6 +66,7 @@ __global__ __launch_bounds__(RT) void k_reduce_final(const double* __restrict__ 
 
 int launch_reduce(const float* psi, const float* ref, uint64_t n, double* d_partials, int n_blocks,
                   double* d_out, hipStream_t s) {
+  ProfScope prof(PROF_REDUCE, s);
   hipLaunchKernelGGL(k_reduce_partial, dim3(n_blocks), dim3(RT), 0, s, reinterpret_cast<const float2*>(psi),
                      reinterpret_cast<const float2*>(ref), n, d_partials);
   CCUT_HIP(hipGetLastError());

@@ -159,6 +159,7 @@ int launch_sim_t(const SimJob* d_jobs, int n_jobs, int total_wg, const PassDesc*
                                  (int)(2 * TAB * sizeof(uint64_t) + (sizeof(float2) << PASS_MAX_B))));
     attr_set = true;
   }
+  ProfScope prof(PROF_SIM, s);
   hipLaunchKernelGGL(k_sim<NT>, dim3(grid), dim3(NT), shmem, s, d_jobs, n_jobs, total_wg, d_passes, d_ops,
                      reinterpret_cast<float2*>(base));
   CCUT_HIP(hipGetLastError());

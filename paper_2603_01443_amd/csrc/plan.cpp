@@ -274,6 +274,10 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
     P->launches.push_back(L);
   }
 
+  pack_image(P);
+  P->tables_off = align256(P->split_off + P->split_bytes);
+  P->total_arena = align256(P->tables_off + P->image.size());
+
   *plan_out = guard.release();
   return CCUT_OK;
 }
@@ -298,7 +302,7 @@ extern "C" int ccut_plan_info(const ccut_plan_t* plan, ccut_plan_info_t* info) {
   for (size_t b = 0; b < plan->c_b.size(); ++b) info->c_boundary[b] = plan->c_b[b];
   info->n_terms = (int64_t)1 << info->c_total;
   info->state_bytes = plan->state_bytes;
-  info->arena_bytes = plan->arena_bytes + plan->split_bytes;
+  info->arena_bytes = plan->total_arena;
   info->psi_bytes = plan->psi_bytes;
   return CCUT_OK;
 }

@@ -30,7 +30,13 @@ struct ccut_plan {
   struct Launch { int job_begin, n_jobs, total_wg; };
   std::vector<Launch> launches;
 
-  ccut::DeviceTables dev;
+  // Packed table image (ops | passes | jobs | weights) and where it sits in the arena.
+  std::vector<unsigned char> image;
+  uint64_t img_ops = 0, img_passes = 0, img_jobs = 0, img_weights = 0;
+  uint64_t tables_off = 0;  // arena byte offset of the table region
+  uint64_t total_arena = 0; // bytes the caller's arena must hold
+
+  ccut::DeviceTables dev;   // plan-owned copy after ccut_plan_prepare (graph capture)
 };
 
 namespace ccut {
@@ -38,4 +44,8 @@ namespace ccut {
 int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<KOp>& kops);
 int gate_matrix(const ccut_gate_t& g, cd m[4]);
 void release_device(DeviceTables& t);
+// Packs the tables into one image with 256-byte aligned sections.
+void pack_image(ccut_plan* P);
+// Enqueues a copy of `bytes` host bytes to device memory `dst` through a pinned staging ring.
+int staged_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s);
 }  // namespace ccut
