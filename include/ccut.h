@@ -218,6 +218,118 @@ int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, vo
  */
 int ccut_norm_fidelity(const void* d_psi, const void* d_ref, int32_t q, double out[5], void* stream);
 
+/* ------------------------------------------------- launches, graphs, tuning */
+/*
+ * Launch configuration of a plan's subcircuit simulation (the batched
+ * subcircuit stage of Algorithm 2):
+ *   threads      workgroup size of the simulation kernel: 256, 512 or 1024
+ *   grid_cap     0: one workgroup per amplitude block; > 0: a persistent grid of
+ *                at most grid_cap workgroups looping over all blocks of all variants
+ *   per_variant  0: one launch covers every variant of every segment (per pass);
+ *                1: one launch per (segment, variant), the unbatched reference
+ *   mfma_min_terms  CCUT_PREC_AUTO merges on MFMA from this term count K
+ *                (-1: library default 8)
+ * Results do not depend on the configuration.  ccut_plan_get_launch returns
+ * (threads, grid_cap, per_variant, mfma_min_terms).  Host-only.
+ */
+int ccut_plan_set_launch(ccut_plan_t* plan, int32_t threads, int32_t grid_cap, int32_t per_variant,
+                         int32_t mfma_min_terms);
+int ccut_plan_get_launch(const ccut_plan_t* plan, int32_t out[4]);
+
+/*
+ * Autotuner: times the simulation kernel over workgroup sizes x persistent
+ * grid sizes, and the merge with the float32 kernel against the split-bfloat16
+ * MFMA kernel (median of `reps` runs, HIP events on `stream`), applies the
+ * fastest to the plan and records it in a process-wide cache keyed by
+ * (architecture, plan shape); later plans of the same shape start from it.
+ * Overwrites the arena and d_psi.  *best_ms (nullable) receives the tuned
+ * simulation + merge time.  ccut_autotune_save / _load write and read the
+ * cache as text (one "key threads grid_cap mfma_min_terms" line per entry).
+ * Errors: CCUT_EINVAL, CCUT_ENOSPC, CCUT_EHIP.
+ */
+int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* d_psi, uint64_t psi_bytes,
+                  int32_t reps, void* stream, double* best_ms);
+int ccut_autotune_save(const char* path);
+int ccut_autotune_load(const char* path);
+
+/*
+ * HIP graph of a plan's whole device pipeline (subcircuit simulation, then
+ * merge at `precision`) captured on `stream` (must not be the default
+ * stream).  The plan is prepared first, so replays copy nothing from the
+ * host; the arena and d_psi addresses are baked into the graph and must stay
+ * valid.  ccut_graph_launch replays it on any stream.  The graph does not own
+ * the plan: keep the plan alive while the graph is used.
+ * Errors: CCUT_EINVAL, CCUT_ENOSPC, CCUT_EHIP.
+ */
+typedef struct ccut_graph ccut_graph_t;
+int ccut_graph_create(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* d_psi, uint64_t psi_bytes,
+                      int32_t precision, void* stream, ccut_graph_t** out);
+int ccut_graph_launch(ccut_graph_t* graph, void* stream);
+void ccut_graph_free(ccut_graph_t* graph);
+
+/* ------------------------------------------------------------ cost model */
+/*
+ * Closed-form subcircuit-stage threshold of Sec. IV for equal partitioning
+ * into n segments (k = 2): c_total < *bound, with *bound = q/2 for n = 2
+ * (Eq. threshold_n2) and q (n-1)^2/(2n) + (n-1) log2(n/(n-2))/2 for n >= 3
+ * (Eq. threshold_nge3, Table II).  Host-only.  Errors: CCUT_EINVAL.
+ */
+int ccut_threshold_ctotal(int32_t q, int32_t n, double* bound);
+
+/*
+ * log2 margin of Eq. (speedup_depth_free), N_sub / n < 2^{q (1 - 1/n)}, with
+ * N_sub = sum_i 2^{c_i} counted exactly from n-1 cut counts per boundary:
+ * q (1 - 1/n) - log2(N_sub / n).  Positive: the subcircuit stage beats the
+ * uncut simulation.  Host-only.  Errors: CCUT_EINVAL.
+ */
+int ccut_speedup_margin(int32_t q, int32_t n, const int32_t* cuts_per_boundary, double* margin);
+
+/*
+ * The learned cost model (not part of the paper): a 4-64-64-3 tanh MLP,
+ * CCUT_MLP_PARAMS float32 parameters laid out W1[4][64], b1[64], W2[64][64],
+ * b2[64], W3[64][3], b3[3], mapping features of (q, d, n, c_total) to
+ * ln T_pre, ln T_sub, ln T_merge in seconds (an uncut run is the row n = 1,
+ * c_total = 0 with T_orig in the T_sub slot).
+ *
+ * ccut_cost_features: the 4 input features (host):
+ *   ((q - 24) / 8, log2 d - log2 20, n - 3, (c_total - 4) / 4).
+ * ccut_mlp_predict: d_y[rows][3] = net(d_x[rows][4]) on the device.
+ * ccut_mlp_grad: mean-squared-error loss against d_t[rows][3] (written to
+ *   host *loss) and its gradient d_grad[CCUT_MLP_PARAMS]; synchronous.
+ * ccut_mlp_train: `epochs` full-batch Adam steps (lr, betas 0.9 / 0.999,
+ *   eps 1e-8) updating d_params in place; the per-epoch losses go to host
+ *   `losses` (epochs floats, or NULL).  Work buffer: ccut_mlp_work_bytes.
+ *   Synchronous.  A non-default stream lets training replay captured HIP
+ *   graphs of 50 epochs.
+ * All d_ pointers are device memory owned by the caller.
+ * Errors: CCUT_EINVAL, CCUT_ENOSPC (work buffer), CCUT_EHIP.
+ */
+#define CCUT_MLP_PARAMS 4675
+int ccut_cost_features(int32_t q, int32_t d, int32_t n, int32_t c_total, float out[4]);
+int ccut_mlp_work_bytes(int64_t rows, int32_t epochs, uint64_t* bytes);
+int ccut_mlp_predict(const float* d_params, const float* d_x, int64_t rows, float* d_y, void* stream);
+int ccut_mlp_grad(const float* d_params, const float* d_x, const float* d_t, int64_t rows, void* d_work,
+                  uint64_t work_bytes, float* d_grad, float* loss, void* stream);
+int ccut_mlp_train(float* d_params, const float* d_x, const float* d_t, int64_t rows, int32_t epochs, float lr,
+                   void* d_work, uint64_t work_bytes, float* losses, void* stream);
+
+/*
+ * Whether and how to cut a circuit of q qubits, depth d and c_total cut
+ * gates.  Candidates: no cut, and n = 2, 3, 4 equal segments with the cuts
+ * spread evenly over the n-1 boundaries.
+ *  - d_params == NULL: the closed-form rule of Sec. IV: the n whose
+ *    Eq. (speedup_depth_free) margin is largest and positive, else no cut;
+ *    *predicted_s = NaN.  Host-only.
+ *  - otherwise: the learned model predicts each candidate's wall clock
+ *    (T_pre + T_sub + T_merge, or T_orig) and the smallest wins;
+ *    *predicted_s is its prediction.  If budget_s > 0 and even that exceeds
+ *    it, *choice = -1 (infeasible).  Synchronises `stream`.
+ * *choice: 0 = simulate uncut, n >= 2 = cut into n segments, -1 = infeasible.
+ * Errors: CCUT_EINVAL, CCUT_EHIP.
+ */
+int ccut_decide(int32_t q, int32_t d, int32_t c_total, const float* d_params, double budget_s, int32_t* choice,
+                double* predicted_s, void* stream);
+
 /*
  * Kernel timing.  While enabled, every kernel this library launches is
  * bracketed by HIP events recorded on the stream it runs on (a few

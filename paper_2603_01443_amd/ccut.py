@@ -89,6 +89,35 @@ def _load():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    fp, dp = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)
+    more = {
+        "ccut_threshold_ctotal": [i32, i32, dp],
+        "ccut_speedup_margin": [i32, i32, vp, dp],
+        "ccut_cost_features": [i32, i32, i32, i32, fp],
+        "ccut_mlp_work_bytes": [i64, i32, ctypes.POINTER(u64)],
+        "ccut_mlp_predict": [vp, vp, i64, vp, vp],
+        "ccut_mlp_grad": [vp, vp, vp, i64, vp, u64, vp, fp, vp],
+        "ccut_mlp_train": [vp, vp, vp, i64, i32, ctypes.c_float, vp, u64, fp, vp],
+        "ccut_decide": [i32, i32, i32, vp, ctypes.c_double, ctypes.POINTER(i32), dp, vp],
+    }
+    for name, args in more.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    for name, args in {
+        "ccut_plan_set_launch": [vp, i32, i32, i32, i32],
+        "ccut_plan_get_launch": [vp, ctypes.POINTER(i32)],
+        "ccut_autotune": [vp, vp, u64, vp, u64, i32, vp, dp],
+        "ccut_autotune_save": [ctypes.c_char_p],
+        "ccut_autotune_load": [ctypes.c_char_p],
+        "ccut_graph_create": [vp, vp, u64, vp, u64, i32, vp, ctypes.POINTER(vp)],
+        "ccut_graph_launch": [vp, vp],
+    }.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.ccut_graph_free.argtypes = [vp]
+    lib.ccut_graph_free.restype = None
     lib.ccut_profile_enable.argtypes = [i32]
     lib.ccut_profile_enable.restype = ctypes.c_int
     lib.ccut_profile_read.argtypes = [i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
@@ -246,6 +275,61 @@ def norm_fidelity(psi, ref, q: int, stream=None) -> dict:
 
 
 PROF_KERNELS = 7
+MLP_PARAMS = 4675
+
+
+def threshold_ctotal(q: int, n: int) -> float:
+    out = ctypes.c_double()
+    _check(_lib.ccut_threshold_ctotal(q, n, ctypes.byref(out)))
+    return out.value
+
+
+def speedup_margin(q: int, n: int, cuts_per_boundary: Sequence[int]) -> float:
+    arr = (ctypes.c_int32 * max(1, len(cuts_per_boundary)))(*cuts_per_boundary)
+    out = ctypes.c_double()
+    _check(_lib.ccut_speedup_margin(q, n, arr, ctypes.byref(out)))
+    return out.value
+
+
+def cost_features(q: int, d: int, n: int, c_total: int) -> List[float]:
+    out = (ctypes.c_float * 4)()
+    _check(_lib.ccut_cost_features(q, d, n, c_total, out))
+    return list(out)
+
+
+def mlp_work_bytes(rows: int, epochs: int) -> int:
+    out = ctypes.c_uint64()
+    _check(_lib.ccut_mlp_work_bytes(rows, epochs, ctypes.byref(out)))
+    return out.value
+
+
+def mlp_predict(params, x, y, rows: int, stream=None) -> None:
+    _check(_lib.ccut_mlp_predict(_ptr(params), _ptr(x), rows, _ptr(y), _stream(stream)))
+
+
+def mlp_grad(params, x, t, rows: int, work, grad, work_bytes: Optional[int] = None, stream=None) -> float:
+    loss = ctypes.c_float()
+    _check(_lib.ccut_mlp_grad(_ptr(params), _ptr(x), _ptr(t), rows, _ptr(work), _nbytes(work, work_bytes),
+                              _ptr(grad), ctypes.byref(loss), _stream(stream)))
+    return loss.value
+
+
+def mlp_train(params, x, t, rows: int, epochs: int, lr: float, work, work_bytes: Optional[int] = None,
+              stream=None) -> np.ndarray:
+    losses = np.zeros(max(epochs, 1), dtype=np.float32)
+    _check(_lib.ccut_mlp_train(_ptr(params), _ptr(x), _ptr(t), rows, epochs, lr, _ptr(work),
+                               _nbytes(work, work_bytes), losses.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                               _stream(stream)))
+    return losses[:epochs]
+
+
+def decide(q: int, d: int, c_total: int, params=None, budget_s: float = 0.0, stream=None):
+    """(choice, predicted seconds): choice 0 = no cut, n >= 2 segments, -1 = over budget."""
+    choice = ctypes.c_int32()
+    pred = ctypes.c_double()
+    _check(_lib.ccut_decide(q, d, c_total, _ptr(params) if params is not None else None, budget_s,
+                            ctypes.byref(choice), ctypes.byref(pred), _stream(stream)))
+    return choice.value, pred.value
 
 
 def profile_enable(on: bool = True) -> None:
@@ -266,6 +350,60 @@ def profile_read() -> dict:
         _check(_lib.ccut_profile_read(k, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(name)))
         out[name.value.decode()] = (n.value, ms.value)
     return out
+
+
+def plan_set_launch(plan: Plan, threads: int = 256, grid_cap: int = 0, per_variant: bool = False,
+                    mfma_min_terms: int = -1) -> None:
+    _check(_lib.ccut_plan_set_launch(plan.handle, threads, grid_cap, 1 if per_variant else 0, mfma_min_terms))
+
+
+def plan_get_launch(plan: Plan) -> dict:
+    out = (ctypes.c_int32 * 4)()
+    _check(_lib.ccut_plan_get_launch(plan.handle, out))
+    return {"threads": out[0], "grid_cap": out[1], "per_variant": out[2], "mfma_min_terms": out[3]}
+
+
+def autotune(plan: Plan, arena, psi, reps: int = 3, arena_bytes: Optional[int] = None,
+             psi_bytes: Optional[int] = None, stream=None) -> float:
+    best = ctypes.c_double()
+    _check(_lib.ccut_autotune(plan.handle, _ptr(arena), _nbytes(arena, arena_bytes), _ptr(psi),
+                              _nbytes(psi, psi_bytes), reps, _stream(stream), ctypes.byref(best)))
+    return best.value
+
+
+def autotune_save(path: str) -> None:
+    _check(_lib.ccut_autotune_save(path.encode()))
+
+
+def autotune_load(path: str) -> None:
+    _check(_lib.ccut_autotune_load(path.encode()))
+
+
+class Graph:
+    """Owner of a captured pipeline graph (ccut_graph_t)."""
+
+    def __init__(self, plan: Plan, arena, psi, precision="auto", stream=None,
+                 arena_bytes: Optional[int] = None, psi_bytes: Optional[int] = None):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p(0)
+        _check(_lib.ccut_graph_create(plan.handle, _ptr(arena), _nbytes(arena, arena_bytes), _ptr(psi),
+                                      _nbytes(psi, psi_bytes), prec, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.plan = plan   # the graph reads the plan's device tables
+
+    def launch(self, stream=None) -> None:
+        _check(_lib.ccut_graph_launch(self._h, _stream(stream)))
+
+    def free(self) -> None:
+        if self._h and self._h.value:
+            _lib.ccut_graph_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def version() -> str:

@@ -239,8 +239,18 @@ extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint6
   DeviceTables T;
   if (int rc = plan_tables(plan, static_cast<char*>(d_arena), s, T)) return rc;
   for (const auto& L : plan->launches) {
-    if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, L.total_wg, T.passes, T.ops,
-                            static_cast<float*>(d_arena), plan->bmax, 256, s))
+    if (plan->sim_per_variant) {
+      for (int j = 0; j < L.n_jobs; ++j) {
+        const SimJob& job = plan->jobs[L.job_begin + j];
+        const int nb = plan->pass_descs[job.pass_id].n_blocks;
+        if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, nb, job.wg_begin, T.passes, T.ops,
+                                static_cast<float*>(d_arena), plan->bmax, plan->sim_threads, 0, s))
+          return rc;
+      }
+      continue;
+    }
+    if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, L.total_wg, 0, T.passes, T.ops,
+                            static_cast<float*>(d_arena), plan->bmax, plan->sim_threads, plan->sim_grid_cap, s))
       return rc;
   }
   return CCUT_OK;
@@ -272,7 +282,10 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
   };
   for (const MergeStage& st : plan->stages) {
     int mode = precision;
-    if (mode == CCUT_PREC_AUTO) mode = st.K >= MFMA_MIN_TERMS ? CCUT_PREC_BF16X3 : CCUT_PREC_FP32;
+    if (mode == CCUT_PREC_AUTO) {
+      const int kmin = plan->auto_mfma_min_k >= 0 ? plan->auto_mfma_min_k : MFMA_MIN_TERMS;
+      mode = st.K >= kmin ? CCUT_PREC_BF16X3 : CCUT_PREC_FP32;
+    }
     if (mode == CCUT_PREC_FP32 || !merge_mfma_supported(st.qx, st.qy)) {
       // shapes below one MFMA tile take the float32 kernel, which is at least as accurate
       if (int rc = launch_merge_f32(st, buf(st.a_src), buf(st.b_src), buf(st.out_dst), T.weights, s))
@@ -350,8 +363,8 @@ extern "C" int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t 
   U->stamp = ++g_uncut_clock;
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (size_t p = 0; p < U->jobs.size(); ++p) {
-    if (int rc = launch_sim(U->dev.jobs + p, 1, U->descs[p].n_blocks, U->dev.passes, U->dev.ops,
-                            static_cast<float*>(d_psi), PASS_MAX_B, 256, s))
+    if (int rc = launch_sim(U->dev.jobs + p, 1, U->descs[p].n_blocks, 0, U->dev.passes, U->dev.ops,
+                            static_cast<float*>(d_psi), PASS_MAX_B, 256, 0, s))
       return rc;
   }
   return CCUT_OK;

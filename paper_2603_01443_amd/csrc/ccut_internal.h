@@ -147,8 +147,10 @@ struct ProfScope {
   ~ProfScope() { prof_end(tok, s); }
 };
 
-int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, const PassDesc* d_passes,
-               const KOp* d_ops, float* base, int bmax, int threads, hipStream_t s);
+// Runs workgroups [wg_offset, wg_offset + total_wg) of a job list; grid_cap > 0
+// makes the launch persistent (each workgroup loops over several blocks).
+int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
+               const KOp* d_ops, float* base, int bmax, int threads, int grid_cap, hipStream_t s);
 
 int launch_merge_f32(const MergeStage& st, const float* A, const float* B, float* out,
                      const float* d_weights, hipStream_t s);

@@ -32,7 +32,7 @@ __device__ __forceinline__ float2 cmadd2(float2 m0, float2 x, float2 m1, float2 
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int n_jobs, int total_wg,
-                                            const PassDesc* __restrict__ passes,
+                                            int wg_offset, const PassDesc* __restrict__ passes,
                                             const KOp* __restrict__ ops, float2* __restrict__ base) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* lo_tab = reinterpret_cast<uint64_t*>(smem);
@@ -40,7 +40,8 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
   float2* sh = reinterpret_cast<float2*>(hi_tab + TAB);
   const int tid = threadIdx.x;
 
-  for (int wg = blockIdx.x; wg < total_wg; wg += gridDim.x) {
+  for (int w = blockIdx.x; w < total_wg; w += gridDim.x) {
+    const int wg = w + wg_offset;
     // job lookup: last job whose first workgroup is <= wg
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
@@ -150,8 +151,8 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
 }
 
 template <int NT>
-int launch_sim_t(const SimJob* d_jobs, int n_jobs, int total_wg, const PassDesc* d_passes, const KOp* d_ops,
-                 float* base, int bmax, int grid, hipStream_t s) {
+int launch_sim_t(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
+                 const KOp* d_ops, float* base, int bmax, int grid, hipStream_t s) {
   const size_t shmem = 2 * TAB * sizeof(uint64_t) + (sizeof(float2) << bmax);
   static bool attr_set = false;
   if (!attr_set) {
@@ -160,23 +161,23 @@ int launch_sim_t(const SimJob* d_jobs, int n_jobs, int total_wg, const PassDesc*
     attr_set = true;
   }
   ProfScope prof(PROF_SIM, s);
-  hipLaunchKernelGGL(k_sim<NT>, dim3(grid), dim3(NT), shmem, s, d_jobs, n_jobs, total_wg, d_passes, d_ops,
-                     reinterpret_cast<float2*>(base));
+  hipLaunchKernelGGL(k_sim<NT>, dim3(grid), dim3(NT), shmem, s, d_jobs, n_jobs, total_wg, wg_offset, d_passes,
+                     d_ops, reinterpret_cast<float2*>(base));
   CCUT_HIP(hipGetLastError());
   return 0;
 }
 
 }  // namespace
 
-int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, const PassDesc* d_passes, const KOp* d_ops,
-               float* base, int bmax, int threads, hipStream_t s) {
+int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
+               const KOp* d_ops, float* base, int bmax, int threads, int grid_cap, hipStream_t s) {
   if (total_wg <= 0 || n_jobs <= 0) return 0;
   if (bmax < 1 || bmax > PASS_MAX_B) return fail(CCUT_EINVAL, "bad block bits %d", bmax);
-  const int grid = total_wg;
+  const int grid = (grid_cap > 0 && grid_cap < total_wg) ? grid_cap : total_wg;
   switch (threads) {
-    case 256: return launch_sim_t<256>(d_jobs, n_jobs, total_wg, d_passes, d_ops, base, bmax, grid, s);
-    case 512: return launch_sim_t<512>(d_jobs, n_jobs, total_wg, d_passes, d_ops, base, bmax, grid, s);
-    case 1024: return launch_sim_t<1024>(d_jobs, n_jobs, total_wg, d_passes, d_ops, base, bmax, grid, s);
+    case 256: return launch_sim_t<256>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_ops, base, bmax, grid, s);
+    case 512: return launch_sim_t<512>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_ops, base, bmax, grid, s);
+    case 1024: return launch_sim_t<1024>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_ops, base, bmax, grid, s);
     default: return fail(CCUT_EINVAL, "unsupported workgroup size %d", threads);
   }
 }

@@ -277,6 +277,7 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
   pack_image(P);
   P->tables_off = align256(P->split_off + P->split_bytes);
   P->total_arena = align256(P->tables_off + P->image.size());
+  apply_tuned(P);
 
   *plan_out = guard.release();
   return CCUT_OK;

@@ -37,6 +37,12 @@ struct ccut_plan {
   uint64_t total_arena = 0; // bytes the caller's arena must hold
 
   ccut::DeviceTables dev;   // plan-owned copy after ccut_plan_prepare (graph capture)
+
+  // launch configuration (ccut_plan_set_launch / ccut_autotune)
+  int sim_threads = 256;     // workgroup size of the simulation kernel
+  int sim_grid_cap = 0;      // 0: one workgroup per block; > 0: persistent grid of this size
+  int sim_per_variant = 0;   // 1: one launch per (segment, variant) instead of one per pass index
+  int auto_mfma_min_k = -1;  // CCUT_PREC_AUTO threshold on K (-1: library default)
 };
 
 namespace ccut {
@@ -46,6 +52,8 @@ int gate_matrix(const ccut_gate_t& g, cd m[4]);
 void release_device(DeviceTables& t);
 // Packs the tables into one image with 256-byte aligned sections.
 void pack_image(ccut_plan* P);
+// Applies a cached autotuned launch configuration to a new plan, if any.
+void apply_tuned(ccut_plan* P);
 // Enqueues a copy of `bytes` host bytes to device memory `dst` through a pinned staging ring.
 int staged_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s);
 }  // namespace ccut

@@ -42,6 +42,8 @@ hipEvent_t take() {
 int prof_begin(int kernel, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return -1;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
   Record r{kernel, take(), take()};
   if (!r.a || !r.b) return -1;
   if (hipEventRecord(r.a, s) != hipSuccess) return -1;

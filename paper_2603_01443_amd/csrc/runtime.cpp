@@ -1,0 +1,244 @@
+// Runtime around the kernels: HIP-graph capture of a plan's whole pipeline,
+// launch configuration, and a measuring autotuner with a persistent cache.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <new>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+struct ccut_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = -1;
+};
+
+namespace ccut {
+
+namespace {
+
+struct TuneEntry {
+  int threads = 256;
+  int grid_cap = 0;
+  int mfma_min_k = -1;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+
+std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+  std::string a = p.gcnArchName;
+  return a.substr(0, a.find(':'));
+}
+
+// Shape signature of a plan: segment sizes, variants, passes and merge stages.
+std::string signature(const ccut_plan* P) {
+  std::string s = "q" + std::to_string(P->q);
+  for (const auto& S : P->segs)
+    s += "|" + std::to_string(S.q) + "x" + std::to_string(1 << S.c) + "p" + std::to_string(S.passes.size());
+  for (const auto& st : P->stages)
+    s += "|m" + std::to_string(st.qx) + "," + std::to_string(st.qy) + "," + std::to_string(st.K) + "," +
+         std::to_string(st.batch);
+  return s;
+}
+
+int time_call(hipStream_t s, int reps, float* ms_out, const std::function<int()>& fn) {
+  hipEvent_t a, b;
+  CCUT_HIP(hipEventCreate(&a));
+  CCUT_HIP(hipEventCreate(&b));
+  int rc = fn();  // warm-up
+  std::vector<float> t;
+  for (int r = 0; r < reps && rc == 0; ++r) {
+    (void)hipEventRecord(a, s);
+    rc = fn();
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    t.push_back(ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  std::sort(t.begin(), t.end());
+  *ms_out = t[t.size() / 2];
+  return 0;
+}
+
+}  // namespace
+
+// Applies a cached configuration to a freshly built plan, if one exists.
+void apply_tuned(ccut_plan* P) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune.empty()) return;
+  auto it = g_tune.find(arch_name() + "|" + signature(P));
+  if (it == g_tune.end()) return;
+  P->sim_threads = it->second.threads;
+  P->sim_grid_cap = it->second.grid_cap;
+  P->auto_mfma_min_k = it->second.mfma_min_k;
+}
+
+}  // namespace ccut
+
+using namespace ccut;
+
+extern "C" int ccut_plan_set_launch(ccut_plan_t* plan, int32_t threads, int32_t grid_cap, int32_t per_variant,
+                                    int32_t mfma_min_terms) {
+  clear_error();
+  if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
+  if (threads != 256 && threads != 512 && threads != 1024) return fail(CCUT_EINVAL, "threads must be 256/512/1024");
+  if (grid_cap < 0 || mfma_min_terms < -1) return fail(CCUT_EINVAL, "bad launch configuration");
+  plan->sim_threads = threads;
+  plan->sim_grid_cap = grid_cap;
+  plan->sim_per_variant = per_variant ? 1 : 0;
+  plan->auto_mfma_min_k = mfma_min_terms;
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_get_launch(const ccut_plan_t* plan, int32_t out[4]) {
+  clear_error();
+  if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
+  out[0] = plan->sim_threads;
+  out[1] = plan->sim_grid_cap;
+  out[2] = plan->sim_per_variant;
+  out[3] = plan->auto_mfma_min_k;
+  return CCUT_OK;
+}
+
+extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* d_psi,
+                             uint64_t psi_bytes, int32_t reps, void* stream, double* best_ms) {
+  clear_error();
+  if (!plan || !d_arena || !d_psi || reps < 1) return fail(CCUT_EINVAL, "bad argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int saved_pv = plan->sim_per_variant;
+  plan->sim_per_variant = 0;
+  int total_wg = 0;
+  for (const auto& L : plan->launches) total_wg = std::max(total_wg, L.total_wg);
+  float best = 1e30f;
+  int bt = plan->sim_threads, bg = plan->sim_grid_cap;
+  const int threads[3] = {256, 512, 1024};
+  const int caps[5] = {0, 256, 512, 1024, 2048};
+  for (int t : threads) {
+    for (int c : caps) {
+      if (c != 0 && c >= total_wg) continue;
+      plan->sim_threads = t;
+      plan->sim_grid_cap = c;
+      float ms = 0.f;
+      int rc = time_call(s, reps, &ms, [&]() { return ccut_simulate_subcircuits(plan, d_arena, arena_bytes, stream); });
+      if (rc) {
+        plan->sim_per_variant = saved_pv;
+        return rc;
+      }
+      if (ms < best) { best = ms; bt = t; bg = c; }
+    }
+  }
+  plan->sim_threads = bt;
+  plan->sim_grid_cap = bg;
+  // merge: float32 vector kernel against the split-bfloat16 MFMA kernel at this plan's term counts
+  float t32 = 0.f, tmf = 0.f;
+  int rc = time_call(s, reps, &t32, [&]() {
+    return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_FP32, stream);
+  });
+  if (!rc)
+    rc = time_call(s, reps, &tmf, [&]() {
+      return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_BF16X3, stream);
+    });
+  plan->sim_per_variant = saved_pv;
+  if (rc) return rc;
+  int kmax = 1;
+  for (const auto& st : plan->stages) kmax = std::max(kmax, st.K);
+  plan->auto_mfma_min_k = tmf < t32 ? 1 : kmax + 1;
+  if (best_ms) *best_ms = best + std::min(t32, tmf);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[arch_name() + "|" + signature(plan)] = TuneEntry{bt, bg, plan->auto_mfma_min_k};
+  return CCUT_OK;
+}
+
+extern "C" int ccut_autotune_save(const char* path) {
+  clear_error();
+  if (!path) return fail(CCUT_EINVAL, "path is NULL");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(CCUT_EINVAL, "cannot write %s", path);
+  std::fprintf(f, "# ccut autotune cache: key threads grid_cap mfma_min_k\n");
+  for (const auto& kv : g_tune)
+    std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.threads, kv.second.grid_cap, kv.second.mfma_min_k);
+  std::fclose(f);
+  return CCUT_OK;
+}
+
+extern "C" int ccut_autotune_load(const char* path) {
+  clear_error();
+  if (!path) return fail(CCUT_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(CCUT_EINVAL, "cannot read %s", path);
+  char key[1024];
+  int t, c, k;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  char line[1200];
+  while (std::fgets(line, sizeof(line), f)) {
+    if (line[0] == '#') continue;
+    if (std::sscanf(line, "%1023s %d %d %d", key, &t, &c, &k) == 4 && (t == 256 || t == 512 || t == 1024) &&
+        c >= 0 && k >= -1)
+      g_tune[key] = TuneEntry{t, c, k};
+  }
+  std::fclose(f);
+  return CCUT_OK;
+}
+
+extern "C" int ccut_graph_create(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* d_psi,
+                                 uint64_t psi_bytes, int32_t precision, void* stream, ccut_graph_t** out) {
+  clear_error();
+  if (!plan || !d_arena || !d_psi || !out) return fail(CCUT_EINVAL, "NULL argument");
+  if (!stream) return fail(CCUT_EINVAL, "graph capture needs a non-default stream");
+  *out = nullptr;
+  if (int rc = ccut_plan_prepare(plan)) return rc;  // tables must not be copied inside the graph
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto* G = new (std::nothrow) ccut_graph();
+  if (!G) return fail(CCUT_ENOMEM, "host allocation failed");
+  CCUT_HIP(hipGetDevice(&G->device));
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    delete G;
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  int rc = ccut_simulate_subcircuits(plan, d_arena, arena_bytes, stream);
+  if (rc == 0) rc = ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, precision, stream);
+  std::string msg = rc ? ccut_last_error() : "";
+  e = hipStreamEndCapture(s, &G->graph);
+  if (rc || e != hipSuccess) {
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+    return rc ? fail(rc, "%s", msg.c_str()) : hip_fail(e, "hipStreamEndCapture");
+  }
+  e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(G->graph);
+    delete G;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  *out = G;
+  return CCUT_OK;
+}
+
+extern "C" int ccut_graph_launch(ccut_graph_t* g, void* stream) {
+  clear_error();
+  if (!g || !g->exec) return fail(CCUT_EINVAL, "graph is NULL");
+  CCUT_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+  return CCUT_OK;
+}
+
+extern "C" void ccut_graph_free(ccut_graph_t* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}

@@ -1,0 +1,93 @@
+"""GPU kernels of the learned cost model against the float64 oracle MLP.
+
+The network is not in the paper (parity unpinned with respect to it); the
+kernels are checked against the oracle's float64 forward pass and its
+backpropagation, which the CPU tests pin to central finite differences.
+Float32 tolerances: outputs and gradients agree to ~1e-5 relative.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from inputs.mlp_init import glorot_params  # noqa: E402
+from oracle import mlp as omlp, threshold  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ccut():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_01443_amd import ccut
+    return ccut
+
+
+def data(rows, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(rows, 4))
+    t = np.stack([0.3 * x[:, 0] - x[:, 1], np.tanh(x[:, 2]) + 0.1 * x[:, 3], x[:, 0] * x[:, 3]], axis=1)
+    return x, t
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a, dtype=np.float32), device="cuda")
+
+
+@pytest.mark.parametrize("rows", [1, 31, 32, 33, 257])
+def test_forward_matches_oracle(ccut, rows):
+    p = glorot_params(1)
+    x, _ = data(rows, 2)
+    y = torch.empty(rows, 3, device="cuda")
+    ccut.mlp_predict(dev(p), dev(x), y, rows)
+    want, _ = omlp.forward(p.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(y.cpu().numpy() - want)) < 1e-5 * (1 + np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("rows", [5, 64, 333])
+def test_gradient_matches_oracle(ccut, rows):
+    p = glorot_params(4)
+    x, t = data(rows, 5)
+    p32, x32, t32 = (a.astype(np.float32).astype(np.float64) for a in (p, x, t))
+    work = torch.empty(ccut.mlp_work_bytes(rows, 1), dtype=torch.uint8, device="cuda")
+    grad = torch.empty(ccut.MLP_PARAMS, device="cuda")
+    loss = ccut.mlp_grad(dev(p), dev(x), dev(t), rows, work, grad)
+    y, cache = omlp.forward(p32, x32)
+    want = omlp.backward(p32, cache, y, t32)
+    got = grad.cpu().numpy()
+    assert abs(loss - omlp.loss(y, t32)) < 1e-5 * omlp.loss(y, t32)
+    assert np.max(np.abs(got - want)) < 1e-5 * np.max(np.abs(want))
+
+
+def test_training_tracks_oracle_and_graph_replay_is_exact(ccut):
+    rows, epochs, lr = 200, 120, 1e-2
+    p0 = glorot_params(7)
+    x, t = data(rows, 8)
+    work = torch.empty(ccut.mlp_work_bytes(rows, epochs), dtype=torch.uint8, device="cuda")
+    pa = dev(p0)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        la = ccut.mlp_train(pa, dev(x), dev(t), rows, epochs, lr, work, stream=s)   # graph replays
+    torch.cuda.synchronize()
+    pb = dev(p0)
+    lb = ccut.mlp_train(pb, dev(x), dev(t), rows, epochs, lr, work, stream=None)    # plain launches
+    assert torch.equal(pa, pb)
+    assert np.array_equal(la, lb)
+    pw, hist = omlp.train(p0.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64),
+                          t.astype(np.float32).astype(np.float64), epochs, lr)
+    assert la[-1] < 0.3 * la[0]
+    assert np.max(np.abs(np.asarray(la, dtype=np.float64) - hist) / np.asarray(hist)) < 1e-3
+    assert np.max(np.abs(pa.cpu().numpy() - pw)) < 1e-3
+
+
+def test_learned_decision_prefers_cheaper_prediction(ccut):
+    # a network with zero weights and biases (ln 1e-3, ln 1e-3, ln 1e-3) predicts 3 ms per cut run
+    # and 1 ms uncut, so the learned rule must keep the circuit uncut
+    p = np.zeros(ccut.MLP_PARAMS)
+    p[-3:] = np.log(1e-3)
+    choice, pred = ccut.decide(24, 20, 4, dev(p))
+    assert choice == 0 and abs(pred - 1e-3) < 1e-8
+    choice, pred = ccut.decide(24, 20, 4, dev(p), budget_s=1e-4)
+    assert choice == -1
+    assert ccut.decide(24, 20, 4)[0] == threshold.closed_form_choice(24, 4)

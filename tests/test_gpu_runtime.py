@@ -1,0 +1,85 @@
+"""Batching, launch configuration, HIP-graph replay and autotuning: every
+configuration must give bit-identical results to the default launch path."""
+
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from inputs import brickwork  # noqa: E402
+from oracle import metrics, statevector  # noqa: E402
+
+from .gpu_util import to_np  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_01443_amd import ccut, pipeline
+    return ccut, pipeline
+
+
+def arena_copy(run):
+    torch.cuda.synchronize()
+    return run.arena[: run.info["state_bytes"]].clone()
+
+
+@pytest.mark.parametrize("q,n,sizes,cuts", [(20, 2, [10, 10], [6]), (32, 3, [10, 11, 11], [3, 3]),
+                                            (30, 2, [15, 15], [2])])
+def test_launch_configurations_bit_identical(lib, q, n, sizes, cuts):
+    """One launch for all variants vs persistent grids vs one launch per variant (uneven sizes too)."""
+    ccut, pipeline = lib
+    g = brickwork(q, 6, n, sum(cuts), seed=4, seg_sizes=sizes, cuts_per_boundary=cuts)
+    run = pipeline.CutRun(q, g, n, sizes, psi=torch.empty(8, dtype=torch.complex64, device="cuda"))
+    run.simulate_subcircuits()
+    ref = arena_copy(run)
+    for threads, cap, pv in [(1024, 0, False), (512, 64, False), (256, 200, False), (256, 0, True),
+                             (1024, 0, True)]:
+        ccut.plan_set_launch(run.plan, threads, cap, pv)
+        run.arena[: run.info["state_bytes"]].zero_()
+        run.simulate_subcircuits()
+        assert torch.equal(arena_copy(run), ref), (threads, cap, pv)
+
+
+def test_graph_replay_matches_direct(lib):
+    ccut, pipeline = lib
+    q, n = 20, 2
+    g = brickwork(q, 10, n, 6, seed=2)
+    run = pipeline.CutRun(q, g, n)
+    direct = run.run("auto").clone()
+    s = torch.cuda.Stream()
+    graph = ccut.Graph(run.plan, run.arena, run.psi, "auto", stream=s)
+    for rep in range(3):
+        run.psi.zero_()
+        run.arena.zero_()
+        scratch = pipeline.uncut(16, brickwork(16, 4, 2, 1, seed=rep))   # eager work between replays
+        torch.cuda.synchronize()
+        graph.launch(s)
+        s.synchronize()
+        assert torch.equal(torch.view_as_real(run.psi), torch.view_as_real(direct)), rep
+        del scratch
+    graph.free()
+
+
+def test_autotune_keeps_results_and_caches(lib, tmp_path):
+    ccut, pipeline = lib
+    q, n = 22, 2
+    g = brickwork(q, 10, n, 6, seed=6)
+    run = pipeline.CutRun(q, g, n)
+    before = run.run("bf16x3").clone()
+    best = ccut.autotune(run.plan, run.arena, run.psi, reps=2, stream=torch.cuda.current_stream())
+    cfg = ccut.plan_get_launch(run.plan)
+    print("autotuned", cfg, f"{best:.3f} ms", flush=True)
+    assert best > 0 and cfg["threads"] in (256, 512, 1024)
+    after = run.run("bf16x3")
+    assert torch.equal(torch.view_as_real(after), torch.view_as_real(before))
+    path = str(tmp_path / "tune.txt")
+    ccut.autotune_save(path)
+    assert os.path.getsize(path) > 0
+    ccut.autotune_load(path)
+    fresh = ccut.cut_plan(q, g, n)                 # same shape: starts from the cached entry
+    assert ccut.plan_get_launch(fresh) == {**cfg, "per_variant": 0}
