@@ -237,6 +237,15 @@ int ccut_plan_set_launch(ccut_plan_t* plan, int32_t threads, int32_t grid_cap, i
 int ccut_plan_get_launch(const ccut_plan_t* plan, int32_t out[4]);
 
 /*
+ * Store path and grid of the MFMA merge GEMM: epilogue 0 stores accumulators
+ * directly, 1 transposes 32-row slabs through LDS into 16-byte row stores;
+ * grid_cap 0 launches one workgroup per 128 x 256 tile, > 0 a persistent grid
+ * of at most grid_cap workgroups that loop over tiles.  Results do not depend
+ * on either.  Host-only.  Errors: CCUT_EINVAL.
+ */
+int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap);
+
+/*
  * Autotuner: times the simulation kernel over workgroup sizes x persistent
  * grid sizes, and the merge with the float32 kernel against the split-bfloat16
  * MFMA kernel (median of `reps` runs, HIP events on `stream`), applies the

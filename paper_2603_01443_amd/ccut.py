@@ -107,6 +107,7 @@ def _load():
     for name, args in {
         "ccut_plan_set_launch": [vp, i32, i32, i32, i32],
         "ccut_plan_get_launch": [vp, ctypes.POINTER(i32)],
+        "ccut_plan_set_merge": [vp, i32, i32],
         "ccut_autotune": [vp, vp, u64, vp, u64, i32, vp, dp],
         "ccut_autotune_save": [ctypes.c_char_p],
         "ccut_autotune_load": [ctypes.c_char_p],
@@ -355,6 +356,10 @@ def profile_read() -> dict:
 def plan_set_launch(plan: Plan, threads: int = 256, grid_cap: int = 0, per_variant: bool = False,
                     mfma_min_terms: int = -1) -> None:
     _check(_lib.ccut_plan_set_launch(plan.handle, threads, grid_cap, 1 if per_variant else 0, mfma_min_terms))
+
+
+def plan_set_merge(plan: Plan, epilogue: int = 0, grid_cap: int = 0) -> None:
+    _check(_lib.ccut_plan_set_merge(plan.handle, epilogue, grid_cap))
 
 
 def plan_get_launch(plan: Plan) -> dict:

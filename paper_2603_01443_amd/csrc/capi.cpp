@@ -71,6 +71,7 @@ void pack_image(ccut_plan* P) {
   P->image.clear();
   pack(P->image, P->kops, P->img_ops);
   pack(P->image, P->pass_descs, P->img_passes);
+  pack(P->image, P->stage_descs, P->img_stages);
   pack(P->image, P->jobs, P->img_jobs);
   pack(P->image, P->weights, P->img_weights);
   if (P->image.empty()) P->image.resize(256);
@@ -103,7 +104,7 @@ int staged_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s) {
 
 // Copies a table image to a new device allocation (synchronous).
 int upload_tables(DeviceTables& t, const std::vector<unsigned char>& img, uint64_t o_ops, uint64_t o_pass,
-                  uint64_t o_jobs, uint64_t o_w) {
+                  uint64_t o_stage, uint64_t o_jobs, uint64_t o_w) {
   int dev = 0;
   CCUT_HIP(hipGetDevice(&dev));
   if (t.device == dev) return 0;
@@ -119,6 +120,7 @@ int upload_tables(DeviceTables& t, const std::vector<unsigned char>& img, uint64
   t.blob = blob;
   t.ops = reinterpret_cast<KOp*>(b + o_ops);
   t.passes = reinterpret_cast<PassDesc*>(b + o_pass);
+  t.stages = reinterpret_cast<StageDesc*>(b + o_stage);
   t.jobs = reinterpret_cast<SimJob*>(b + o_jobs);
   t.weights = reinterpret_cast<float*>(b + o_w);
   t.device = dev;
@@ -134,6 +136,7 @@ int plan_tables(ccut_plan* P, char* arena, hipStream_t s, DeviceTables& out) {
     out = DeviceTables();
     out.ops = P->dev.ops;
     out.passes = P->dev.passes;
+    out.stages = P->dev.stages;
     out.jobs = P->dev.jobs;
     out.weights = P->dev.weights;
     return 0;
@@ -143,6 +146,7 @@ int plan_tables(ccut_plan* P, char* arena, hipStream_t s, DeviceTables& out) {
   out = DeviceTables();
   out.ops = reinterpret_cast<KOp*>(b + P->img_ops);
   out.passes = reinterpret_cast<PassDesc*>(b + P->img_passes);
+  out.stages = reinterpret_cast<StageDesc*>(b + P->img_stages);
   out.jobs = reinterpret_cast<SimJob*>(b + P->img_jobs);
   out.weights = reinterpret_cast<float*>(b + P->img_weights);
   return 0;
@@ -170,6 +174,7 @@ struct UncutProg {
   int32_t q = 0;
   std::vector<ccut_gate_t> gates;
   std::vector<PassDesc> descs;
+  std::vector<StageDesc> stages;
   std::vector<KOp> kops;
   std::vector<SimJob> jobs;  // one per pass
   DeviceTables dev;
@@ -206,7 +211,7 @@ int compile_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, UncutPro
   std::vector<Pass> passes;
   if (int rc = schedule_passes(pb.prog, PASS_MAX_B, 4, passes)) return rc;
   for (const Pass& p : passes) {
-    int pid = append_pass(p, q, U.descs, U.kops);
+    int pid = append_pass(p, q, U.descs, U.stages, U.kops);
     SimJob j;
     std::memset(&j, 0, sizeof(j));
     j.pass_id = pid;
@@ -226,7 +231,8 @@ extern "C" const char* ccut_version(void) { return "ccut 0.1 gfx950"; }
 extern "C" int ccut_plan_prepare(ccut_plan_t* plan) {
   clear_error();
   if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
-  return upload_tables(plan->dev, plan->image, plan->img_ops, plan->img_passes, plan->img_jobs, plan->img_weights);
+  return upload_tables(plan->dev, plan->image, plan->img_ops, plan->img_passes, plan->img_stages, plan->img_jobs,
+                       plan->img_weights);
 }
 
 extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* stream) {
@@ -243,13 +249,13 @@ extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint6
       for (int j = 0; j < L.n_jobs; ++j) {
         const SimJob& job = plan->jobs[L.job_begin + j];
         const int nb = plan->pass_descs[job.pass_id].n_blocks;
-        if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, nb, job.wg_begin, T.passes, T.ops,
+        if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, nb, job.wg_begin, T.passes, T.stages, T.ops,
                                 static_cast<float*>(d_arena), plan->bmax, plan->sim_threads, 0, s))
           return rc;
       }
       continue;
     }
-    if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, L.total_wg, 0, T.passes, T.ops,
+    if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, L.total_wg, 0, T.passes, T.stages, T.ops,
                             static_cast<float*>(d_arena), plan->bmax, plan->sim_threads, plan->sim_grid_cap, s))
       return rc;
   }
@@ -315,7 +321,7 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
     a.Rlo = a.Rhi + (uint64_t)a.r_batch * a.r_plane_stride;
     a.out = buf(st.out_dst) + 2 * st.out_off;
     a.out_bstride = st.out_bstride;
-    if (int rc = launch_merge_mfma(a, mode, s)) return rc;
+    if (int rc = launch_merge_mfma(a, mode, plan->merge_epilogue, plan->merge_grid_cap, s)) return rc;
   }
   return CCUT_OK;
 }
@@ -344,12 +350,13 @@ extern "C" int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t 
     fresh->gates.assign(gates, gates + n_gates);
     if (int rc = compile_uncut(q, gates, n_gates, *fresh)) return rc;
     std::vector<unsigned char> img;
-    uint64_t o_ops, o_pass, o_jobs, o_w;
+    uint64_t o_ops, o_pass, o_stage, o_jobs, o_w;
     pack(img, fresh->kops, o_ops);
     pack(img, fresh->descs, o_pass);
+    pack(img, fresh->stages, o_stage);
     pack(img, fresh->jobs, o_jobs);
     o_w = img.size();
-    if (int rc = upload_tables(fresh->dev, img, o_ops, o_pass, o_jobs, o_w)) return rc;
+    if (int rc = upload_tables(fresh->dev, img, o_ops, o_pass, o_stage, o_jobs, o_w)) return rc;
     if (g_uncut.size() >= UNCUT_CACHE) {
       auto oldest = g_uncut.begin();
       for (auto i = g_uncut.begin(); i != g_uncut.end(); ++i)
@@ -363,8 +370,8 @@ extern "C" int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t 
   U->stamp = ++g_uncut_clock;
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (size_t p = 0; p < U->jobs.size(); ++p) {
-    if (int rc = launch_sim(U->dev.jobs + p, 1, U->descs[p].n_blocks, 0, U->dev.passes, U->dev.ops,
-                            static_cast<float*>(d_psi), PASS_MAX_B, 256, 0, s))
+    if (int rc = launch_sim(U->dev.jobs + p, 1, U->descs[p].n_blocks, 0, U->dev.passes, U->dev.stages, U->dev.ops,
+                            static_cast<float*>(d_psi), PASS_MAX_B, 1024, 0, s))
       return rc;
   }
   return CCUT_OK;

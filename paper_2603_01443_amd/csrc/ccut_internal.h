@@ -77,6 +77,21 @@ struct KOp {
 static_assert(sizeof(KOp) == 96, "KOp layout");
 
 constexpr int PASS_MAX_B = 14;   // 2^14 complex64 = 128 KiB of LDS per block
+constexpr int REG_BITS = 4;      // amplitudes held per thread in a register stage: 2^4
+constexpr int STAGE_MIN_B = 9;   // blocks of at least 2^9 amplitudes run in register stages
+
+// A register stage inside an LDS block: every thread holds the 2^REG_BITS
+// amplitudes spanned by local bits reg[], its other local bits fixed by tfix[]
+// (thread slot bit j -> local bit tfix[j]).  Ops of a stage: KOP_DENSE.a and
+// KOP_CXL.b name register positions (0..REG_BITS-1); every other bit field is a
+// local bit.
+struct StageDesc {
+  int32_t op_begin;
+  int32_t op_count;
+  int32_t reg[REG_BITS];
+  int32_t tfix[PASS_MAX_B];
+  int32_t pad[2];
+};
 
 // One LDS-blocked pass over a state: blocks of 2^b amplitudes spanning the
 // register qubits group[0..b); the other qubits are fixed per block.
@@ -87,15 +102,20 @@ struct PassDesc {
   int32_t op_count;
   int32_t init;      // 1: the state is |0...0> before this pass (nothing is read)
   int32_t n_blocks;  // 2^(nq - b)
+  int32_t stage_begin;  // into the stage table; stage_count == 0: ops run one by one
+  int32_t stage_count;
   int32_t group[24]; // local bit j -> register qubit
   int32_t fixed[24]; // j-th non-group qubit (ascending), takes bit j of the block id
 };
 
 struct Pass {
   std::vector<int32_t> group;  // size b, low qubits first
-  std::vector<KOp> kops;
+  std::vector<KOp> kops;       // block-level ops (local bits)
   bool init = false;
 };
+
+// Splits a pass's block-level ops into register stages (stage-level op encoding).
+void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& stages, std::vector<KOp>& out);
 
 // Schedule a program into LDS-blocked passes of at most 2^bmax amplitudes.
 // Low qubits [0, low_bits) sit in every block (coalesced runs).
@@ -130,6 +150,7 @@ struct DeviceTables {
   void* blob = nullptr;
   KOp* ops = nullptr;
   PassDesc* passes = nullptr;
+  StageDesc* stages = nullptr;
   SimJob* jobs = nullptr;
   float* weights = nullptr;    // complex64 merge weights
 };
@@ -150,7 +171,8 @@ struct ProfScope {
 // Runs workgroups [wg_offset, wg_offset + total_wg) of a job list; grid_cap > 0
 // makes the launch persistent (each workgroup loops over several blocks).
 int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
-               const KOp* d_ops, float* base, int bmax, int threads, int grid_cap, hipStream_t s);
+               const StageDesc* d_stages, const KOp* d_ops, float* base, int bmax, int threads, int grid_cap,
+               hipStream_t s);
 
 int launch_merge_f32(const MergeStage& st, const float* A, const float* B, float* out,
                      const float* d_weights, hipStream_t s);

@@ -19,10 +19,12 @@
 //   Rf[(cb * S + s) * 64 + lane][e] = R[16 s + 8 (lane / 32) + e][32 cb + lane % 32]
 // with S = ceil(2K / 16) steps (the inner dimension is zero-padded).
 //
-// Tiles: a workgroup (4 wavefronts, 2 x 2) owns 128 rows x 256 real columns;
-// each wavefront 64 x 128 = 2 x 4 blocks of 32 x 32.  Consecutive workgroups
-// land on consecutive XCDs; each XCD is given one band of columns so that the
-// R fragments of its band stay in its L2 while rows stream through.
+// Tiles: a workgroup (4 wavefronts, 2 x 2) owns 128 rows x 256 real columns
+// at a time; each wavefront 64 x 128 = 2 x 4 blocks of 32 x 32.  Consecutive
+// workgroups land on consecutive XCDs; each XCD is given one band of columns
+// so that the R fragments of its band stay in its L2 while rows stream
+// through.  With a capped grid the kernel is persistent: workgroups loop over
+// tiles, so a tile's stores drain while the next tile is computed.
 #include "ccut_internal.h"
 #include "merge_mfma.h"
 
@@ -33,6 +35,7 @@ namespace {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
@@ -143,86 +146,126 @@ __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
   }
 }
 
-template <int MODE>
+// EPI 0: every lane stores its accumulators directly (4-byte non-temporal stores,
+//        two full 128-byte rows per instruction).
+// EPI 1: each wavefront writes a 32-row slab through LDS and stores it back as
+//        16-byte chunks, two 512-byte row segments per instruction.
+constexpr int EPI_LDS_ROW = 128 + 4;  // floats per LDS row (padded)
+
+template <int MODE, int EPI>
 __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lhi, const uint4* __restrict__ Llo,
                                                     const uint4* __restrict__ Rhi, const uint4* __restrict__ Rlo,
                                                     uint64_t l_bstride, uint64_t r_bstride, float* __restrict__ out,
                                                     uint64_t out_bstride, int qx, int qy, int S, int col_tiles,
                                                     int row_tiles) {
   const int beta = blockIdx.y;
-  // XCD-aware tile order: workgroup b runs on XCD b % 8; give each XCD a band of columns.
-  const int b = blockIdx.x;
-  int trow, tcol;
-  if ((col_tiles & 7) == 0) {
-    const int band = col_tiles >> 3;
-    const int xcd = b & 7, i = b >> 3;
-    trow = i / band;
-    tcol = xcd * band + i % band;
-  } else {
-    trow = b / col_tiles;
-    tcol = b % col_tiles;
-  }
-  if (trow >= row_tiles) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rb0 = trow * 4 + (wave >> 1) * 2;  // 32-row blocks of this wave
-  const int cb0 = tcol * 8 + (wave & 1) * 4;   // 32-column blocks of this wave
-  const uint4* lh = Lhi + beta * l_bstride + ((uint64_t)rb0 * S) * 64 + lane;
-  const uint4* ll = Llo + beta * l_bstride + ((uint64_t)rb0 * S) * 64 + lane;
-  const uint4* rh = Rhi + beta * r_bstride + ((uint64_t)cb0 * S) * 64 + lane;
-  const uint4* rl = Rlo + beta * r_bstride + ((uint64_t)cb0 * S) * 64 + lane;
   const uint64_t lstep = (uint64_t)S * 64;  // next 32-row (or column) block
-
-  f32x16 acc[2][4];
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.f;
-
-  for (int s = 0; s < S; ++s) {
-    uint4 a_hi[2], a_lo[2], b_hi[4], b_lo[4];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      a_hi[r] = lh[r * lstep + s * 64];
-      if (MODE != MERGE_BF16) a_lo[r] = ll[r * lstep + s * 64];
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      b_hi[c] = rh[c * lstep + s * 64];
-      if (MODE != MERGE_BF16) b_lo[c] = rl[c * lstep + s * 64];
-    }
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        if (MODE != MERGE_BF16) {
-          acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
-          acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
-        }
-        acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
-      }
-  }
-
   const float scale = MODE == MERGE_FP16X3 ? (1.0f / 268435456.0f) : 1.0f;  // 2^-28
   const uint64_t ncols = (uint64_t)2 << qx;
   float* ob = out + beta * out_bstride;
+  const int ntiles = col_tiles * row_tiles;
+  // Persistent tile loop.  Workgroup b runs on XCD b % 8; with whole XCD bands the
+  // workgroups of one XCD sweep the tiles of one column band, so the band's R
+  // fragments stay in that XCD's L2.  The stores of a tile drain while the next
+  // tile's MFMAs run.
+  const bool banded = (col_tiles & 7) == 0 && (gridDim.x & 7) == 0;
+  const int band = col_tiles >> 3;
+  const int step = banded ? (int)(gridDim.x >> 3) : (int)gridDim.x;
+  const int first = banded ? (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+  const int limit = banded ? ntiles >> 3 : ntiles;
+  for (int i = first; i < limit; i += step) {
+    int trow, tcol;
+    if (banded) {
+      trow = i / band;
+      tcol = (int)(blockIdx.x & 7) * band + i % band;
+    } else {
+      trow = i / col_tiles;
+      tcol = i % col_tiles;
+    }
+    const int rb0 = trow * 4 + (wave >> 1) * 2;  // 32-row blocks of this wave
+    const int cb0 = tcol * 8 + (wave & 1) * 4;   // 32-column blocks of this wave
+    const uint4* lh = Lhi + beta * l_bstride + ((uint64_t)rb0 * S) * 64 + lane;
+    const uint4* ll = Llo + beta * l_bstride + ((uint64_t)rb0 * S) * 64 + lane;
+    const uint4* rh = Rhi + beta * r_bstride + ((uint64_t)cb0 * S) * 64 + lane;
+    const uint4* rl = Rlo + beta * r_bstride + ((uint64_t)cb0 * S) * 64 + lane;
+
+    f32x16 acc[2][4];
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const uint64_t col = (uint64_t)(cb0 + c) * 32 + (lane & 31);
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const uint64_t row = (uint64_t)(rb0 + r) * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
-        __builtin_nontemporal_store(acc[r][c][v] * scale, ob + row * ncols + col);
+        for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.f;
+
+    for (int s = 0; s < S; ++s) {
+      uint4 a_hi[2], a_lo[2], b_hi[4], b_lo[4];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        a_hi[r] = lh[r * lstep + s * 64];
+        if (MODE != MERGE_BF16) a_lo[r] = ll[r * lstep + s * 64];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        b_hi[c] = rh[c * lstep + s * 64];
+        if (MODE != MERGE_BF16) b_lo[c] = rl[c * lstep + s * 64];
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (MODE != MERGE_BF16) {
+            acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
+            acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
+          }
+          acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
+        }
+    }
+
+    if (EPI == 0) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const uint64_t col = (uint64_t)(cb0 + c) * 32 + (lane & 31);
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const uint64_t row = (uint64_t)(rb0 + r) * 32 + (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+            __builtin_nontemporal_store(acc[r][c][v] * scale, ob + row * ncols + col);
+          }
+        }
+    } else {
+      __shared__ float slab[4][32 * EPI_LDS_ROW];
+      float* my = slab[wave];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int row = (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
+            my[row * EPI_LDS_ROW + c * 32 + (lane & 31)] = acc[r][c][v];
+          }
+        __syncthreads();
+        // lanes 0..31 cover one 128-float row, lanes 32..63 the next
+        const uint64_t col0 = (uint64_t)cb0 * 32 + 4 * (lane & 31);
+#pragma unroll
+        for (int rr = 0; rr < 32; rr += 2) {
+          const int row = rr + (lane >> 5);
+          f32x4 v = *reinterpret_cast<const f32x4*>(my + row * EPI_LDS_ROW + 4 * (lane & 31));
+          v *= scale;
+          const uint64_t grow = (uint64_t)(rb0 + r) * 32 + row;
+          __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(ob + grow * ncols + col0));
+        }
+        __syncthreads();
       }
     }
+  }
   (void)qy;
 }
 
 template <int MODE>
-int launch_mode(const MergeMfmaArgs& a, hipStream_t s) {
+int launch_mode(const MergeMfmaArgs& a, int epilogue, int grid_cap, hipStream_t s) {
   const int S = a.S;
   // split R (the A side, weights folded in): per batch entry unless shared
   {
@@ -243,11 +286,16 @@ int launch_mode(const MergeMfmaArgs& a, hipStream_t s) {
   }
   const int col_tiles = 1 << (a.qx + 1 - 8);  // 256 real columns per tile
   const int row_tiles = 1 << (a.qy - 7);      // 128 rows per tile
-  dim3 grid((unsigned)(col_tiles * row_tiles), a.batch);
+  const int ntiles = col_tiles * row_tiles;
+  dim3 grid((unsigned)((grid_cap > 0 && grid_cap < ntiles) ? grid_cap : ntiles), a.batch);
   const uint64_t r_bstride = a.r_batch > 1 ? a.r_plane_stride : 0;
   ProfScope prof(PROF_MERGE_GEMM, s);
-  hipLaunchKernelGGL(k_merge_gemm<MODE>, grid, dim3(256), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo, a.l_plane_stride,
-                     r_bstride, a.out, a.out_bstride * 2, a.qx, a.qy, S, col_tiles, row_tiles);
+  if (epilogue == 1)
+    hipLaunchKernelGGL((k_merge_gemm<MODE, 1>), grid, dim3(256), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo, a.l_plane_stride,
+                       r_bstride, a.out, a.out_bstride * 2, a.qx, a.qy, S, col_tiles, row_tiles);
+  else
+    hipLaunchKernelGGL((k_merge_gemm<MODE, 0>), grid, dim3(256), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo, a.l_plane_stride,
+                       r_bstride, a.out, a.out_bstride * 2, a.qx, a.qy, S, col_tiles, row_tiles);
   CCUT_HIP(hipGetLastError());
   return 0;
 }
@@ -256,13 +304,13 @@ int launch_mode(const MergeMfmaArgs& a, hipStream_t s) {
 
 bool merge_mfma_supported(int qx, int qy) { return qx >= 7 && qy >= 7 && qx + 1 - 8 + qy - 7 <= 31; }
 
-int launch_merge_mfma(const MergeMfmaArgs& a, int mode, hipStream_t s) {
+int launch_merge_mfma(const MergeMfmaArgs& a, int mode, int epilogue, int grid_cap, hipStream_t s) {
   if (!merge_mfma_supported(a.qx, a.qy)) return fail(CCUT_EUNSUPPORTED, "MFMA merge needs qx, qy >= 7");
   if (a.batch > 65535 || a.r_batch > 65535) return fail(CCUT_EUNSUPPORTED, "merge batch too large");
   switch (mode) {
-    case MERGE_BF16X3: return launch_mode<MERGE_BF16X3>(a, s);
-    case MERGE_FP16X3: return launch_mode<MERGE_FP16X3>(a, s);
-    case MERGE_BF16: return launch_mode<MERGE_BF16>(a, s);
+    case MERGE_BF16X3: return launch_mode<MERGE_BF16X3>(a, epilogue, grid_cap, s);
+    case MERGE_FP16X3: return launch_mode<MERGE_FP16X3>(a, epilogue, grid_cap, s);
+    case MERGE_BF16: return launch_mode<MERGE_BF16>(a, epilogue, grid_cap, s);
     default: return fail(CCUT_EINVAL, "bad MFMA merge mode %d", mode);
   }
 }

@@ -22,7 +22,9 @@ struct MergeMfmaArgs {
 };
 
 bool merge_mfma_supported(int qx, int qy);
-int launch_merge_mfma(const MergeMfmaArgs& a, int mode, hipStream_t s);
+// epilogue: 0 = direct accumulator stores, 1 = LDS-transposed 16-byte stores
+// grid_cap > 0: persistent grid of at most grid_cap workgroups per batch entry
+int launch_merge_mfma(const MergeMfmaArgs& a, int mode, int epilogue, int grid_cap, hipStream_t s);
 
 // uint4 elements of one L (rows) / R (columns) plane for a stage
 inline uint64_t mfma_l_plane(int qy, int S) { return ((uint64_t)1 << qy) / 32 * S * 64; }

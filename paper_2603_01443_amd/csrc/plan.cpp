@@ -12,7 +12,8 @@
 
 namespace ccut {
 
-int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<KOp>& kops) {
+int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<StageDesc>& stages,
+                std::vector<KOp>& kops) {
   PassDesc d;
   std::memset(&d, 0, sizeof(d));
   d.b = (int32_t)p.group.size();
@@ -29,7 +30,22 @@ int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector
   int f = 0;
   for (int t = 0; t < nq; ++t)
     if (!in[t]) d.fixed[f++] = t;
-  kops.insert(kops.end(), p.kops.begin(), p.kops.end());
+  if (d.b >= STAGE_MIN_B) {
+    // register stages carry their own (stage-level) op ranges
+    std::vector<StageDesc> st;
+    std::vector<KOp> sk;
+    stage_kops(p.kops, d.b, st, sk);
+    const int32_t base = (int32_t)kops.size();
+    for (StageDesc& s : st) s.op_begin += base;
+    d.stage_begin = (int32_t)stages.size();
+    d.stage_count = (int32_t)st.size();
+    d.op_begin = base;
+    d.op_count = (int32_t)sk.size();
+    stages.insert(stages.end(), st.begin(), st.end());
+    kops.insert(kops.end(), sk.begin(), sk.end());
+  } else {
+    kops.insert(kops.end(), p.kops.begin(), p.kops.end());
+  }
   descs.push_back(d);
   return (int)descs.size() - 1;
 }
@@ -255,7 +271,7 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P->segs[a].q > P->segs[b].q; });
     for (int i : order) {
       auto& S = P->segs[i];
-      int pid = append_pass(S.passes[p], S.q, P->pass_descs, P->kops);
+      int pid = append_pass(S.passes[p], S.q, P->pass_descs, P->stage_descs, P->kops);
       int nb = P->pass_descs[pid].n_blocks;
       for (int64_t r = 0; r < ((int64_t)1 << S.c); ++r) {
         SimJob j;

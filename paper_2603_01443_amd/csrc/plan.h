@@ -25,6 +25,7 @@ struct ccut_plan {
   // simulation launches: one per pass index, jobs for every (segment, variant)
   int bmax = ccut::PASS_MAX_B, low_bits = 4;
   std::vector<ccut::PassDesc> pass_descs;
+  std::vector<ccut::StageDesc> stage_descs;
   std::vector<ccut::KOp> kops;
   std::vector<ccut::SimJob> jobs;
   struct Launch { int job_begin, n_jobs, total_wg; };
@@ -32,22 +33,25 @@ struct ccut_plan {
 
   // Packed table image (ops | passes | jobs | weights) and where it sits in the arena.
   std::vector<unsigned char> image;
-  uint64_t img_ops = 0, img_passes = 0, img_jobs = 0, img_weights = 0;
+  uint64_t img_ops = 0, img_passes = 0, img_stages = 0, img_jobs = 0, img_weights = 0;
   uint64_t tables_off = 0;  // arena byte offset of the table region
   uint64_t total_arena = 0; // bytes the caller's arena must hold
 
   ccut::DeviceTables dev;   // plan-owned copy after ccut_plan_prepare (graph capture)
 
   // launch configuration (ccut_plan_set_launch / ccut_autotune)
-  int sim_threads = 256;     // workgroup size of the simulation kernel
+  int sim_threads = 1024;    // workgroup size of the simulation kernel
   int sim_grid_cap = 0;      // 0: one workgroup per block; > 0: persistent grid of this size
   int sim_per_variant = 0;   // 1: one launch per (segment, variant) instead of one per pass index
   int auto_mfma_min_k = -1;  // CCUT_PREC_AUTO threshold on K (-1: library default)
+  int merge_epilogue = 1;    // MFMA merge store path: 0 direct, 1 through LDS
+  int merge_grid_cap = 0;    // MFMA merge: 0 one workgroup per tile, > 0 persistent grid
 };
 
 namespace ccut {
 // Appends a pass to the device tables; returns its PassDesc index.
-int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<KOp>& kops);
+int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<StageDesc>& stages,
+                std::vector<KOp>& kops);
 int gate_matrix(const ccut_gate_t& g, cd m[4]);
 void release_device(DeviceTables& t);
 // Packs the tables into one image with 256-byte aligned sections.

@@ -237,6 +237,83 @@ void localize(const Program& prog, const std::vector<int>& take, const std::vect
 
 }  // namespace
 
+// ------------------------------------------------------------ register stages
+
+namespace {
+
+// Local bits an op acts on non-diagonally (at most one) and diagonally.
+void kop_roles(const KOp& k, int* nd, int* n_nd, int* dg, int* n_dg) {
+  *n_nd = *n_dg = 0;
+  switch (k.type) {
+    case KOP_DENSE: nd[(*n_nd)++] = k.a; break;
+    case KOP_DIAG: dg[(*n_dg)++] = k.a; break;
+    case KOP_CXL: dg[(*n_dg)++] = k.a; nd[(*n_nd)++] = k.b; break;
+    case KOP_CZL: {
+      const uint32_t* t = reinterpret_cast<const uint32_t*>(k.m);
+      uint32_t bits = 0;
+      for (int i = 0; i < k.nterms; ++i) bits |= t[2 * i + 1] | (t[2 * i + 1] << t[2 * i]);
+      for (int j = 0; j < 32; ++j)
+        if ((bits >> j) & 1) dg[(*n_dg)++] = j;
+      break;
+    }
+    default: break;  // KOP_SCALAR: a block-wide phase, commutes with everything
+  }
+}
+
+}  // namespace
+
+void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& stages, std::vector<KOp>& out) {
+  std::vector<int> pending(kops.size());
+  for (size_t i = 0; i < pending.size(); ++i) pending[i] = (int)i;
+  while (!pending.empty()) {
+    std::vector<long> need(b, (long)1 << 40);
+    for (size_t pos = 0; pos < pending.size(); ++pos) {
+      int nd[1], dg[32], n_nd, n_dg;
+      kop_roles(kops[pending[pos]], nd, &n_nd, dg, &n_dg);
+      for (int i = 0; i < n_nd; ++i) need[nd[i]] = std::min(need[nd[i]], (long)pos);
+    }
+    std::vector<int> cand(b);
+    for (int j = 0; j < b; ++j) cand[j] = j;
+    std::stable_sort(cand.begin(), cand.end(), [&](int x, int y) { return need[x] < need[y]; });
+    std::vector<int> reg(cand.begin(), cand.begin() + REG_BITS);
+    std::sort(reg.begin(), reg.end());
+    std::vector<int> pos_of(b, -1);
+    for (int k = 0; k < REG_BITS; ++k) pos_of[reg[k]] = k;
+    std::vector<uint8_t> sk_any(b, 0), sk_nd(b, 0);
+    std::vector<int> take, keep;
+    for (int idx : pending) {
+      int nd[1], dg[32], n_nd, n_dg;
+      kop_roles(kops[idx], nd, &n_nd, dg, &n_dg);
+      bool ok = true;
+      for (int i = 0; i < n_nd; ++i) ok = ok && pos_of[nd[i]] >= 0 && !sk_any[nd[i]];
+      for (int i = 0; i < n_dg; ++i) ok = ok && !sk_nd[dg[i]];
+      if (ok) {
+        take.push_back(idx);
+      } else {
+        keep.push_back(idx);
+        for (int i = 0; i < n_nd; ++i) sk_any[nd[i]] = sk_nd[nd[i]] = 1;
+        for (int i = 0; i < n_dg; ++i) sk_any[dg[i]] = 1;
+      }
+    }
+    StageDesc st;
+    std::memset(&st, 0, sizeof(st));
+    st.op_begin = (int32_t)out.size();
+    for (int k = 0; k < REG_BITS; ++k) st.reg[k] = reg[k];
+    int f = 0;
+    for (int j = 0; j < b; ++j)
+      if (pos_of[j] < 0) st.tfix[f++] = j;
+    for (int idx : take) {
+      KOp k = kops[idx];
+      if (k.type == KOP_DENSE) k.a = pos_of[k.a];
+      if (k.type == KOP_CXL) k.b = pos_of[k.b];
+      out.push_back(k);
+    }
+    st.op_count = (int32_t)take.size();
+    stages.push_back(st);
+    pending.swap(keep);
+  }
+}
+
 int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out) {
   out.clear();
   const int nq = prog.nq;

@@ -23,9 +23,11 @@ namespace ccut {
 namespace {
 
 struct TuneEntry {
-  int threads = 256;
+  int threads = 1024;
   int grid_cap = 0;
   int mfma_min_k = -1;
+  int epilogue = 0;
+  int merge_grid = 0;
 };
 
 std::mutex g_tune_mu;
@@ -84,6 +86,8 @@ void apply_tuned(ccut_plan* P) {
   P->sim_threads = it->second.threads;
   P->sim_grid_cap = it->second.grid_cap;
   P->auto_mfma_min_k = it->second.mfma_min_k;
+  P->merge_epilogue = it->second.epilogue;
+  P->merge_grid_cap = it->second.merge_grid;
 }
 
 }  // namespace ccut
@@ -100,6 +104,15 @@ extern "C" int ccut_plan_set_launch(ccut_plan_t* plan, int32_t threads, int32_t 
   plan->sim_grid_cap = grid_cap;
   plan->sim_per_variant = per_variant ? 1 : 0;
   plan->auto_mfma_min_k = mfma_min_terms;
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap) {
+  clear_error();
+  if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
+  if ((epilogue != 0 && epilogue != 1) || grid_cap < 0) return fail(CCUT_EINVAL, "bad merge configuration");
+  plan->merge_epilogue = epilogue;
+  plan->merge_grid_cap = grid_cap;
   return CCUT_OK;
 }
 
@@ -143,14 +156,26 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   plan->sim_threads = bt;
   plan->sim_grid_cap = bg;
   // merge: float32 vector kernel against the split-bfloat16 MFMA kernel at this plan's term counts
-  float t32 = 0.f, tmf = 0.f;
+  float t32 = 0.f, tmf = 1e30f;
   int rc = time_call(s, reps, &t32, [&]() {
     return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_FP32, stream);
   });
-  if (!rc)
-    rc = time_call(s, reps, &tmf, [&]() {
-      return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_BF16X3, stream);
-    });
+  int best_epi = plan->merge_epilogue, best_grid = plan->merge_grid_cap;
+  const int grids[4] = {0, 512, 1024, 2048};
+  for (int epi = 0; epi < 2 && !rc; ++epi) {
+    for (int gc : grids) {
+      plan->merge_epilogue = epi;
+      plan->merge_grid_cap = gc;
+      float t = 0.f;
+      rc = time_call(s, reps, &t, [&]() {
+        return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_BF16X3, stream);
+      });
+      if (rc) break;
+      if (t < tmf) { tmf = t; best_epi = epi; best_grid = gc; }
+    }
+  }
+  plan->merge_epilogue = best_epi;
+  plan->merge_grid_cap = best_grid;
   plan->sim_per_variant = saved_pv;
   if (rc) return rc;
   int kmax = 1;
@@ -158,7 +183,7 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   plan->auto_mfma_min_k = tmf < t32 ? 1 : kmax + 1;
   if (best_ms) *best_ms = best + std::min(t32, tmf);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[arch_name() + "|" + signature(plan)] = TuneEntry{bt, bg, plan->auto_mfma_min_k};
+  g_tune[arch_name() + "|" + signature(plan)] = TuneEntry{bt, bg, plan->auto_mfma_min_k, best_epi, best_grid};
   return CCUT_OK;
 }
 
@@ -168,9 +193,10 @@ extern "C" int ccut_autotune_save(const char* path) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(CCUT_EINVAL, "cannot write %s", path);
-  std::fprintf(f, "# ccut autotune cache: key threads grid_cap mfma_min_k\n");
+  std::fprintf(f, "# ccut autotune cache: key threads grid_cap mfma_min_k epilogue merge_grid\n");
   for (const auto& kv : g_tune)
-    std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.threads, kv.second.grid_cap, kv.second.mfma_min_k);
+    std::fprintf(f, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.threads, kv.second.grid_cap,
+                 kv.second.mfma_min_k, kv.second.epilogue, kv.second.merge_grid);
   std::fclose(f);
   return CCUT_OK;
 }
@@ -181,14 +207,14 @@ extern "C" int ccut_autotune_load(const char* path) {
   FILE* f = std::fopen(path, "r");
   if (!f) return fail(CCUT_EINVAL, "cannot read %s", path);
   char key[1024];
-  int t, c, k;
+  int t, c, k, ep, mg;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   char line[1200];
   while (std::fgets(line, sizeof(line), f)) {
     if (line[0] == '#') continue;
-    if (std::sscanf(line, "%1023s %d %d %d", key, &t, &c, &k) == 4 && (t == 256 || t == 512 || t == 1024) &&
-        c >= 0 && k >= -1)
-      g_tune[key] = TuneEntry{t, c, k};
+    if (std::sscanf(line, "%1023s %d %d %d %d %d", key, &t, &c, &k, &ep, &mg) == 6 &&
+        (t == 256 || t == 512 || t == 1024) && c >= 0 && k >= -1 && (ep == 0 || ep == 1) && mg >= 0)
+      g_tune[key] = TuneEntry{t, c, k, ep, mg};
   }
   std::fclose(f);
   return CCUT_OK;
