@@ -237,11 +237,13 @@ int ccut_plan_set_launch(ccut_plan_t* plan, int32_t threads, int32_t grid_cap, i
 int ccut_plan_get_launch(const ccut_plan_t* plan, int32_t out[4]);
 
 /*
- * Store path and grid of the MFMA merge GEMM: epilogue 0 stores accumulators
- * directly, 1 transposes 32-row slabs through LDS into 16-byte row stores;
- * grid_cap 0 launches one workgroup per 128 x 256 tile, > 0 a persistent grid
- * of at most grid_cap workgroups that loop over tiles.  Results do not depend
- * on either.  Host-only.  Errors: CCUT_EINVAL.
+ * Variant and grid of the MFMA merge GEMM.  epilogue (0..3): bit 0 set stores
+ * 32-row slabs through an LDS transpose as 16-byte row stores (clear: each
+ * lane stores its accumulators directly); bit 1 set stages each step's MFMA
+ * operands once per workgroup in double-buffered LDS (clear: every wavefront
+ * loads its own fragments).  grid_cap 0 launches one workgroup per 128 x 256
+ * tile, > 0 a persistent grid of at most grid_cap workgroups looping over
+ * tiles.  Results do not depend on either.  Host-only.  Errors: CCUT_EINVAL.
  */
 int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap);
 
@@ -330,14 +332,16 @@ int ccut_mlp_train(float* d_params, const float* d_x, const float* d_t, int64_t 
  *    Eq. (speedup_depth_free) margin is largest and positive, else no cut;
  *    *predicted_s = NaN.  Host-only.
  *  - otherwise: the learned model predicts each candidate's wall clock
- *    (T_pre + T_sub + T_merge, or T_orig) and the smallest wins;
- *    *predicted_s is its prediction.  If budget_s > 0 and even that exceeds
- *    it, *choice = -1 (infeasible).  Synchronises `stream`.
+ *    (T_pre + T_sub + T_merge, or T_orig) and the smallest wins, except that
+ *    the closed-form choice is kept unless the winner is predicted faster than
+ *    it by more than the fraction `margin` (0 <= margin < 1; 0: plain argmin).
+ *    *predicted_s is the chosen candidate's prediction.  If budget_s > 0 and
+ *    it exceeds the budget, *choice = -1 (infeasible).  Synchronises `stream`.
  * *choice: 0 = simulate uncut, n >= 2 = cut into n segments, -1 = infeasible.
  * Errors: CCUT_EINVAL, CCUT_EHIP.
  */
-int ccut_decide(int32_t q, int32_t d, int32_t c_total, const float* d_params, double budget_s, int32_t* choice,
-                double* predicted_s, void* stream);
+int ccut_decide(int32_t q, int32_t d, int32_t c_total, const float* d_params, double budget_s, double margin,
+                int32_t* choice, double* predicted_s, void* stream);
 
 /*
  * Kernel timing.  While enabled, every kernel this library launches is

@@ -98,7 +98,7 @@ def _load():
         "ccut_mlp_predict": [vp, vp, i64, vp, vp],
         "ccut_mlp_grad": [vp, vp, vp, i64, vp, u64, vp, fp, vp],
         "ccut_mlp_train": [vp, vp, vp, i64, i32, ctypes.c_float, vp, u64, fp, vp],
-        "ccut_decide": [i32, i32, i32, vp, ctypes.c_double, ctypes.POINTER(i32), dp, vp],
+        "ccut_decide": [i32, i32, i32, vp, ctypes.c_double, ctypes.c_double, ctypes.POINTER(i32), dp, vp],
     }
     for name, args in more.items():
         fn = getattr(lib, name)
@@ -324,11 +324,12 @@ def mlp_train(params, x, t, rows: int, epochs: int, lr: float, work, work_bytes:
     return losses[:epochs]
 
 
-def decide(q: int, d: int, c_total: int, params=None, budget_s: float = 0.0, stream=None):
+def decide(q: int, d: int, c_total: int, params=None, budget_s: float = 0.0, margin: float = 0.0,
+           stream=None):
     """(choice, predicted seconds): choice 0 = no cut, n >= 2 segments, -1 = over budget."""
     choice = ctypes.c_int32()
     pred = ctypes.c_double()
-    _check(_lib.ccut_decide(q, d, c_total, _ptr(params) if params is not None else None, budget_s,
+    _check(_lib.ccut_decide(q, d, c_total, _ptr(params) if params is not None else None, budget_s, margin,
                             ctypes.byref(choice), ctypes.byref(pred), _stream(stream)))
     return choice.value, pred.value
 

@@ -102,24 +102,31 @@ extern "C" int ccut_mlp_train(float* d_params, const float* d_x, const float* d_
                    static_cast<hipStream_t>(stream));
 }
 
+namespace {
+// Closed-form rule: the n whose Eq. (speedup_depth_free) margin is largest and positive, else 0.
+int closed_form_choice(int q, int c_total) {
+  int best = 0;
+  double best_m = 0.0;
+  for (int n = 2; n <= 4; ++n) {
+    if (n > q) continue;
+    int cb[CCUT_MAX_SEG];
+    split_even(c_total, n, cb);
+    const double m = q * (1.0 - 1.0 / n) - std::log2(n_sub(n, cb) / n);
+    if (m > best_m) { best = n; best_m = m; }
+  }
+  return best;
+}
+}  // namespace
+
 extern "C" int ccut_decide(int32_t q, int32_t d, int32_t c_total, const float* d_params, double budget_s,
-                           int32_t* choice, double* predicted_s, void* stream) {
+                           double margin, int32_t* choice, double* predicted_s, void* stream) {
   clear_error();
-  if (!choice || q < 1 || d < 1 || c_total < 0) return fail(CCUT_EINVAL, "bad argument");
+  if (!choice || q < 1 || d < 1 || c_total < 0 || !(margin >= 0.0 && margin < 1.0))
+    return fail(CCUT_EINVAL, "bad argument");
   const int cands[4] = {1, 2, 3, 4};
+  const int cf = closed_form_choice(q, c_total);
   if (!d_params) {
-    // Closed-form fallback: the n whose Eq. (speedup_depth_free) margin is largest, else no cut.
-    int best = 0;
-    double best_m = 0.0;
-    for (int i = 1; i < 4; ++i) {
-      const int n = cands[i];
-      if (n > q) continue;
-      int cb[CCUT_MAX_SEG];
-      split_even(c_total, n, cb);
-      const double m = q * (1.0 - 1.0 / n) - std::log2(n_sub(n, cb) / n);
-      if (m > best_m) { best = n; best_m = m; }
-    }
-    *choice = best;
+    *choice = cf;
     if (predicted_s) *predicted_s = NAN;
     return CCUT_OK;
   }
@@ -128,7 +135,7 @@ extern "C" int ccut_decide(int32_t q, int32_t d, int32_t c_total, const float* d
   int valid[4];
   for (int i = 0; i < 4; ++i) {
     const int n = cands[i];
-    valid[i] = (n == 1) || (n <= q && c_total >= n - 1);
+    valid[i] = n <= q;
     features(q, d, n, n == 1 ? 0 : c_total, x + 4 * i);
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -145,13 +152,19 @@ extern "C" int ccut_decide(int32_t q, int32_t d, int32_t c_total, const float* d
   CCUT_HIP(hipMemcpyAsync(y, dy, sizeof(y), hipMemcpyDeviceToHost, s));
   CCUT_HIP(hipStreamSynchronize(s));
   int best = -1;
-  double best_t = INFINITY;
+  double best_t = INFINITY, t_cf = INFINITY;
   for (int i = 0; i < 4; ++i) {
     if (!valid[i]) continue;
     const double t = cands[i] == 1 ? std::exp((double)y[3 * i + 1])
                                    : std::exp((double)y[3 * i]) + std::exp((double)y[3 * i + 1]) +
                                          std::exp((double)y[3 * i + 2]);
     if (t < best_t) { best_t = t; best = cands[i]; }
+    if ((cands[i] == 1 ? 0 : cands[i]) == cf) t_cf = t;
+  }
+  // guard: leave the closed-form choice only for a predicted gain of more than `margin`
+  if ((best == 1 ? 0 : best) != cf && best_t > (1.0 - margin) * t_cf) {
+    best = cf == 0 ? 1 : cf;
+    best_t = t_cf;
   }
   *choice = best == 1 ? 0 : best;
   if (budget_s > 0 && best_t > budget_s) *choice = -1;  // nothing fits the budget

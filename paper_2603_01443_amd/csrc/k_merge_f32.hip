@@ -45,8 +45,9 @@ __global__ __launch_bounds__(MT) void k_merge_f32_tiled(MergeArgs a) {
   const int GY = MT / TX;
   const int TY = GY * RB;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int x = blockIdx.y * TX + tx;
-  const int y0 = blockIdx.x * TY;
+  const int ny_tiles = (NY + TY - 1) / TY;  // tiles are flattened into grid.x
+  const int x = (blockIdx.x / ny_tiles) * TX + tx;
+  const int y0 = (blockIdx.x % ny_tiles) * TY;
   const int beta = blockIdx.z;
   const float2* A = a.A + beta * a.a_bstride + x;
   const float2* B = a.B + beta * a.b_bstride + y0;
@@ -119,8 +120,9 @@ int launch_merge_f32(const MergeStage& st, const float* A, const float* B, float
   if (NX >= 64) {
     const uint64_t TX = NX < MT ? NX : MT;
     const uint64_t TY = (MT / TX) * RB;
-    dim3 grid((unsigned)((NY + TY - 1) / TY), (unsigned)(NX / TX), st.batch);
-    if (grid.y > 65535u) return fail(CCUT_EUNSUPPORTED, "merge grid too large");
+    const uint64_t tiles = ((NY + TY - 1) / TY) * (NX / TX);
+    if (tiles > 0x7fffffffu) return fail(CCUT_EUNSUPPORTED, "merge grid too large");
+    dim3 grid((unsigned)tiles, 1, st.batch);
     ProfScope prof(PROF_MERGE_F32, s);
     hipLaunchKernelGGL(k_merge_f32_tiled, grid, dim3(MT), 0, s, a);
   } else {

@@ -152,7 +152,13 @@ __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
 //        16-byte chunks, two 512-byte row segments per instruction.
 constexpr int EPI_LDS_ROW = 128 + 4;  // floats per LDS row (padded)
 
-template <int MODE, int EPI>
+// LDSOP 0: each wavefront loads its own fragments from global memory (L2).
+// LDSOP 1: the workgroup loads each step's fragments once into a double-buffered
+//          LDS region (the next step is fetched while the current one computes).
+constexpr int OPS_U4 = (4 + 8) * 2 * 64;  // uint4 per step: 4 L + 8 R fragments, hi and lo
+constexpr int SMEM_F = (4 * 32 * EPI_LDS_ROW > 2 * OPS_U4 * 4) ? 4 * 32 * EPI_LDS_ROW : 2 * OPS_U4 * 4;
+
+template <int MODE, int EPI, int LDSOP>
 __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lhi, const uint4* __restrict__ Llo,
                                                     const uint4* __restrict__ Rhi, const uint4* __restrict__ Rlo,
                                                     uint64_t l_bstride, uint64_t r_bstride, float* __restrict__ out,
@@ -161,6 +167,7 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
   const int beta = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lstep = (uint64_t)S * 64;  // next 32-row (or column) block
+  __shared__ __align__(16) float smem_f[(EPI == 1 || LDSOP == 1) ? SMEM_F : 4];
   const float scale = MODE == MERGE_FP16X3 ? (1.0f / 268435456.0f) : 1.0f;  // 2^-28
   const uint64_t ncols = (uint64_t)2 << qx;
   float* ob = out + beta * out_bstride;
@@ -198,28 +205,97 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.f;
 
-    for (int s = 0; s < S; ++s) {
-      uint4 a_hi[2], a_lo[2], b_hi[4], b_lo[4];
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        a_hi[r] = lh[r * lstep + s * 64];
-        if (MODE != MERGE_BF16) a_lo[r] = ll[r * lstep + s * 64];
+    if (LDSOP == 0) {
+      for (int s = 0; s < S; ++s) {
+        uint4 a_hi[2], a_lo[2], b_hi[4], b_lo[4];
+  #pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          a_hi[r] = lh[r * lstep + s * 64];
+          if (MODE != MERGE_BF16) a_lo[r] = ll[r * lstep + s * 64];
+        }
+  #pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          b_hi[c] = rh[c * lstep + s * 64];
+          if (MODE != MERGE_BF16) b_lo[c] = rl[c * lstep + s * 64];
+        }
+  #pragma unroll
+        for (int r = 0; r < 2; ++r)
+  #pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (MODE != MERGE_BF16) {
+              acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
+              acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
+            }
+            acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
+          }
       }
+    } else {
+      // cooperative, double-buffered staging of the step's fragments in LDS
+      uint4* ops = reinterpret_cast<uint4*>(smem_f);
+      const int nfr = MODE != MERGE_BF16 ? 24 : 12;  // fragments per step
+      const int tid = threadIdx.x;
+      uint4 pf[6];
+      auto gaddr = [&](int f, int s, int ln) -> const uint4* {
+        const int planes = MODE != MERGE_BF16 ? 2 : 1;
+        if (f < 4 * planes) {
+          const int rbl = f / planes, pl = f % planes;
+          const uint4* base = pl ? Llo : Lhi;
+          return base + beta * l_bstride + (((uint64_t)(trow * 4 + rbl) * S + s) * 64 + ln);
+        }
+        const int g = f - 4 * planes;
+        const int cbl = g / planes, pl = g % planes;
+        const uint4* base = pl ? Rlo : Rhi;
+        return base + beta * r_bstride + (((uint64_t)(tcol * 8 + cbl) * S + s) * 64 + ln);
+      };
+      auto fetch = [&](int s) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        b_hi[c] = rh[c * lstep + s * 64];
-        if (MODE != MERGE_BF16) b_lo[c] = rl[c * lstep + s * 64];
-      }
+        for (int j = 0; j < 6; ++j) {
+          const int i = tid + 256 * j;
+          if (i < nfr * 64) pf[j] = *gaddr(i >> 6, s, i & 63);
+        }
+      };
+      auto stash = [&](int buf) {
 #pragma unroll
-      for (int r = 0; r < 2; ++r)
+        for (int j = 0; j < 6; ++j) {
+          const int i = tid + 256 * j;
+          if (i < nfr * 64) ops[buf * OPS_U4 + i] = pf[j];
+        }
+      };
+      __syncthreads();  // the previous tile's epilogue may still read this LDS
+      fetch(0);
+      stash(0);
+      __syncthreads();
+      const int planes = MODE != MERGE_BF16 ? 2 : 1;
+      for (int s = 0; s < S; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < S) fetch(s + 1);
+        const uint4* ob_ = ops + buf * OPS_U4;
+        uint4 a_hi[2], a_lo[2], b_hi[4], b_lo[4];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int f = ((wave >> 1) * 2 + r) * planes;
+          a_hi[r] = ob_[f * 64 + lane];
+          if (MODE != MERGE_BF16) a_lo[r] = ob_[(f + 1) * 64 + lane];
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          if (MODE != MERGE_BF16) {
-            acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
-            acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
-          }
-          acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
+          const int f = 4 * planes + ((wave & 1) * 4 + c) * planes;
+          b_hi[c] = ob_[f * 64 + lane];
+          if (MODE != MERGE_BF16) b_lo[c] = ob_[(f + 1) * 64 + lane];
         }
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (MODE != MERGE_BF16) {
+              acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
+              acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
+            }
+            acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
+          }
+        if (s + 1 < S) stash(buf ^ 1);
+        __syncthreads();
+      }
     }
 
     if (EPI == 0) {
@@ -235,8 +311,7 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
           }
         }
     } else {
-      __shared__ float slab[4][32 * EPI_LDS_ROW];
-      float* my = slab[wave];
+      float* my = smem_f + wave * 32 * EPI_LDS_ROW;
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
 #pragma unroll
@@ -265,7 +340,7 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
 }
 
 template <int MODE>
-int launch_mode(const MergeMfmaArgs& a, int epilogue, int grid_cap, hipStream_t s) {
+int launch_mode(const MergeMfmaArgs& a, int variant, int grid_cap, hipStream_t s) {
   const int S = a.S;
   // split R (the A side, weights folded in): per batch entry unless shared
   {
@@ -290,12 +365,16 @@ int launch_mode(const MergeMfmaArgs& a, int epilogue, int grid_cap, hipStream_t 
   dim3 grid((unsigned)((grid_cap > 0 && grid_cap < ntiles) ? grid_cap : ntiles), a.batch);
   const uint64_t r_bstride = a.r_batch > 1 ? a.r_plane_stride : 0;
   ProfScope prof(PROF_MERGE_GEMM, s);
-  if (epilogue == 1)
-    hipLaunchKernelGGL((k_merge_gemm<MODE, 1>), grid, dim3(256), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo, a.l_plane_stride,
-                       r_bstride, a.out, a.out_bstride * 2, a.qx, a.qy, S, col_tiles, row_tiles);
-  else
-    hipLaunchKernelGGL((k_merge_gemm<MODE, 0>), grid, dim3(256), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo, a.l_plane_stride,
-                       r_bstride, a.out, a.out_bstride * 2, a.qx, a.qy, S, col_tiles, row_tiles);
+#define CCUT_GEMM(E, L)                                                                                       \
+  hipLaunchKernelGGL((k_merge_gemm<MODE, E, L>), grid, dim3(256), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo, a.l_plane_stride, \
+                     r_bstride, a.out, a.out_bstride * 2, a.qx, a.qy, S, col_tiles, row_tiles)
+  switch (variant & 3) {
+    case 0: CCUT_GEMM(0, 0); break;
+    case 1: CCUT_GEMM(1, 0); break;
+    case 2: CCUT_GEMM(0, 1); break;
+    default: CCUT_GEMM(1, 1); break;
+  }
+#undef CCUT_GEMM
   CCUT_HIP(hipGetLastError());
   return 0;
 }
@@ -304,13 +383,13 @@ int launch_mode(const MergeMfmaArgs& a, int epilogue, int grid_cap, hipStream_t 
 
 bool merge_mfma_supported(int qx, int qy) { return qx >= 7 && qy >= 7 && qx + 1 - 8 + qy - 7 <= 31; }
 
-int launch_merge_mfma(const MergeMfmaArgs& a, int mode, int epilogue, int grid_cap, hipStream_t s) {
+int launch_merge_mfma(const MergeMfmaArgs& a, int mode, int variant, int grid_cap, hipStream_t s) {
   if (!merge_mfma_supported(a.qx, a.qy)) return fail(CCUT_EUNSUPPORTED, "MFMA merge needs qx, qy >= 7");
   if (a.batch > 65535 || a.r_batch > 65535) return fail(CCUT_EUNSUPPORTED, "merge batch too large");
   switch (mode) {
-    case MERGE_BF16X3: return launch_mode<MERGE_BF16X3>(a, epilogue, grid_cap, s);
-    case MERGE_FP16X3: return launch_mode<MERGE_FP16X3>(a, epilogue, grid_cap, s);
-    case MERGE_BF16: return launch_mode<MERGE_BF16>(a, epilogue, grid_cap, s);
+    case MERGE_BF16X3: return launch_mode<MERGE_BF16X3>(a, variant, grid_cap, s);
+    case MERGE_FP16X3: return launch_mode<MERGE_FP16X3>(a, variant, grid_cap, s);
+    case MERGE_BF16: return launch_mode<MERGE_BF16>(a, variant, grid_cap, s);
     default: return fail(CCUT_EINVAL, "bad MFMA merge mode %d", mode);
   }
 }

@@ -22,9 +22,10 @@ struct MergeMfmaArgs {
 };
 
 bool merge_mfma_supported(int qx, int qy);
-// epilogue: 0 = direct accumulator stores, 1 = LDS-transposed 16-byte stores
-// grid_cap > 0: persistent grid of at most grid_cap workgroups per batch entry
-int launch_merge_mfma(const MergeMfmaArgs& a, int mode, int epilogue, int grid_cap, hipStream_t s);
+// variant bit 0: stores through an LDS transpose (else direct accumulator stores);
+// variant bit 1: operands staged in LDS per workgroup (else loaded per wavefront).
+// grid_cap > 0: persistent grid of at most grid_cap workgroups per batch entry.
+int launch_merge_mfma(const MergeMfmaArgs& a, int mode, int variant, int grid_cap, hipStream_t s);
 
 // uint4 elements of one L (rows) / R (columns) plane for a stage
 inline uint64_t mfma_l_plane(int qy, int S) { return ((uint64_t)1 << qy) / 32 * S * 64; }

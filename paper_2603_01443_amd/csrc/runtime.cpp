@@ -110,7 +110,7 @@ extern "C" int ccut_plan_set_launch(ccut_plan_t* plan, int32_t threads, int32_t 
 extern "C" int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap) {
   clear_error();
   if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
-  if ((epilogue != 0 && epilogue != 1) || grid_cap < 0) return fail(CCUT_EINVAL, "bad merge configuration");
+  if (epilogue < 0 || epilogue > 3 || grid_cap < 0) return fail(CCUT_EINVAL, "bad merge configuration");
   plan->merge_epilogue = epilogue;
   plan->merge_grid_cap = grid_cap;
   return CCUT_OK;
@@ -162,7 +162,7 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   });
   int best_epi = plan->merge_epilogue, best_grid = plan->merge_grid_cap;
   const int grids[4] = {0, 512, 1024, 2048};
-  for (int epi = 0; epi < 2 && !rc; ++epi) {
+  for (int epi = 0; epi < 4 && !rc; ++epi) {
     for (int gc : grids) {
       plan->merge_epilogue = epi;
       plan->merge_grid_cap = gc;
@@ -213,7 +213,7 @@ extern "C" int ccut_autotune_load(const char* path) {
   while (std::fgets(line, sizeof(line), f)) {
     if (line[0] == '#') continue;
     if (std::sscanf(line, "%1023s %d %d %d %d %d", key, &t, &c, &k, &ep, &mg) == 6 &&
-        (t == 256 || t == 512 || t == 1024) && c >= 0 && k >= -1 && (ep == 0 || ep == 1) && mg >= 0)
+        (t == 256 || t == 512 || t == 1024) && c >= 0 && k >= -1 && ep >= 0 && ep <= 3 && mg >= 0)
       g_tune[key] = TuneEntry{t, c, k, ep, mg};
   }
   std::fclose(f);

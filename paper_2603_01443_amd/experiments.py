@@ -1,0 +1,461 @@
+"""Measured experiments on one GPU (each writes a JSON file).
+
+    python -m paper_2603_01443_amd.experiments sweep      --out results/threshold_sweep_q24.json
+    python -m paper_2603_01443_amd.experiments precision  --out results/precision_q30.json
+    python -m paper_2603_01443_amd.experiments batching   --out results/batching_q32_n3.json
+    python -m paper_2603_01443_amd.experiments costmodel  --out results/cost_model.json
+    python -m paper_2603_01443_amd.experiments gemm       --out results/merge_gemm_variants.json
+
+sweep      Random brickwork, q = 24 in two blocks of 12, d in {10, 20, 40},
+           c_total in {0, 1, 2, 3, 4, 6} (extended to 12 when cutting still
+           pays): T_pre, T_sub, T_merge and the uncut T_orig on the same GPU,
+           Delta = (T_cut - T_orig) / T_orig (Sec. V.A.3), and the first c_total
+           where Delta >= 0, beside the closed-form threshold c_total < q/2
+           (Eq. threshold_n2).
+precision  q = 30 (15 + 15), d = 20, c_total in {2, 4, 6, 8}: merge time for the
+           float32, split-bfloat16, split-float16 and unsplit-bfloat16 merges,
+           their norm drift and 1 - F against the uncut state; accuracy against
+           the complex128 oracle on a q = 20 (10 + 10) instance of the same
+           generator.
+batching   q = 32 in blocks 10 / 11 / 11, d = 30, 3 + 3 cuts (80 variants): the
+           subcircuit stage as one launch, as per-variant launches, autotuned,
+           and replayed from a HIP graph; the 2^32 state merged once in place.
+costmodel  Timing grid q in {16, ..., 32} x d in {10, 20, 40} x n in {2, 3, 4} x
+           c_total in {0..8} x seeds {0, 1, 2} plus uncut rows; the 4-64-64-3
+           network is trained on the GPU (seeds 0, 1, q < 32) and the learned
+           cut/no-cut choice is compared with the closed-form rule on the held-out
+           rows by measured wall clock.
+
+Timings: host wall clock for T_pre (cut_plan); HIP events on the stream for the
+device stages; warm-up runs first, then the mean of the timed repeats.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import torch  # noqa: E402
+
+from inputs import brickwork, equal_blocks, split_cuts  # noqa: E402
+from paper_2603_01443_amd import ccut  # noqa: E402
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Buffers:
+    """Grow-only device buffers shared by all runs of an experiment."""
+
+    def __init__(self):
+        self.arena = None
+        self.psi = None
+        self.ref = None
+
+    def get(self, name, nbytes):
+        t = getattr(self, name)
+        if t is None or t.numel() < nbytes:
+            setattr(self, name, None)
+            torch.cuda.empty_cache()
+            t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+            setattr(self, name, t)
+        return t
+
+
+def events(n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def time_cut(q, gates, n, sizes, bufs, precision="auto", warm=1, reps=3):
+    """(T_pre, T_sub, T_merge) in seconds, means over reps."""
+    garr = ccut.gate_array(gates)
+    s = torch.cuda.current_stream()
+    pre, sub, mer = [], [], []
+    plan = None
+    for it in range(warm + reps):
+        t0 = time.perf_counter()
+        plan = ccut.cut_plan(q, garr, n, sizes)
+        t1 = time.perf_counter()
+        info = plan.info()
+        arena = bufs.get("arena", info["arena_bytes"])
+        psi = bufs.get("psi", info["psi_bytes"])
+        e = events(3)
+        e[0].record(s)
+        ccut.simulate_subcircuits(plan, arena, arena_bytes=arena.numel(), stream=s)
+        e[1].record(s)
+        ccut.merge_full_state(plan, arena, psi, precision, arena_bytes=arena.numel(),
+                              psi_bytes=psi.numel(), stream=s)
+        e[2].record(s)
+        torch.cuda.synchronize()
+        if it >= warm:
+            pre.append(t1 - t0)
+            sub.append(e[0].elapsed_time(e[1]) * 1e-3)
+            mer.append(e[1].elapsed_time(e[2]) * 1e-3)
+    return float(np.mean(pre)), float(np.mean(sub)), float(np.mean(mer)), plan
+
+
+def time_uncut(q, gates, bufs, warm=1, reps=3, name="ref"):
+    garr = ccut.gate_array(gates)
+    s = torch.cuda.current_stream()
+    out = bufs.get(name, 8 << q)
+    ts = []
+    for it in range(warm + reps):
+        e = events(2)
+        e[0].record(s)
+        ccut.simulate_uncut(q, garr, out, psi_bytes=out.numel(), stream=s)
+        e[1].record(s)
+        torch.cuda.synchronize()
+        if it >= warm:
+            ts.append(e[0].elapsed_time(e[1]) * 1e-3)
+    return float(np.mean(ts))
+
+
+def c64(t, q):
+    return t[: 8 << q].view(torch.complex64)
+
+
+# ------------------------------------------------------------------ sweep
+def run_sweep(args):
+    q, n = 24, 2
+    sizes = equal_blocks(q, n)
+    bufs = Buffers()
+    rows = []
+    for d in (10, 20, 40):
+        t_orig = None
+        cs = [0, 1, 2, 3, 4, 6]
+        i = 0
+        while i < len(cs):
+            c = cs[i]
+            g = brickwork(q, d, n, c, seed=0)
+            if t_orig is None:
+                t_orig = time_uncut(q, g, bufs, reps=args.reps)
+            pre, sub, mer, _ = time_cut(q, g, n, sizes, bufs, reps=args.reps)
+            t_cut = pre + sub + mer
+            rows.append({"q": q, "d": d, "c_total": c, "T_pre": pre, "T_sub": sub, "T_merge": mer,
+                         "T_cut": t_cut, "T_orig": t_orig, "delta": (t_cut - t_orig) / t_orig})
+            log(f"sweep d={d} c={c}: pre {pre*1e3:.3f} sub {sub*1e3:.3f} merge {mer*1e3:.3f} "
+                f"orig {t_orig*1e3:.3f} ms  delta {rows[-1]['delta']:+.3f}")
+            cmax = min(12, d)   # at most one cut per boundary and layer
+            if i == len(cs) - 1 and rows[-1]["delta"] < 0 and c < cmax:
+                cs.append(min(c + 2, cmax))   # extend until cutting stops paying
+            i += 1
+    cross = {}
+    for d in (10, 20, 40):
+        bad = [r["c_total"] for r in rows if r["d"] == d and r["delta"] >= 0]
+        cross[str(d)] = min(bad) if bad else None
+    return {"experiment": "threshold sweep", "rows": rows, "first_c_without_speedup": cross,
+            "closed_form_threshold_c_total_lt": ccut.threshold_ctotal(q, 2)}
+
+
+# ------------------------------------------------------------------ precision
+def run_precision(args):
+    from oracle import cutting, metrics
+    out = {"experiment": "merge precision", "q30": [], "q20_oracle": []}
+    bufs = Buffers()
+    s = torch.cuda.current_stream()
+    precs = ["fp32", "bf16x3", "fp16x3", "bf16"]
+    for c in (2, 4, 6, 8):
+        q, n, d = 30, 2, 20
+        g = brickwork(q, d, n, c, seed=c)
+        time_uncut(q, g, bufs, reps=1)
+        ref = c64(bufs.ref, q)
+        row = {"c_total": c, "K": 2 ** c}
+        for p in precs:
+            pre, sub, mer, plan = time_cut(q, g, n, [15, 15], bufs, precision=p, reps=args.reps)
+            psi = c64(bufs.psi, q)
+            st = ccut.norm_fidelity(psi, ref, q, stream=s)
+            row[p] = {"T_merge": mer, "T_sub": sub, "norm_drift": abs(st["norm2"] - 1.0),
+                      "one_minus_F_vs_uncut": 1.0 - st["fidelity"], "max_abs_vs_uncut": st["max_abs"]}
+            log(f"precision q30 c={c} {p}: merge {mer*1e3:.3f} ms 1-F {1 - st['fidelity']:.2e} "
+                f"drift {abs(st['norm2'] - 1):.2e}")
+        out["q30"].append(row)
+        q, sizes = 20, [10, 10]
+        g = brickwork(q, d, n, c, seed=100 + c)
+        oref = cutting.cut_simulate(q, g, sizes)
+        row = {"c_total": c, "K": 2 ** c}
+        for p in precs:
+            time_cut(q, g, n, sizes, bufs, precision=p, warm=0, reps=1)
+            got = c64(bufs.psi, q).cpu().numpy().astype(np.complex128)
+            row[p] = {"max_abs": metrics.max_abs_error(oref, got), "one_minus_F": metrics.one_minus_fidelity(oref, got),
+                      "norm_drift": abs(metrics.norm2(got) - 1.0)}
+            log(f"precision q20 oracle c={c} {p}: max-abs {row[p]['max_abs']:.2e} 1-F {row[p]['one_minus_F']:.2e}")
+        out["q20_oracle"].append(row)
+    return out
+
+
+# ------------------------------------------------------------------ batching
+def run_batching(args):
+    from oracle import cutting
+    q, n, d, sizes, cb = 32, 3, 30, [10, 11, 11], [3, 3]
+    g = brickwork(q, d, n, 6, seed=0, seg_sizes=sizes, cuts_per_boundary=cb)
+    garr = ccut.gate_array(g)
+    plan = ccut.cut_plan(q, garr, n, sizes)
+    info = plan.info()
+    arena = torch.empty(info["arena_bytes"], dtype=torch.uint8, device="cuda")
+    psi = torch.empty(1 << q, dtype=torch.complex64, device="cuda")
+    s = torch.cuda.Stream()
+    res = {"experiment": "batching", "q": q, "sizes": sizes, "d": d, "cuts": cb, "n_sub": info["n_sub"]}
+
+    def t_sub(reps=5):
+        with torch.cuda.stream(s):
+            ccut.simulate_subcircuits(plan, arena, stream=s)
+            e = events(2)
+            e[0].record(s)
+            for _ in range(reps):
+                ccut.simulate_subcircuits(plan, arena, stream=s)
+            e[1].record(s)
+        torch.cuda.synchronize()
+        return e[0].elapsed_time(e[1]) / reps * 1e-3
+
+    ccut.plan_set_launch(plan, 1024, 0, True)
+    res["T_sub_per_variant_launches"] = t_sub()
+    ccut.plan_set_launch(plan, 1024, 0, False)
+    res["T_sub_one_launch"] = t_sub()
+    ccut.plan_set_launch(plan, 256, 0, False)
+    res["T_sub_one_launch_256"] = t_sub()
+    with torch.cuda.stream(s):
+        res["autotuned_ms"] = ccut.autotune(plan, arena, psi, reps=3, stream=s)
+    res["autotuned_launch"] = ccut.plan_get_launch(plan)
+    res["T_sub_autotuned"] = t_sub()
+    # direct pipeline vs graph replay
+    e = events(4)
+    with torch.cuda.stream(s):
+        ccut.simulate_subcircuits(plan, arena, stream=s)
+        ccut.merge_full_state(plan, arena, psi, "auto", stream=s)
+        e[0].record(s)
+        for _ in range(3):
+            ccut.simulate_subcircuits(plan, arena, stream=s)
+            ccut.merge_full_state(plan, arena, psi, "auto", stream=s)
+        e[1].record(s)
+    torch.cuda.synchronize()
+    direct = psi.clone()
+    graph = ccut.Graph(plan, arena, psi, "auto", stream=s)
+    with torch.cuda.stream(s):
+        graph.launch(s)
+        e[2].record(s)
+        for _ in range(3):
+            graph.launch(s)
+        e[3].record(s)
+    torch.cuda.synchronize()
+    res["T_pipeline_direct"] = e[0].elapsed_time(e[1]) / 3 * 1e-3
+    res["T_pipeline_graph"] = e[2].elapsed_time(e[3]) / 3 * 1e-3
+    res["graph_bit_identical"] = bool(torch.equal(torch.view_as_real(psi), torch.view_as_real(direct)))
+    del direct
+    ccut.profile_reset()
+    ccut.profile_enable(True)
+    with torch.cuda.stream(s):
+        ccut.merge_full_state(plan, arena, psi, "auto", stream=s)
+    torch.cuda.synchronize()
+    ccut.profile_enable(False)
+    res["merge_kernels_ms"] = {k: v[1] / v[0] for k, v in ccut.profile_read().items() if v[0]}
+    res["merge_out_bytes"] = 8 << q
+    ocuts = cutting.find_cuts(q, g, sizes)
+    ost = cutting.variant_states(q, g, sizes, ocuts)
+    rng = np.random.default_rng(0)
+    xs = sorted(set(int(x) for x in rng.integers(0, 1 << q, size=256)))
+    want = cutting.amplitudes(xs, sizes, ocuts, ost)
+    got = psi[torch.tensor(xs, device="cuda")].cpu().numpy().astype(np.complex128)
+    res["oracle_sampled_max_abs"] = float(np.max(np.abs(got - want)))
+    st = ccut.norm_fidelity(psi, None, q)
+    res["norm_drift"] = abs(st["norm2"] - 1.0)
+    graph.free()
+    log(json.dumps(res))
+    return res
+
+
+# ------------------------------------------------------------------ cost model
+def run_costmodel(args):
+    qs = list(range(16, 34, 2)) if not args.quick else [16, 18, 20]
+    ds = (10, 20, 40)
+    ns = (2, 3, 4)
+    cs = range(0, 9)
+    seeds = (0, 1, 2)
+    bufs = Buffers()
+    rows = []
+    t0 = time.time()
+    for q in qs:
+        for d in ds:
+            for seed in seeds:
+                g1 = brickwork(q, d, 2, 0, seed=seed)
+                t_orig = time_uncut(q, g1, bufs, warm=1, reps=2)
+                rows.append({"q": q, "d": d, "n": 1, "c_total": 0, "seed": seed, "T_pre": 0.0, "T_sub": t_orig,
+                             "T_merge": 0.0, "total": t_orig})
+                for n in ns:
+                    for c in cs:
+                        cb = split_cuts(c, n)
+                        g = brickwork(q, d, n, c, seed=seed, cuts_per_boundary=cb)
+                        pre, sub, mer, _ = time_cut(q, g, n, equal_blocks(q, n), bufs, warm=1, reps=2)
+                        rows.append({"q": q, "d": d, "n": n, "c_total": c, "seed": seed, "T_pre": pre,
+                                     "T_sub": sub, "T_merge": mer, "total": pre + sub + mer})
+            log(f"costmodel grid q={q} d={d}: {len(rows)} rows, {time.time() - t0:.0f} s")
+    floor = math.log(1e-6)
+
+    def target(r):
+        if r["n"] == 1:
+            return [floor, math.log(r["T_sub"]), floor]
+        return [math.log(max(r["T_pre"], 1e-6)), math.log(max(r["T_sub"], 1e-6)), math.log(max(r["T_merge"], 1e-6))]
+
+    qmax = max(qs)
+    train = [r for r in rows if r["seed"] != 2 and r["q"] != qmax]
+    test = [r for r in rows if r["seed"] == 2 or r["q"] == qmax]
+    X = np.array([ccut.cost_features(r["q"], r["d"], r["n"], r["c_total"]) for r in train], dtype=np.float32)
+    Y = np.array([target(r) for r in train], dtype=np.float32)
+    from inputs.mlp_init import glorot_params
+    params = torch.tensor(glorot_params(0).astype(np.float32), device="cuda")
+    dx, dy = torch.tensor(X, device="cuda"), torch.tensor(Y, device="cuda")
+    epochs = args.epochs
+    work = torch.empty(ccut.mlp_work_bytes(len(X), epochs), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    tt = time.perf_counter()
+    with torch.cuda.stream(s):
+        losses = ccut.mlp_train(params, dx, dy, len(X), epochs, args.lr, work, stream=s)
+    train_s = time.perf_counter() - tt
+    log(f"costmodel: trained {epochs} epochs on {len(X)} rows in {train_s:.2f} s, loss {losses[0]:.3f} -> {losses[-1]:.4f}")
+
+    # prediction error on held-out rows
+    Xt = np.array([ccut.cost_features(r["q"], r["d"], r["n"], r["c_total"]) for r in test], dtype=np.float32)
+    Yt = np.array([target(r) for r in test], dtype=np.float32)
+    yt = torch.empty(len(Xt), 3, device="cuda")
+    ccut.mlp_predict(params, torch.tensor(Xt, device="cuda"), yt, len(Xt))
+    pred = yt.cpu().numpy()
+    err_stage = np.abs(pred - Yt)
+    # decisions on held-out circuits (q, d, c, seed) against measured wall clock
+    by = {}
+    for r in test:
+        by.setdefault((r["q"], r["d"], r["c_total"] if r["n"] > 1 else None, r["seed"]), []).append(r)
+    decisions = []
+    for r in test:
+        if r["n"] != 2:
+            continue
+        key_c = (r["q"], r["d"], r["c_total"], r["seed"])
+        cand = {0: next(x for x in test if x["n"] == 1 and x["q"] == r["q"] and x["d"] == r["d"]
+                        and x["seed"] == r["seed"])["total"]}
+        for n in ns:
+            m = [x for x in test if x["n"] == n and (x["q"], x["d"], x["c_total"], x["seed"]) == key_c]
+            if m:
+                cand[n] = m[0]["total"]
+        learned, pred_s = ccut.decide(r["q"], r["d"], r["c_total"], params, margin=args.margin)
+        closed, _ = ccut.decide(r["q"], r["d"], r["c_total"])
+        best = min(cand, key=cand.get)
+        by_margin = {str(m): ccut.decide(r["q"], r["d"], r["c_total"], params, margin=m)[0]
+                     for m in (0.0, 0.05, 0.1, 0.2, 0.3)}
+        decisions.append({"q": r["q"], "d": r["d"], "c_total": r["c_total"], "seed": r["seed"],
+                          "measured": {str(k): v for k, v in cand.items()}, "best": best,
+                          "learned": learned, "closed_form": closed, "learned_predicted_s": pred_s,
+                          "by_margin": by_margin,
+                          "t_learned": cand.get(learned, float("nan")), "t_closed": cand.get(closed, float("nan")),
+                          "t_best": cand[best]})
+    tl = np.array([x["t_learned"] for x in decisions])
+    tc = np.array([x["t_closed"] for x in decisions])
+    tb = np.array([x["t_best"] for x in decisions])
+    margin_table = {}
+    for m in ("0.0", "0.05", "0.1", "0.2", "0.3"):
+        tm = np.array([x["measured"][str(x["by_margin"][m])] for x in decisions])
+        margin_table[m] = {"total_s": float(tm.sum()), "optimal_frac": float(np.mean([x["by_margin"][m] == x["best"]
+                                                                                     for x in decisions])),
+                           "slower_than_closed": int(np.sum(tm > tc)),
+                           "slower_than_closed_by_5pct": int(np.sum(tm > 1.05 * tc)),
+                           "slower_than_closed_by_10pct": int(np.sum(tm > 1.10 * tc)),
+                           "cut_decision_disagrees_with_best": int(np.sum([(x["by_margin"][m] == 0) != (x["best"] == 0)
+                                                                           for x in decisions]))}
+    summary = {
+        "margin_table": margin_table,
+        "held_out_decisions": len(decisions),
+        "learned_optimal_frac": float(np.mean([x["learned"] == x["best"] for x in decisions])),
+        "closed_optimal_frac": float(np.mean([x["closed_form"] == x["best"] for x in decisions])),
+        "learned_total_s": float(tl.sum()), "closed_total_s": float(tc.sum()), "best_total_s": float(tb.sum()),
+        "learned_mean_regret": float(np.mean(tl / tb - 1)), "closed_mean_regret": float(np.mean(tc / tb - 1)),
+        "learned_slower_than_closed_by_more_than_10pct": int(np.sum(tl > 1.10 * tc)),
+        "learned_slower_than_closed_any": int(np.sum(tl > tc)),
+        "stage_abs_log_error_mean": [float(v) for v in err_stage.mean(axis=0)],
+        "train_rows": len(train), "test_rows": len(test), "epochs": epochs, "train_seconds": train_s,
+        "final_loss": float(losses[-1]),
+    }
+    # budget illustration (scaled: everything here finishes in far less than 10 minutes)
+    budget = args.budget_ms * 1e-3
+    feas = {}
+    for d in ds:
+        unc = [r["q"] for r in rows if r["n"] == 1 and r["d"] == d and r["total"] <= budget]
+        cut = [r["q"] for r in rows if r["n"] == 2 and r["c_total"] == 6 and r["d"] == d and r["total"] <= budget]
+        feas[str(d)] = {"uncut_max_q": max(unc) if unc else None, "cut_n2_c6_max_q": max(cut) if cut else None}
+    summary["budget_s"] = budget
+    summary["max_feasible_q"] = feas
+    log(json.dumps(summary))
+    return {"experiment": "cost model", "summary": summary, "loss_curve": [float(v) for v in losses[:: max(1, epochs // 100)]],
+            "decisions": decisions, "rows": rows,
+            "params": params.cpu().numpy().tolist()}
+
+
+# ------------------------------------------------------------------ merge GEMM variants
+def run_gemm(args):
+    """Merge GEMM per precision x variant x grid at q=28 (K=64) and q=30 (K=256)."""
+    out = {"experiment": "merge gemm variants", "rows": []}
+    for q, c in ((28, 6), (30, 8)):
+        n = 2
+        g = ccut.gate_array(brickwork(q, 20, n, c, 0))
+        plan = ccut.cut_plan(q, g, n)
+        info = plan.info()
+        arena = torch.empty(info["arena_bytes"], dtype=torch.uint8, device="cuda")
+        psi = torch.empty(1 << q, dtype=torch.complex64, device="cuda")
+        s = torch.cuda.current_stream()
+        ccut.simulate_subcircuits(plan, arena, stream=s)
+        alg = 8 * (1 << q) + 8 * (2 ** c) * 2 * (1 << (q // 2))
+        ccut.profile_enable(True)
+        for prec in ("bf16x3", "fp16x3", "bf16"):
+            for v in range(4):
+                for gc in (0, 1024):
+                    ccut.plan_set_merge(plan, v, gc)
+                    ccut.merge_full_state(plan, arena, psi, prec, stream=s)
+                    torch.cuda.synchronize()
+                    ccut.profile_reset()
+                    for _ in range(args.reps):
+                        ccut.merge_full_state(plan, arena, psi, prec, stream=s)
+                    torch.cuda.synchronize()
+                    k = ccut.profile_read()["merge_gemm"]
+                    ms = k[1] / k[0]
+                    row = {"q": q, "K": 2 ** c, "precision": prec, "variant": v, "grid_cap": gc, "gemm_ms": ms,
+                           "algorithmic_GBs": alg / (ms * 1e-3) / 1e9}
+                    out["rows"].append(row)
+                    log(f"gemm q{q} K{2 ** c} {prec} v{v} grid{gc}: {ms:.3f} ms {row['algorithmic_GBs']:.0f} GB/s")
+        ccut.profile_enable(False)
+        del arena, psi
+        torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["sweep", "precision", "batching", "costmodel", "gemm"])
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--epochs", type=int, default=3000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--budget-ms", type=float, default=20.0)
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--margin", type=float, default=0.2)
+    args = ap.parse_args()
+    if not torch.cuda.is_available():
+        raise SystemExit("experiments need a GPU")
+    fn = {"sweep": run_sweep, "precision": run_precision, "batching": run_batching, "costmodel": run_costmodel,
+          "gemm": run_gemm}
+    res = fn[args.which](args)
+    res["device"] = torch.cuda.get_device_name(0)
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as f:
+        json.dump(res, f, indent=1)
+    log(f"wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()

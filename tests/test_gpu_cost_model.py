@@ -90,4 +90,9 @@ def test_learned_decision_prefers_cheaper_prediction(ccut):
     assert choice == 0 and abs(pred - 1e-3) < 1e-8
     choice, pred = ccut.decide(24, 20, 4, dev(p), budget_s=1e-4)
     assert choice == -1
-    assert ccut.decide(24, 20, 4)[0] == threshold.closed_form_choice(24, 4)
+    cf = threshold.closed_form_choice(24, 4)
+    assert cf != 0 and ccut.decide(24, 20, 4)[0] == cf
+    # a predicted 3x gain clears a 0.5 guard margin; a 0.7 margin keeps the closed-form choice
+    assert ccut.decide(24, 20, 4, dev(p), margin=0.5)[0] == 0
+    choice, pred = ccut.decide(24, 20, 4, dev(p), margin=0.7)
+    assert choice == cf and abs(pred - 3e-3) < 1e-8

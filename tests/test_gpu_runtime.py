@@ -83,3 +83,23 @@ def test_autotune_keeps_results_and_caches(lib, tmp_path):
     ccut.autotune_load(path)
     fresh = ccut.cut_plan(q, g, n)                 # same shape: starts from the cached entry
     assert ccut.plan_get_launch(fresh) == {**cfg, "per_variant": 0}
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "bf16"])
+def test_merge_gemm_variants_bit_identical(lib, prec):
+    """Store path (direct / LDS transpose), operand staging (per wavefront / LDS) and persistent
+    grids change only data movement: every variant writes the same bits."""
+    ccut, pipeline = lib
+    q, n = 22, 2
+    g = brickwork(q, 6, n, 6, seed=12)
+    run = pipeline.CutRun(q, g, n)
+    run.simulate_subcircuits()
+    ref = None
+    for variant in range(4):
+        for cap in (0, 37, 512):
+            ccut.plan_set_merge(run.plan, variant, cap)
+            run.psi.zero_()
+            out = run.merge(prec).clone()
+            if ref is None:
+                ref = out
+            assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref)), (variant, cap)
