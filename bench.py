@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the merge GEMM from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by
 # a 1 GiB copy (2.0 x FETCH + 1.0 x WRITE); see profiles/.  Only valid for the kernel revision
 # it was measured on: set to None whenever that kernel changes.
-MEASURED_TRAFFIC = {"merge_gemm (bf16x3)": 2.232e9}
+MEASURED_TRAFFIC = {"merge_gemm (fp16x2, v3)": 2.223e9}
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
 
@@ -187,7 +187,7 @@ def main():
     merge_ms = float(np.mean(t_merge))
     merge_bytes = 8 * (1 << Q) + 8 * K * ((1 << sizes[0]) + (1 << sizes[1]))
     merge_flops = 8 * K * (1 << Q)
-    used = prec if prec != "auto" else ("bf16x3" if K >= 8 else "fp32")
+    used = prec if prec != "auto" else ("fp16x2" if K >= 8 else "fp32")
     kernels_ms = {k: v[1] / v[0] for k, v in kprof.items() if v[0] > 0}
     kernel_launches = {k: v[0] // args.steps for k, v in kprof.items() if v[0] > 0}
     if used == "fp32":
@@ -205,7 +205,7 @@ def main():
         roof = {"bound": "hbm", "achieved": merge_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = f"{kname} ({used})"
+    roof["kernel"] = f"{kname} ({used}, v{ccut.plan_get_merge(plan0)['variant']})"
     roof["traffic"] = MEASURED_TRAFFIC.get(roof["kernel"])
     roof["avg_ms"] = k_ms
     roof["algorithmic_bytes"] = merge_bytes

@@ -174,11 +174,13 @@ int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint64_t arena_b
 
 /* Merge precisions (Algorithm 3 arithmetic). */
 enum {
-  CCUT_PREC_AUTO = -1,   /* pick by term count: FP32 for few terms, BF16X3 above the ridge */
+  CCUT_PREC_AUTO = -1,   /* by term count: FP32 below K = 8 (or the autotuned threshold), else FP16X2 */
   CCUT_PREC_FP32 = 0,    /* complex64 factors, float32 FMA accumulation (vector ALUs) */
   CCUT_PREC_BF16X3 = 1,  /* factors split hi + lo in bfloat16, hi.hi + hi.lo + lo.hi on MFMA, float32 accumulate */
   CCUT_PREC_FP16X3 = 2,  /* as BF16X3 with float16 halves and power-of-two pre-scaling */
-  CCUT_PREC_BF16 = 3     /* unsplit bfloat16 on MFMA: a low-accuracy control */
+  CCUT_PREC_BF16 = 3,    /* unsplit bfloat16 on MFMA: a low-accuracy control */
+  CCUT_PREC_FP16X2 = 4   /* float16, only the high-qubit factor split: Lhi.R + Llo.R (R rounded once);
+                            relative error of R <= 2^-11, 1 - F ~ 1e-7 */
 };
 
 /*
@@ -227,8 +229,8 @@ int ccut_norm_fidelity(const void* d_psi, const void* d_ref, int32_t q, double o
  *                at most grid_cap workgroups looping over all blocks of all variants
  *   per_variant  0: one launch covers every variant of every segment (per pass);
  *                1: one launch per (segment, variant), the unbatched reference
- *   mfma_min_terms  CCUT_PREC_AUTO merges on MFMA from this term count K
- *                (-1: library default 8)
+ *   mfma_min_terms  CCUT_PREC_AUTO merges on MFMA (FP16X2) from this term
+ *                count K (-1: library default 8)
  * Results do not depend on the configuration.  ccut_plan_get_launch returns
  * (threads, grid_cap, per_variant, mfma_min_terms).  Host-only.
  */
@@ -237,15 +239,26 @@ int ccut_plan_set_launch(ccut_plan_t* plan, int32_t threads, int32_t grid_cap, i
 int ccut_plan_get_launch(const ccut_plan_t* plan, int32_t out[4]);
 
 /*
- * Variant and grid of the MFMA merge GEMM.  epilogue (0..3): bit 0 set stores
- * 32-row slabs through an LDS transpose as 16-byte row stores (clear: each
- * lane stores its accumulators directly); bit 1 set stages each step's MFMA
- * operands once per workgroup in double-buffered LDS (clear: every wavefront
- * loads its own fragments).  grid_cap 0 launches one workgroup per 128 x 256
- * tile, > 0 a persistent grid of at most grid_cap workgroups looping over
- * tiles.  Results do not depend on either.  Host-only.  Errors: CCUT_EINVAL.
+ * Shape of a plan's compiled simulation programs (host-only): out[0] pass
+ * descriptors, [1] register stages, [2] device ops, [3] dense ops (2x2 and
+ * CX), [4] diagonal ops, [5] fused register-level ops of all segments,
+ * [6] simulation launches, [7] (segment, variant, pass) jobs.  Counts cover
+ * every segment once (variants share their segment's program).
+ */
+int ccut_plan_stats(const ccut_plan_t* plan, int64_t out[8]);
+
+/*
+ * Variant and grid of the MFMA merge GEMM.  epilogue (0..3): bit 0 set
+ * transposes 16-row slabs through LDS into 16-byte row stores (clear: each
+ * lane stores its accumulators directly); bit 1 set uses 64 x 256 tiles with
+ * 32 rows per wavefront (clear: 128 x 256 tiles, 64 rows per wavefront).
+ * grid_cap 0 launches one workgroup per tile, > 0 a persistent grid of at most
+ * grid_cap workgroups looping over tiles.  Results do not depend on either.
+ * Host-only.  Errors: CCUT_EINVAL.
  */
 int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap);
+/* The current (epilogue, grid_cap) of a plan (host-only). */
+int ccut_plan_get_merge(const ccut_plan_t* plan, int32_t out[2]);
 
 /*
  * Autotuner: times the simulation kernel over workgroup sizes x persistent

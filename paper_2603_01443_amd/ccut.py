@@ -26,9 +26,9 @@ MAX_SEG = 8
 
 OK, EINVAL, EUNCUTTABLE, ENOSPC, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 
-PREC_AUTO, PREC_FP32, PREC_BF16X3, PREC_FP16X3, PREC_BF16 = -1, 0, 1, 2, 3
+PREC_AUTO, PREC_FP32, PREC_BF16X3, PREC_FP16X3, PREC_BF16, PREC_FP16X2 = -1, 0, 1, 2, 3, 4
 PRECISIONS = {"auto": PREC_AUTO, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "fp16x3": PREC_FP16X3,
-              "bf16": PREC_BF16}
+              "bf16": PREC_BF16, "fp16x2": PREC_FP16X2}
 
 GATE_KIND = {
     "H": 0, "X": 1, "Y": 2, "Z": 3, "S": 4, "SDG": 5, "T": 6, "TDG": 7,
@@ -108,6 +108,8 @@ def _load():
         "ccut_plan_set_launch": [vp, i32, i32, i32, i32],
         "ccut_plan_get_launch": [vp, ctypes.POINTER(i32)],
         "ccut_plan_set_merge": [vp, i32, i32],
+        "ccut_plan_get_merge": [vp, ctypes.POINTER(i32)],
+        "ccut_plan_stats": [vp, ctypes.POINTER(i64)],
         "ccut_autotune": [vp, vp, u64, vp, u64, i32, vp, dp],
         "ccut_autotune_save": [ctypes.c_char_p],
         "ccut_autotune_load": [ctypes.c_char_p],
@@ -361,6 +363,19 @@ def plan_set_launch(plan: Plan, threads: int = 256, grid_cap: int = 0, per_varia
 
 def plan_set_merge(plan: Plan, epilogue: int = 0, grid_cap: int = 0) -> None:
     _check(_lib.ccut_plan_set_merge(plan.handle, epilogue, grid_cap))
+
+
+def plan_get_merge(plan: Plan) -> dict:
+    out = (ctypes.c_int32 * 2)()
+    _check(_lib.ccut_plan_get_merge(plan.handle, out))
+    return {"variant": out[0], "grid_cap": out[1]}
+
+
+def plan_stats(plan: Plan) -> dict:
+    out = (ctypes.c_int64 * 8)()
+    _check(_lib.ccut_plan_stats(plan.handle, out))
+    keys = ("passes", "stages", "device_ops", "dense_ops", "diag_ops", "fused_ops", "launches", "jobs")
+    return dict(zip(keys, out[:]))
 
 
 def plan_get_launch(plan: Plan) -> dict:

@@ -270,7 +270,7 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
   if (psi_bytes < plan->psi_bytes)
     return fail(CCUT_ENOSPC, "psi has %llu bytes, needs %llu", (unsigned long long)psi_bytes,
                 (unsigned long long)plan->psi_bytes);
-  if (precision < CCUT_PREC_AUTO || precision > CCUT_PREC_BF16)
+  if (precision < CCUT_PREC_AUTO || precision > CCUT_PREC_FP16X2)
     return fail(CCUT_EINVAL, "unknown precision %d", precision);
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* arena = static_cast<char*>(d_arena);
@@ -290,7 +290,7 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
     int mode = precision;
     if (mode == CCUT_PREC_AUTO) {
       const int kmin = plan->auto_mfma_min_k >= 0 ? plan->auto_mfma_min_k : MFMA_MIN_TERMS;
-      mode = st.K >= kmin ? CCUT_PREC_BF16X3 : CCUT_PREC_FP32;
+      mode = st.K >= kmin ? CCUT_PREC_FP16X2 : CCUT_PREC_FP32;
     }
     if (mode == CCUT_PREC_FP32 || !merge_mfma_supported(st.qx, st.qy)) {
       // shapes below one MFMA tile take the float32 kernel, which is at least as accurate

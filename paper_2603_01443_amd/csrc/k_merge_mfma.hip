@@ -11,7 +11,10 @@
 // hi = round16(v) and lo = round16(v - hi), and C = Lhi.Rhi + Lhi.Rlo + Llo.Rhi
 // with float32 accumulation (the lo.lo term, ~2^-16 relative for bfloat16, is
 // dropped).  For float16 both factors are scaled by 2^14 first so that lo parts
-// stay normal, and the result is scaled back by 2^-28 (exact).
+// stay normal, and the result is scaled back by 2^-28 (exact).  The fp16x2 mode
+// splits only L: C = Lhi.Rhi + Llo.Rhi, R rounded once to float16 (relative
+// error <= 2^-11 per R value, 1 - F ~ 1e-7): two MFMAs and two thirds of the
+// operand loads of the three-product modes.
 //
 // Layout: L and R are stored in MFMA fragment order, so that each wavefront's
 // operand load for one 32x32x16 step is one contiguous 1 KiB:
@@ -44,9 +47,11 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+constexpr bool is_f16(int mode) { return mode == MERGE_FP16X3 || mode == MERGE_FP16X2; }
+
 template <int MODE>
 __device__ __forceinline__ void split_value(float v, uint16_t& hi, uint16_t& lo) {
-  if (MODE == MERGE_FP16X3) {
+  if (is_f16(MODE)) {
     const float s = v * 16384.0f;  // 2^14
     const _Float16 h = (_Float16)s;
     const _Float16 l = (_Float16)(s - (float)h);
@@ -137,7 +142,7 @@ __global__ __launch_bounds__(256) void k_split_L(const float2* __restrict__ B, u
 // ------------------------------------------------------------- GEMM kernel
 template <int MODE>
 __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
-  if (MODE == MERGE_FP16X3) {
+  if (is_f16(MODE)) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
                                                  0, 0, 0);
   } else {
@@ -152,30 +157,28 @@ __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
 //        16-byte chunks, two 512-byte row segments per instruction.
 constexpr int EPI_LDS_ROW = 128 + 4;  // floats per LDS row (padded)
 
-// LDSOP 0: each wavefront loads its own fragments from global memory (L2).
-// LDSOP 1: the workgroup loads each step's fragments once into a double-buffered
-//          LDS region (the next step is fetched while the current one computes).
-constexpr int OPS_U4 = (4 + 8) * 2 * 64;  // uint4 per step: 4 L + 8 R fragments, hi and lo
-constexpr int SMEM_F = (4 * 32 * EPI_LDS_ROW > 2 * OPS_U4 * 4) ? 4 * 32 * EPI_LDS_ROW : 2 * OPS_U4 * 4;
-
-template <int MODE, int EPI, int LDSOP>
+template <int MODE, int EPI, int RBW>
 __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lhi, const uint4* __restrict__ Llo,
                                                     const uint4* __restrict__ Rhi, const uint4* __restrict__ Rlo,
                                                     uint64_t l_bstride, uint64_t r_bstride, float* __restrict__ out,
                                                     uint64_t out_bstride, int qx, int qy, int S, int col_tiles,
                                                     int row_tiles) {
+  // RBW: 32-row blocks per wavefront (2: 64 x 128 per wavefront, 128 x 256 per
+  // workgroup; 1: 32 x 128 and 64 x 256, half the accumulators so that more
+  // workgroups share a CU and one's stores drain while another computes).
   const int beta = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lstep = (uint64_t)S * 64;  // next 32-row (or column) block
-  __shared__ __align__(16) float smem_f[(EPI == 1 || LDSOP == 1) ? SMEM_F : 4];
-  const float scale = MODE == MERGE_FP16X3 ? (1.0f / 268435456.0f) : 1.0f;  // 2^-28
+  __shared__ __align__(16) float smem_f[EPI == 1 ? 4 * 16 * EPI_LDS_ROW : 4];
+  constexpr bool L_SPLIT = MODE != MERGE_BF16;
+  constexpr bool R_SPLIT = MODE == MERGE_BF16X3 || MODE == MERGE_FP16X3;
+  const float scale = is_f16(MODE) ? (1.0f / 268435456.0f) : 1.0f;  // 2^-28
   const uint64_t ncols = (uint64_t)2 << qx;
   float* ob = out + beta * out_bstride;
   const int ntiles = col_tiles * row_tiles;
-  // Persistent tile loop.  Workgroup b runs on XCD b % 8; with whole XCD bands the
-  // workgroups of one XCD sweep the tiles of one column band, so the band's R
-  // fragments stay in that XCD's L2.  The stores of a tile drain while the next
-  // tile's MFMAs run.
+  // Tile loop (persistent when the grid is capped).  Workgroup b runs on XCD b % 8;
+  // with whole XCD bands the workgroups of one XCD sweep the tiles of one column
+  // band, so the band's R fragments stay in that XCD's L2.
   const bool banded = (col_tiles & 7) == 0 && (gridDim.x & 7) == 0;
   const int band = col_tiles >> 3;
   const int step = banded ? (int)(gridDim.x >> 3) : (int)gridDim.x;
@@ -190,117 +193,46 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
       trow = i / col_tiles;
       tcol = i % col_tiles;
     }
-    const int rb0 = trow * 4 + (wave >> 1) * 2;  // 32-row blocks of this wave
-    const int cb0 = tcol * 8 + (wave & 1) * 4;   // 32-column blocks of this wave
+    const int rb0 = trow * (2 * RBW) + (wave >> 1) * RBW;  // 32-row blocks of this wave
+    const int cb0 = tcol * 8 + (wave & 1) * 4;             // 32-column blocks of this wave
     const uint4* lh = Lhi + beta * l_bstride + ((uint64_t)rb0 * S) * 64 + lane;
     const uint4* ll = Llo + beta * l_bstride + ((uint64_t)rb0 * S) * 64 + lane;
     const uint4* rh = Rhi + beta * r_bstride + ((uint64_t)cb0 * S) * 64 + lane;
     const uint4* rl = Rlo + beta * r_bstride + ((uint64_t)cb0 * S) * 64 + lane;
 
-    f32x16 acc[2][4];
+    f32x16 acc[RBW][4];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < RBW; ++r)
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.f;
 
-    if (LDSOP == 0) {
-      for (int s = 0; s < S; ++s) {
-        uint4 a_hi[2], a_lo[2], b_hi[4], b_lo[4];
-  #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          a_hi[r] = lh[r * lstep + s * 64];
-          if (MODE != MERGE_BF16) a_lo[r] = ll[r * lstep + s * 64];
-        }
-  #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          b_hi[c] = rh[c * lstep + s * 64];
-          if (MODE != MERGE_BF16) b_lo[c] = rl[c * lstep + s * 64];
-        }
-  #pragma unroll
-        for (int r = 0; r < 2; ++r)
-  #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            if (MODE != MERGE_BF16) {
-              acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
-              acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
-            }
-            acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
-          }
+    for (int s = 0; s < S; ++s) {
+      uint4 a_hi[RBW], a_lo[RBW], b_hi[4], b_lo[4];
+#pragma unroll
+      for (int r = 0; r < RBW; ++r) {
+        a_hi[r] = lh[r * lstep + s * 64];
+        if (L_SPLIT) a_lo[r] = ll[r * lstep + s * 64];
       }
-    } else {
-      // cooperative, double-buffered staging of the step's fragments in LDS
-      uint4* ops = reinterpret_cast<uint4*>(smem_f);
-      const int nfr = MODE != MERGE_BF16 ? 24 : 12;  // fragments per step
-      const int tid = threadIdx.x;
-      uint4 pf[6];
-      auto gaddr = [&](int f, int s, int ln) -> const uint4* {
-        const int planes = MODE != MERGE_BF16 ? 2 : 1;
-        if (f < 4 * planes) {
-          const int rbl = f / planes, pl = f % planes;
-          const uint4* base = pl ? Llo : Lhi;
-          return base + beta * l_bstride + (((uint64_t)(trow * 4 + rbl) * S + s) * 64 + ln);
-        }
-        const int g = f - 4 * planes;
-        const int cbl = g / planes, pl = g % planes;
-        const uint4* base = pl ? Rlo : Rhi;
-        return base + beta * r_bstride + (((uint64_t)(tcol * 8 + cbl) * S + s) * 64 + ln);
-      };
-      auto fetch = [&](int s) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          const int i = tid + 256 * j;
-          if (i < nfr * 64) pf[j] = *gaddr(i >> 6, s, i & 63);
-        }
-      };
-      auto stash = [&](int buf) {
+      for (int c = 0; c < 4; ++c) {
+        b_hi[c] = rh[c * lstep + s * 64];
+        if (R_SPLIT) b_lo[c] = rl[c * lstep + s * 64];
+      }
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          const int i = tid + 256 * j;
-          if (i < nfr * 64) ops[buf * OPS_U4 + i] = pf[j];
-        }
-      };
-      __syncthreads();  // the previous tile's epilogue may still read this LDS
-      fetch(0);
-      stash(0);
-      __syncthreads();
-      const int planes = MODE != MERGE_BF16 ? 2 : 1;
-      for (int s = 0; s < S; ++s) {
-        const int buf = s & 1;
-        if (s + 1 < S) fetch(s + 1);
-        const uint4* ob_ = ops + buf * OPS_U4;
-        uint4 a_hi[2], a_lo[2], b_hi[4], b_lo[4];
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          const int f = ((wave >> 1) * 2 + r) * planes;
-          a_hi[r] = ob_[f * 64 + lane];
-          if (MODE != MERGE_BF16) a_lo[r] = ob_[(f + 1) * 64 + lane];
-        }
+      for (int r = 0; r < RBW; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const int f = 4 * planes + ((wave & 1) * 4 + c) * planes;
-          b_hi[c] = ob_[f * 64 + lane];
-          if (MODE != MERGE_BF16) b_lo[c] = ob_[(f + 1) * 64 + lane];
+          if (L_SPLIT) acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
+          if (R_SPLIT) acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
+          acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
         }
-#pragma unroll
-        for (int r = 0; r < 2; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            if (MODE != MERGE_BF16) {
-              acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
-              acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
-            }
-            acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
-          }
-        if (s + 1 < S) stash(buf ^ 1);
-        __syncthreads();
-      }
     }
 
     if (EPI == 0) {
 #pragma unroll
-      for (int r = 0; r < 2; ++r)
+      for (int r = 0; r < RBW; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const uint64_t col = (uint64_t)(cb0 + c) * 32 + (lane & 31);
@@ -311,28 +243,32 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
           }
         }
     } else {
-      float* my = smem_f + wave * 32 * EPI_LDS_ROW;
+      // 16-row half slabs per wavefront: accumulator registers v < 8 hold rows 0..15
+      float* my = smem_f + wave * 16 * EPI_LDS_ROW;
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
+      for (int r = 0; r < RBW; ++r) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int h = 0; h < 2; ++h) {
 #pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            const int row = (v & 3) + 4 * (lane >> 5) + 8 * (v >> 2);
-            my[row * EPI_LDS_ROW + c * 32 + (lane & 31)] = acc[r][c][v];
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int v = 8 * h; v < 8 * h + 8; ++v) {
+              const int row = (v & 3) + 4 * (lane >> 5) + 8 * ((v >> 2) & 1);
+              my[row * EPI_LDS_ROW + c * 32 + (lane & 31)] = acc[r][c][v];
+            }
+          __syncthreads();
+          // lanes 0..31 cover one 128-float row, lanes 32..63 the next
+          const uint64_t col0 = (uint64_t)cb0 * 32 + 4 * (lane & 31);
+#pragma unroll
+          for (int rr = 0; rr < 16; rr += 2) {
+            const int row = rr + (lane >> 5);
+            f32x4 v = *reinterpret_cast<const f32x4*>(my + row * EPI_LDS_ROW + 4 * (lane & 31));
+            v *= scale;
+            const uint64_t grow = (uint64_t)(rb0 + r) * 32 + 16 * h + row;
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(ob + grow * ncols + col0));
           }
-        __syncthreads();
-        // lanes 0..31 cover one 128-float row, lanes 32..63 the next
-        const uint64_t col0 = (uint64_t)cb0 * 32 + 4 * (lane & 31);
-#pragma unroll
-        for (int rr = 0; rr < 32; rr += 2) {
-          const int row = rr + (lane >> 5);
-          f32x4 v = *reinterpret_cast<const f32x4*>(my + row * EPI_LDS_ROW + 4 * (lane & 31));
-          v *= scale;
-          const uint64_t grow = (uint64_t)(rb0 + r) * 32 + row;
-          __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(ob + grow * ncols + col0));
+          __syncthreads();
         }
-        __syncthreads();
       }
     }
   }
@@ -359,18 +295,18 @@ int launch_mode(const MergeMfmaArgs& a, int variant, int grid_cap, hipStream_t s
                        a.Llo, a.l_plane_stride);
     CCUT_HIP(hipGetLastError());
   }
-  const int col_tiles = 1 << (a.qx + 1 - 8);  // 256 real columns per tile
-  const int row_tiles = 1 << (a.qy - 7);      // 128 rows per tile
+  const int col_tiles = 1 << (a.qx + 1 - 8);                      // 256 real columns per tile
+  const int row_tiles = 1 << (a.qy - ((variant & 2) ? 6 : 7));    // 64 or 128 rows per tile
   const int ntiles = col_tiles * row_tiles;
   dim3 grid((unsigned)((grid_cap > 0 && grid_cap < ntiles) ? grid_cap : ntiles), a.batch);
   const uint64_t r_bstride = a.r_batch > 1 ? a.r_plane_stride : 0;
   ProfScope prof(PROF_MERGE_GEMM, s);
-#define CCUT_GEMM(E, L)                                                                                       \
-  hipLaunchKernelGGL((k_merge_gemm<MODE, E, L>), grid, dim3(256), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo, a.l_plane_stride, \
+#define CCUT_GEMM(E, R)                                                                                         \
+  hipLaunchKernelGGL((k_merge_gemm<MODE, E, R>), grid, dim3(256), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo, a.l_plane_stride, \
                      r_bstride, a.out, a.out_bstride * 2, a.qx, a.qy, S, col_tiles, row_tiles)
   switch (variant & 3) {
-    case 0: CCUT_GEMM(0, 0); break;
-    case 1: CCUT_GEMM(1, 0); break;
+    case 0: CCUT_GEMM(0, 2); break;
+    case 1: CCUT_GEMM(1, 2); break;
     case 2: CCUT_GEMM(0, 1); break;
     default: CCUT_GEMM(1, 1); break;
   }
@@ -390,6 +326,7 @@ int launch_merge_mfma(const MergeMfmaArgs& a, int mode, int variant, int grid_ca
     case MERGE_BF16X3: return launch_mode<MERGE_BF16X3>(a, variant, grid_cap, s);
     case MERGE_FP16X3: return launch_mode<MERGE_FP16X3>(a, variant, grid_cap, s);
     case MERGE_BF16: return launch_mode<MERGE_BF16>(a, variant, grid_cap, s);
+    case MERGE_FP16X2: return launch_mode<MERGE_FP16X2>(a, variant, grid_cap, s);
     default: return fail(CCUT_EINVAL, "bad MFMA merge mode %d", mode);
   }
 }

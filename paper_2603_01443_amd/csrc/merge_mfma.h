@@ -5,7 +5,7 @@
 
 namespace ccut {
 
-enum MergeMfmaMode : int { MERGE_BF16X3 = 1, MERGE_FP16X3 = 2, MERGE_BF16 = 3 };
+enum MergeMfmaMode : int { MERGE_BF16X3 = 1, MERGE_FP16X3 = 2, MERGE_BF16 = 3, MERGE_FP16X2 = 4 };
 
 struct MergeMfmaArgs {
   const float2* A;          // low-qubit factor (K terms of 2^qx), weights applied
@@ -23,7 +23,7 @@ struct MergeMfmaArgs {
 
 bool merge_mfma_supported(int qx, int qy);
 // variant bit 0: stores through an LDS transpose (else direct accumulator stores);
-// variant bit 1: operands staged in LDS per workgroup (else loaded per wavefront).
+// variant bit 1: 64-row tiles, 32 rows per wavefront (else 128-row tiles).
 // grid_cap > 0: persistent grid of at most grid_cap workgroups per batch entry.
 int launch_merge_mfma(const MergeMfmaArgs& a, int mode, int variant, int grid_cap, hipStream_t s);
 

@@ -290,6 +290,11 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
     P->launches.push_back(L);
   }
 
+  // MFMA merge tile: 64-row tiles while operand loads are light (K <= 64), else 128-row
+  int kmax = 1;
+  for (const MergeStage& st : P->stages) kmax = std::max(kmax, st.K);
+  P->merge_epilogue = kmax <= 64 ? 3 : 1;
+
   pack_image(P);
   P->tables_off = align256(P->split_off + P->split_bytes);
   P->total_arena = align256(P->tables_off + P->image.size());

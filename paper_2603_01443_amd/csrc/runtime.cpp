@@ -116,6 +116,35 @@ extern "C" int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t 
   return CCUT_OK;
 }
 
+extern "C" int ccut_plan_stats(const ccut_plan_t* plan, int64_t out[8]) {
+  clear_error();
+  if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
+  int64_t dense = 0, diag = 0;
+  for (const auto& k : plan->kops) {
+    if (k.type == KOP_DENSE || k.type == KOP_CXL) ++dense;
+    else ++diag;
+  }
+  int64_t hops = 0;
+  for (const auto& S : plan->segs) hops += (int64_t)S.prog.ops.size();
+  out[0] = (int64_t)plan->pass_descs.size();
+  out[1] = (int64_t)plan->stage_descs.size();
+  out[2] = (int64_t)plan->kops.size();
+  out[3] = dense;
+  out[4] = diag;
+  out[5] = hops;
+  out[6] = (int64_t)plan->launches.size();
+  out[7] = (int64_t)plan->jobs.size();
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_get_merge(const ccut_plan_t* plan, int32_t out[2]) {
+  clear_error();
+  if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
+  out[0] = plan->merge_epilogue;
+  out[1] = plan->merge_grid_cap;
+  return CCUT_OK;
+}
+
 extern "C" int ccut_plan_get_launch(const ccut_plan_t* plan, int32_t out[4]) {
   clear_error();
   if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
@@ -155,7 +184,8 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   }
   plan->sim_threads = bt;
   plan->sim_grid_cap = bg;
-  // merge: float32 vector kernel against the split-bfloat16 MFMA kernel at this plan's term counts
+  // merge: float32 vector kernel against the split MFMA kernel (the CCUT_PREC_AUTO mode) at this
+  // plan's term counts, over the GEMM variants and grids
   float t32 = 0.f, tmf = 1e30f;
   int rc = time_call(s, reps, &t32, [&]() {
     return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_FP32, stream);
@@ -168,7 +198,7 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
       plan->merge_grid_cap = gc;
       float t = 0.f;
       rc = time_call(s, reps, &t, [&]() {
-        return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_BF16X3, stream);
+        return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_FP16X2, stream);
       });
       if (rc) break;
       if (t < tmf) { tmf = t; best_epi = epi; best_grid = gc; }

@@ -164,7 +164,7 @@ def run_precision(args):
     out = {"experiment": "merge precision", "q30": [], "q20_oracle": []}
     bufs = Buffers()
     s = torch.cuda.current_stream()
-    precs = ["fp32", "bf16x3", "fp16x3", "bf16"]
+    precs = ["fp32", "bf16x3", "fp16x3", "fp16x2", "bf16"]
     for c in (2, 4, 6, 8):
         q, n, d = 30, 2, 20
         g = brickwork(q, d, n, c, seed=c)
@@ -412,7 +412,7 @@ def run_gemm(args):
         ccut.simulate_subcircuits(plan, arena, stream=s)
         alg = 8 * (1 << q) + 8 * (2 ** c) * 2 * (1 << (q // 2))
         ccut.profile_enable(True)
-        for prec in ("bf16x3", "fp16x3", "bf16"):
+        for prec in ("bf16x3", "fp16x3", "fp16x2", "bf16"):
             for v in range(4):
                 for gc in (0, 1024):
                     ccut.plan_set_merge(plan, v, gc)

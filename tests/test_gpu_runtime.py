@@ -85,10 +85,10 @@ def test_autotune_keeps_results_and_caches(lib, tmp_path):
     assert ccut.plan_get_launch(fresh) == {**cfg, "per_variant": 0}
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "bf16"])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "bf16", "fp16x2"])
 def test_merge_gemm_variants_bit_identical(lib, prec):
-    """Store path (direct / LDS transpose), operand staging (per wavefront / LDS) and persistent
-    grids change only data movement: every variant writes the same bits."""
+    """Store path (direct / LDS transpose) and persistent grids change only data movement:
+    every variant writes the same bits."""
     ccut, pipeline = lib
     q, n = 22, 2
     g = brickwork(q, 6, n, 6, seed=12)
