@@ -240,8 +240,9 @@ int ccut_plan_get_launch(const ccut_plan_t* plan, int32_t out[4]);
 
 /*
  * Shape of a plan's compiled simulation programs (host-only): out[0] pass
- * descriptors, [1] register stages, [2] device ops, [3] dense ops (2x2 and
- * CX), [4] diagonal ops, [5] fused register-level ops of all segments,
+ * descriptors, [1] register stages, [2] device op records (a group of 2x2
+ * gates on distinct register positions is one header plus one record per
+ * position), [3] dense ops (2x2 and CX), [4] diagonal ops, [5] fused register-level ops of all segments,
  * [6] simulation launches, [7] (segment, variant, pass) jobs.  Counts cover
  * every segment once (variants share their segment's program).
  */
@@ -261,14 +262,32 @@ int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap);
 int ccut_plan_get_merge(const ccut_plan_t* plan, int32_t out[2]);
 
 /*
- * Autotuner: times the simulation kernel over workgroup sizes x persistent
- * grid sizes, and the merge with the float32 kernel against the split-bfloat16
- * MFMA kernel (median of `reps` runs, HIP events on `stream`), applies the
- * fastest to the plan and records it in a process-wide cache keyed by
- * (architecture, plan shape); later plans of the same shape start from it.
- * Overwrites the arena and d_psi.  *best_ms (nullable) receives the tuned
- * simulation + merge time.  ccut_autotune_save / _load write and read the
- * cache as text (one "key threads grid_cap mfma_min_terms" line per entry).
+ * LDS block size of the subcircuit simulation (Algorithm 2): blocks of 2^bits
+ * amplitudes, bits in (4, 14]; 0 restores the automatic choice (the largest
+ * size whose first launch has a workgroup per compute unit, not below 2^12).
+ * A segment with more qubits than bits is simulated in several passes over
+ * its state in HBM; smaller blocks trade passes for parallelism when there
+ * are fewer variants than compute units.  Reschedules the plan's programs
+ * (host-only) and may enlarge ccut_plan_info().arena_bytes: query it again
+ * before sizing an arena.  Results agree to float32 rounding across sizes.
+ * Errors: CCUT_EINVAL.
+ */
+int ccut_plan_set_block_bits(ccut_plan_t* plan, int32_t bits);
+/* The block bits the plan's simulation tables are built for (host-only). */
+int ccut_plan_get_block_bits(const ccut_plan_t* plan, int32_t* out);
+
+/*
+ * Autotuner: times the simulation kernel over LDS block sizes (whole segment,
+ * 2 and 4 blocks per state; sizes whose tables do not fit arena_bytes are
+ * skipped) x workgroup sizes x persistent grid sizes, and the merge with the
+ * float32 kernel against the split-precision MFMA GEMM over its variants and
+ * grids (median of `reps` runs, HIP events on `stream`), applies the fastest
+ * to the plan and records it in a process-wide cache keyed by (architecture,
+ * plan shape); later plans of the same shape start from it.  Overwrites the
+ * arena and d_psi.  *best_ms (nullable) receives the tuned simulation + merge
+ * time.  ccut_autotune_save / _load write and read the cache as text (one
+ * "key threads grid_cap mfma_min_terms epilogue merge_grid block_bits" line
+ * per entry).
  * Errors: CCUT_EINVAL, CCUT_ENOSPC, CCUT_EHIP.
  */
 int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* d_psi, uint64_t psi_bytes,

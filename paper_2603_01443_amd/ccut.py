@@ -109,6 +109,8 @@ def _load():
         "ccut_plan_get_launch": [vp, ctypes.POINTER(i32)],
         "ccut_plan_set_merge": [vp, i32, i32],
         "ccut_plan_get_merge": [vp, ctypes.POINTER(i32)],
+        "ccut_plan_set_block_bits": [vp, i32],
+        "ccut_plan_get_block_bits": [vp, ctypes.POINTER(i32)],
         "ccut_plan_stats": [vp, ctypes.POINTER(i64)],
         "ccut_autotune": [vp, vp, u64, vp, u64, i32, vp, dp],
         "ccut_autotune_save": [ctypes.c_char_p],
@@ -369,6 +371,17 @@ def plan_get_merge(plan: Plan) -> dict:
     out = (ctypes.c_int32 * 2)()
     _check(_lib.ccut_plan_get_merge(plan.handle, out))
     return {"variant": out[0], "grid_cap": out[1]}
+
+
+def plan_set_block_bits(plan: Plan, bits: int) -> None:
+    """LDS block size of the simulation (2^bits amplitudes; 0 = automatic)."""
+    _check(_lib.ccut_plan_set_block_bits(plan.handle, int(bits)))
+
+
+def plan_get_block_bits(plan: Plan) -> int:
+    out = ctypes.c_int32(0)
+    _check(_lib.ccut_plan_get_block_bits(plan.handle, ctypes.byref(out)))
+    return int(out.value)
 
 
 def plan_stats(plan: Plan) -> dict:

@@ -61,6 +61,11 @@ enum KOpType : int32_t {
   KOP_CZL = 2,     // sign flip where sum_t popcount(i & (i >> shift_t) & mask_t) is odd
   KOP_SCALAR = 3,  // multiply the block by m0 (bit a of the block base is 0) or m3 (it is 1)
   KOP_CXL = 4,     // CX with local control a, local target b
+  KOP_GROUP = 5,   // register stages only: one 2x2 gate per register position (gates on
+                   // distinct qubits commute); the KOP_DENSE records of positions
+                   // 0..REG_BITS-1 follow (identity where the group has no gate), and
+                   // the header repeats their variant slots in b, slot, cond, nterms so
+                   // that one 32-byte read gives every matrix address
 };
 
 constexpr int KOP_MAX_TERMS = 8;
@@ -81,17 +86,21 @@ constexpr int REG_BITS = 4;      // amplitudes held per thread in a register sta
 constexpr int STAGE_MIN_B = 9;   // blocks of at least 2^9 amplitudes run in register stages
 
 // A register stage inside an LDS block: every thread holds the 2^REG_BITS
-// amplitudes spanned by local bits reg[], its other local bits fixed by tfix[]
-// (thread slot bit j -> local bit tfix[j]).  Ops of a stage: KOP_DENSE.a and
-// KOP_CXL.b name register positions (0..REG_BITS-1); every other bit field is a
-// local bit.
+// amplitudes spanned by local bits reg[] (ascending); thread slot t takes the
+// other local bits in order, i.e. t with a zero inserted at each reg[] bit.
+// Amplitude e of a thread sits at local index base | roff[e] and LDS slot
+// pad(base) + proff[e] (the padding is additive over disjoint bits).  Ops of a
+// stage: KOP_DENSE.a and KOP_CXL.b name register positions (0..REG_BITS-1);
+// every other bit field is a local bit.
 struct StageDesc {
   int32_t op_begin;
   int32_t op_count;
   int32_t reg[REG_BITS];
-  int32_t tfix[PASS_MAX_B];
+  int32_t roff[1 << REG_BITS];
+  int32_t proff[1 << REG_BITS];
   int32_t pad[2];
 };
+static_assert(sizeof(StageDesc) == 160, "StageDesc layout");
 
 // One LDS-blocked pass over a state: blocks of 2^b amplitudes spanning the
 // register qubits group[0..b); the other qubits are fixed per block.

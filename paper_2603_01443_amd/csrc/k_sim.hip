@@ -11,9 +11,10 @@
 //
 // Inside the block the ops run in register stages: each thread takes the 16
 // amplitudes spanned by the stage's four register bits, applies every op of
-// the stage in registers (dense 2x2 gates on register bits; diagonal phases,
-// CZ parities and CX controls on any bit through each amplitude's known local
-// index) and puts them back; one barrier per stage.  Blocks smaller than 2^9
+// the stage in registers (dense 2x2 gates on register bits, grouped so that a
+// run of them costs one table read; diagonal phases, CZ parities and CX
+// controls on any bit through each amplitude's known local index) and puts
+// them back; one barrier per stage.  Blocks smaller than 2^9
 // run their ops one at a time.  LDS is padded by one slot per 16 amplitudes
 // so that strided stage accesses spread over the banks.
 //
@@ -66,16 +67,38 @@ __device__ __forceinline__ void cx_reg(float2 (&a)[R], const int (&idx)[R], int 
   }
 }
 
+// Matrix of a 2x2 record for this variant (slot alternative when the record has one).
+__device__ __forceinline__ const float* kop_matrix(const KOp* k, int slot, int variant) {
+  return k->m + ((slot >= 0) ? 8 * ((variant >> slot) & 1) : 0);
+}
+
 // Applies the ops [o0, o1) of a register stage to one thread's amplitudes.
 __device__ __forceinline__ void run_stage_ops(float2 (&a)[R], const int (&idx)[R], const KOp* __restrict__ ops,
                                               int o0, int o1, uint64_t blockbase, int variant) {
-  for (int o = o0; o < o1; ++o) {
+  for (int o = o0; o < o1;) {
     const KOp* k = ops + o;
+    const int type = k->type;
+    if (type == KOP_GROUP) {
+      // one 2x2 gate per register position: every matrix address comes from the
+      // header, the four matrices are fetched together, then straight-line arithmetic
+      const int4 h = *reinterpret_cast<const int4*>(k);
+      const int s3 = k->nterms;
+      const int s2 = k->cond;
+      const float* m0 = kop_matrix(k + 1, h.z, variant);
+      const float* m1 = kop_matrix(k + 2, h.w, variant);
+      const float* m2 = kop_matrix(k + 3, s2, variant);
+      const float* m3 = kop_matrix(k + 4, s3, variant);
+      dense_reg<0>(a, m0);
+      dense_reg<1>(a, m1);
+      dense_reg<2>(a, m2);
+      dense_reg<3>(a, m3);
+      o += 1 + REG_BITS;
+      continue;
+    }
+    ++o;
     const int cond = k->cond;
     if (cond >= 0 && !((blockbase >> cond) & 1)) continue;
-    const int slot = k->slot;
-    const float* m = k->m + ((slot >= 0) ? 8 * ((variant >> slot) & 1) : 0);
-    const int type = k->type;
+    const float* m = kop_matrix(k, k->slot, variant);
     if (type == KOP_DENSE) {
       switch (k->a) {
         case 0: dense_reg<0>(a, m); break;
@@ -223,25 +246,27 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
       run_ops_direct<NT>(sh, nb, ops, P->op_begin, P->op_begin + P->op_count, blockbase, job.variant);
     } else {
       const int active = nb >> REG_BITS;  // thread slots per stage
-      const int tbits = b - REG_BITS;
       for (int si = 0; si < P->stage_count; ++si) {
         const StageDesc* S = stages + P->stage_begin + si;
         for (int tt = tid; tt < active; tt += NT) {
-          int tb = 0;
-          for (int j = 0; j < tbits; ++j) tb |= ((tt >> j) & 1) << S->tfix[j];
+          // insert a zero at each register bit (ascending) to get the thread's base index
+          int tb = tt;
+#pragma unroll
+          for (int k = 0; k < REG_BITS; ++k) {
+            const int r = S->reg[k];
+            tb = ((tb >> r) << (r + 1)) | (tb & ((1 << r) - 1));
+          }
+          const int pb = pad(tb);
           int idx[R];
           float2 a[R];
 #pragma unroll
           for (int e = 0; e < R; ++e) {
-            int i = tb;
-#pragma unroll
-            for (int k = 0; k < REG_BITS; ++k) i |= ((e >> k) & 1) << S->reg[k];
-            idx[e] = i;
-            a[e] = sh[pad(i)];
+            idx[e] = tb | S->roff[e];
+            a[e] = sh[pb + S->proff[e]];
           }
           run_stage_ops(a, idx, ops, S->op_begin, S->op_begin + S->op_count, blockbase, job.variant);
 #pragma unroll
-          for (int e = 0; e < R; ++e) sh[pad(idx[e])] = a[e];
+          for (int e = 0; e < R; ++e) sh[pb + S->proff[e]] = a[e];
         }
         __syncthreads();
       }

@@ -12,6 +12,8 @@
 
 namespace ccut {
 
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
 int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<StageDesc>& stages,
                 std::vector<KOp>& kops) {
   PassDesc d;
@@ -50,13 +52,82 @@ int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector
   return (int)descs.size() - 1;
 }
 
+
+// Largest block size whose first simulation launch still gives every compute
+// unit of the device a workgroup; never below 2^12 amplitudes per block.
+int auto_block_bits(const ccut_plan* P) {
+  int b = PASS_MAX_B;
+  for (; b > AUTO_MIN_BLOCK_BITS; --b) {
+    int64_t wg = 0;
+    for (const auto& S : P->segs) wg += ((int64_t)1 << S.c) << std::max(0, S.q - b);
+    if (wg >= AUTO_TARGET_WG) break;
+  }
+  return b;
+}
+
+// Schedules every segment program into LDS passes of at most 2^bmax amplitudes
+// and rebuilds the simulation launches and the packed table image.  The table
+// region of the arena is reserved at plan creation with room for later
+// rebuilds at other block sizes; a rebuild that outgrows it enlarges the arena.
+int build_sim_tables(ccut_plan* P, bool first) {
+  P->bmax = P->block_bits > 0 ? P->block_bits : auto_block_bits(P);
+  P->pass_descs.clear();
+  P->stage_descs.clear();
+  P->kops.clear();
+  P->jobs.clear();
+  P->launches.clear();
+  for (auto& S : P->segs)
+    if (int rc = schedule_passes(S.prog, P->bmax, P->low_bits, S.passes)) return rc;
+  const int n_seg = P->n_seg;
+  // Simulation launches: pass p of every segment that has one, all variants.
+  size_t max_passes = 0;
+  for (auto& S : P->segs) max_passes = std::max(max_passes, S.passes.size());
+  for (size_t p = 0; p < max_passes; ++p) {
+    ccut_plan::Launch L{(int)P->jobs.size(), 0, 0};
+    // largest states first so a persistent grid drains evenly
+    std::vector<int> order;
+    for (int i = 0; i < n_seg; ++i)
+      if (P->segs[i].passes.size() > p) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P->segs[a].q > P->segs[b].q; });
+    for (int i : order) {
+      auto& S = P->segs[i];
+      int pid = append_pass(S.passes[p], S.q, P->pass_descs, P->stage_descs, P->kops);
+      int nb = P->pass_descs[pid].n_blocks;
+      for (int64_t r = 0; r < ((int64_t)1 << S.c); ++r) {
+        SimJob j;
+        std::memset(&j, 0, sizeof(j));
+        j.state_off = S.arena_off / 8 + ((uint64_t)r << S.q);
+        j.pass_id = pid;
+        j.variant = (int32_t)r;
+        j.wg_begin = L.total_wg;
+        if ((int64_t)L.total_wg + nb > ((int64_t)1 << 31) - 1)
+          return fail(CCUT_EUNSUPPORTED, "simulation launch exceeds 2^31 workgroups");
+        L.total_wg += nb;
+        P->jobs.push_back(j);
+        L.n_jobs++;
+      }
+    }
+    P->launches.push_back(L);
+  }
+
+  pack_image(P);
+  if (P->dev.blob) {  // a captured graph may still read the old copy: keep it until the plan is freed
+    P->retired.push_back(P->dev);
+    P->dev = DeviceTables();
+  }
+  P->tables_off = align256(P->split_off + P->split_bytes);
+  if (first) P->tables_reserve = align256(4 * (uint64_t)P->image.size() + 65536);
+  P->tables_reserve = std::max<uint64_t>(P->tables_reserve, align256(P->image.size()));
+  P->total_arena = align256(P->tables_off + P->tables_reserve);
+  return 0;
+}
+
+
 }  // namespace ccut
 
 using namespace ccut;
 
 namespace {
-
-uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 // Per-cut weight of Eq. (CZ): s_0 = 1/(1+i), s_1 = i/(1+i).
 cd cut_weight(int bit) { return bit ? cd(0.5, 0.5) : cd(0.5, -0.5); }
@@ -190,7 +261,6 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
       }
     }
     S.prog = std::move(pb.prog);
-    if (int rc = schedule_passes(S.prog, P->bmax, P->low_bits, S.passes)) return rc;
   }
 
   // Arena: segment-major, variant-minor, 256-byte aligned bases.
@@ -259,46 +329,13 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
     P->split_bytes = std::max(P->split_bytes, align256(2 * 16 * u4));
   }
 
-  // Simulation launches: pass p of every segment that has one, all variants.
-  size_t max_passes = 0;
-  for (auto& S : P->segs) max_passes = std::max(max_passes, S.passes.size());
-  for (size_t p = 0; p < max_passes; ++p) {
-    ccut_plan::Launch L{(int)P->jobs.size(), 0, 0};
-    // largest states first so a persistent grid drains evenly
-    std::vector<int> order;
-    for (int i = 0; i < n_seg; ++i)
-      if (P->segs[i].passes.size() > p) order.push_back(i);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P->segs[a].q > P->segs[b].q; });
-    for (int i : order) {
-      auto& S = P->segs[i];
-      int pid = append_pass(S.passes[p], S.q, P->pass_descs, P->stage_descs, P->kops);
-      int nb = P->pass_descs[pid].n_blocks;
-      for (int64_t r = 0; r < ((int64_t)1 << S.c); ++r) {
-        SimJob j;
-        std::memset(&j, 0, sizeof(j));
-        j.state_off = S.arena_off / 8 + ((uint64_t)r << S.q);
-        j.pass_id = pid;
-        j.variant = (int32_t)r;
-        j.wg_begin = L.total_wg;
-        if ((int64_t)L.total_wg + nb > ((int64_t)1 << 31) - 1)
-          return fail(CCUT_EUNSUPPORTED, "simulation launch exceeds 2^31 workgroups");
-        L.total_wg += nb;
-        P->jobs.push_back(j);
-        L.n_jobs++;
-      }
-    }
-    P->launches.push_back(L);
-  }
-
   // MFMA merge tile: 64-row tiles while operand loads are light (K <= 64), else 128-row
   int kmax = 1;
   for (const MergeStage& st : P->stages) kmax = std::max(kmax, st.K);
   P->merge_epilogue = kmax <= 64 ? 3 : 1;
 
-  pack_image(P);
-  P->tables_off = align256(P->split_off + P->split_bytes);
-  P->total_arena = align256(P->tables_off + P->image.size());
   apply_tuned(P);
+  if (int rc = build_sim_tables(P, true)) return rc;
 
   *plan_out = guard.release();
   return CCUT_OK;
@@ -349,5 +386,6 @@ extern "C" int ccut_cut_weight(int32_t bit, double out[2]) {
 extern "C" void ccut_plan_free(ccut_plan_t* plan) {
   if (!plan) return;
   release_device(plan->dev);
+  for (auto& t : plan->retired) release_device(t);
   delete plan;
 }

@@ -23,7 +23,8 @@ struct ccut_plan {
   std::vector<float> weights;     // complex64 merge weights, per stage
 
   // simulation launches: one per pass index, jobs for every (segment, variant)
-  int bmax = ccut::PASS_MAX_B, low_bits = 4;
+  int bmax = ccut::PASS_MAX_B, low_bits = 4;  // bmax: block bits in use
+  int block_bits = 0;                         // requested block bits, 0: automatic
   std::vector<ccut::PassDesc> pass_descs;
   std::vector<ccut::StageDesc> stage_descs;
   std::vector<ccut::KOp> kops;
@@ -35,9 +36,11 @@ struct ccut_plan {
   std::vector<unsigned char> image;
   uint64_t img_ops = 0, img_passes = 0, img_stages = 0, img_jobs = 0, img_weights = 0;
   uint64_t tables_off = 0;  // arena byte offset of the table region
+  uint64_t tables_reserve = 0;  // bytes reserved for it
   uint64_t total_arena = 0; // bytes the caller's arena must hold
 
   ccut::DeviceTables dev;   // plan-owned copy after ccut_plan_prepare (graph capture)
+  std::vector<ccut::DeviceTables> retired;  // copies of earlier table builds (graphs may still use them)
 
   // launch configuration (ccut_plan_set_launch / ccut_autotune)
   int sim_threads = 1024;    // workgroup size of the simulation kernel
@@ -49,6 +52,12 @@ struct ccut_plan {
 };
 
 namespace ccut {
+constexpr int AUTO_TARGET_WG = 256;      // workgroups the first simulation launch should reach (one per CU)
+constexpr int AUTO_MIN_BLOCK_BITS = 12;  // smallest block the automatic choice goes down to
+uint64_t align256(uint64_t x);
+int auto_block_bits(const ccut_plan* P);
+// (Re)schedules the simulation at the plan's block size and repacks its tables.
+int build_sim_tables(ccut_plan* P, bool first);
 // Appends a pass to the device tables; returns its PassDesc index.
 int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<StageDesc>& stages,
                 std::vector<KOp>& kops);

@@ -299,16 +299,54 @@ void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& sta
     std::memset(&st, 0, sizeof(st));
     st.op_begin = (int32_t)out.size();
     for (int k = 0; k < REG_BITS; ++k) st.reg[k] = reg[k];
-    int f = 0;
-    for (int j = 0; j < b; ++j)
-      if (pos_of[j] < 0) st.tfix[f++] = j;
-    for (int idx : take) {
-      KOp k = kops[idx];
-      if (k.type == KOP_DENSE) k.a = pos_of[k.a];
-      if (k.type == KOP_CXL) k.b = pos_of[k.b];
-      out.push_back(k);
+    for (int e = 0; e < (1 << REG_BITS); ++e) {
+      int r = 0;
+      for (int k = 0; k < REG_BITS; ++k)
+        if ((e >> k) & 1) r |= 1 << reg[k];
+      st.roff[e] = r;
+      st.proff[e] = r + (r >> 4);
     }
-    st.op_count = (int32_t)take.size();
+    // Runs of unconditional 2x2 gates on distinct register positions become one
+    // KOP_GROUP (they act on different qubits, so their order inside the run is free).
+    for (size_t t = 0; t < take.size();) {
+      const KOp& k0 = kops[take[t]];
+      if (k0.type != KOP_DENSE || k0.cond >= 0) {
+        KOp k = k0;
+        if (k.type == KOP_DENSE) k.a = pos_of[k.a];
+        if (k.type == KOP_CXL) k.b = pos_of[k.b];
+        out.push_back(k);
+        ++t;
+        continue;
+      }
+      KOp members[REG_BITS];
+      int mask = 0;
+      while (t < take.size()) {
+        const KOp& kd = kops[take[t]];
+        if (kd.type != KOP_DENSE || kd.cond >= 0 || ((mask >> pos_of[kd.a]) & 1)) break;
+        const int p = pos_of[kd.a];
+        members[p] = kd;
+        members[p].a = p;
+        mask |= 1 << p;
+        ++t;
+      }
+      KOp g = blank(KOP_GROUP);
+      g.a = mask;
+      for (int p = 0; p < REG_BITS; ++p) {
+        if (!((mask >> p) & 1)) {  // exact identity: x * 1 + y * 0 reproduces x bit for bit
+          members[p] = blank(KOP_DENSE);
+          members[p].a = p;
+          members[p].m[0] = members[p].m[6] = members[p].m[8] = members[p].m[14] = 1.0f;
+        }
+      }
+      static_assert(REG_BITS == 4, "group header holds four slots");
+      g.b = members[0].slot;
+      g.slot = members[1].slot;
+      g.cond = members[2].slot;
+      g.nterms = members[3].slot;
+      out.push_back(g);
+      for (int p = 0; p < REG_BITS; ++p) out.push_back(members[p]);
+    }
+    st.op_count = (int32_t)out.size() - st.op_begin;
     stages.push_back(st);
     pending.swap(keep);
   }

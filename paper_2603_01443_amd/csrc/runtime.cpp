@@ -28,6 +28,7 @@ struct TuneEntry {
   int mfma_min_k = -1;
   int epilogue = 0;
   int merge_grid = 0;
+  int block_bits = 0;
 };
 
 std::mutex g_tune_mu;
@@ -41,11 +42,12 @@ std::string arch_name() {
   return a.substr(0, a.find(':'));
 }
 
-// Shape signature of a plan: segment sizes, variants, passes and merge stages.
+// Shape signature of a plan: segment sizes, variants, fused program lengths and
+// merge stages (nothing that depends on the launch configuration).
 std::string signature(const ccut_plan* P) {
   std::string s = "q" + std::to_string(P->q);
   for (const auto& S : P->segs)
-    s += "|" + std::to_string(S.q) + "x" + std::to_string(1 << S.c) + "p" + std::to_string(S.passes.size());
+    s += "|" + std::to_string(S.q) + "x" + std::to_string(1 << S.c) + "g" + std::to_string(S.prog.ops.size());
   for (const auto& st : P->stages)
     s += "|m" + std::to_string(st.qx) + "," + std::to_string(st.qy) + "," + std::to_string(st.K) + "," +
          std::to_string(st.batch);
@@ -88,6 +90,7 @@ void apply_tuned(ccut_plan* P) {
   P->auto_mfma_min_k = it->second.mfma_min_k;
   P->merge_epilogue = it->second.epilogue;
   P->merge_grid_cap = it->second.merge_grid;
+  P->block_bits = it->second.block_bits;
 }
 
 }  // namespace ccut
@@ -120,9 +123,16 @@ extern "C" int ccut_plan_stats(const ccut_plan_t* plan, int64_t out[8]) {
   clear_error();
   if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
   int64_t dense = 0, diag = 0;
-  for (const auto& k : plan->kops) {
-    if (k.type == KOP_DENSE || k.type == KOP_CXL) ++dense;
-    else ++diag;
+  for (size_t i = 0; i < plan->kops.size(); ++i) {
+    const KOp& k = plan->kops[i];
+    if (k.type == KOP_GROUP) {
+      dense += __builtin_popcount((unsigned)k.a);
+      i += REG_BITS;  // its member records
+    } else if (k.type == KOP_DENSE || k.type == KOP_CXL) {
+      ++dense;
+    } else {
+      ++diag;
+    }
   }
   int64_t hops = 0;
   for (const auto& S : plan->segs) hops += (int64_t)S.prog.ops.size();
@@ -134,6 +144,28 @@ extern "C" int ccut_plan_stats(const ccut_plan_t* plan, int64_t out[8]) {
   out[5] = hops;
   out[6] = (int64_t)plan->launches.size();
   out[7] = (int64_t)plan->jobs.size();
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_set_block_bits(ccut_plan_t* plan, int32_t bits) {
+  clear_error();
+  if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
+  if (bits != 0 && (bits <= plan->low_bits || bits > PASS_MAX_B))
+    return fail(CCUT_EINVAL, "block bits %d outside (%d, %d] (0: automatic)", bits, plan->low_bits, PASS_MAX_B);
+  const int saved = plan->block_bits;
+  plan->block_bits = bits;
+  if (int rc = build_sim_tables(plan, false)) {
+    plan->block_bits = saved;
+    (void)build_sim_tables(plan, false);
+    return rc;
+  }
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_get_block_bits(const ccut_plan_t* plan, int32_t* out) {
+  clear_error();
+  if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
+  *out = plan->bmax;
   return CCUT_OK;
 }
 
@@ -162,28 +194,50 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int saved_pv = plan->sim_per_variant;
   plan->sim_per_variant = 0;
-  int total_wg = 0;
-  for (const auto& L : plan->launches) total_wg = std::max(total_wg, L.total_wg);
   float best = 1e30f;
-  int bt = plan->sim_threads, bg = plan->sim_grid_cap;
+  int bt = plan->sim_threads, bg = plan->sim_grid_cap, bb = plan->bmax;
+  const int saved_bits = plan->block_bits;
   const int threads[3] = {256, 512, 1024};
   const int caps[5] = {0, 256, 512, 1024, 2048};
-  for (int t : threads) {
-    for (int c : caps) {
-      if (c != 0 && c >= total_wg) continue;
-      plan->sim_threads = t;
-      plan->sim_grid_cap = c;
-      float ms = 0.f;
-      int rc = time_call(s, reps, &ms, [&]() { return ccut_simulate_subcircuits(plan, d_arena, arena_bytes, stream); });
-      if (rc) {
-        plan->sim_per_variant = saved_pv;
-        return rc;
+  int qmax = 0;
+  for (const auto& S : plan->segs) qmax = std::max(qmax, S.q);
+  // block sizes: whole segment states in LDS, then 2 and 4 blocks per state
+  for (int bits = std::min(qmax, PASS_MAX_B); bits >= std::max(plan->low_bits + 1, std::min(qmax, PASS_MAX_B) - 2);
+       --bits) {
+    plan->block_bits = bits;
+    if (int rc = build_sim_tables(plan, false)) {
+      plan->sim_per_variant = saved_pv;
+      plan->block_bits = saved_bits;
+      (void)build_sim_tables(plan, false);
+      return rc;
+    }
+    if (plan->total_arena > arena_bytes) continue;  // tables do not fit this caller's arena
+    int total_wg = 0;
+    for (const auto& L : plan->launches) total_wg = std::max(total_wg, L.total_wg);
+    for (int t : threads) {
+      for (int c : caps) {
+        if (c != 0 && c >= total_wg) continue;
+        plan->sim_threads = t;
+        plan->sim_grid_cap = c;
+        float ms = 0.f;
+        int rc = time_call(s, reps, &ms, [&]() { return ccut_simulate_subcircuits(plan, d_arena, arena_bytes, stream); });
+        if (rc) {
+          plan->sim_per_variant = saved_pv;
+          plan->block_bits = saved_bits;
+          (void)build_sim_tables(plan, false);
+          return rc;
+        }
+        if (ms < best) { best = ms; bt = t; bg = c; bb = bits; }
       }
-      if (ms < best) { best = ms; bt = t; bg = c; }
     }
   }
   plan->sim_threads = bt;
   plan->sim_grid_cap = bg;
+  plan->block_bits = bb;
+  if (int rc = build_sim_tables(plan, false)) {
+    plan->sim_per_variant = saved_pv;
+    return rc;
+  }
   // merge: float32 vector kernel against the split MFMA kernel (the CCUT_PREC_AUTO mode) at this
   // plan's term counts, over the GEMM variants and grids
   float t32 = 0.f, tmf = 1e30f;
@@ -213,7 +267,7 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   plan->auto_mfma_min_k = tmf < t32 ? 1 : kmax + 1;
   if (best_ms) *best_ms = best + std::min(t32, tmf);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[arch_name() + "|" + signature(plan)] = TuneEntry{bt, bg, plan->auto_mfma_min_k, best_epi, best_grid};
+  g_tune[arch_name() + "|" + signature(plan)] = TuneEntry{bt, bg, plan->auto_mfma_min_k, best_epi, best_grid, bb};
   return CCUT_OK;
 }
 
@@ -223,10 +277,10 @@ extern "C" int ccut_autotune_save(const char* path) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(CCUT_EINVAL, "cannot write %s", path);
-  std::fprintf(f, "# ccut autotune cache: key threads grid_cap mfma_min_k epilogue merge_grid\n");
+  std::fprintf(f, "# ccut autotune cache: key threads grid_cap mfma_min_k epilogue merge_grid block_bits\n");
   for (const auto& kv : g_tune)
-    std::fprintf(f, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.threads, kv.second.grid_cap,
-                 kv.second.mfma_min_k, kv.second.epilogue, kv.second.merge_grid);
+    std::fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.threads, kv.second.grid_cap,
+                 kv.second.mfma_min_k, kv.second.epilogue, kv.second.merge_grid, kv.second.block_bits);
   std::fclose(f);
   return CCUT_OK;
 }
@@ -237,14 +291,15 @@ extern "C" int ccut_autotune_load(const char* path) {
   FILE* f = std::fopen(path, "r");
   if (!f) return fail(CCUT_EINVAL, "cannot read %s", path);
   char key[1024];
-  int t, c, k, ep, mg;
+  int t, c, k, ep, mg, bb;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   char line[1200];
   while (std::fgets(line, sizeof(line), f)) {
     if (line[0] == '#') continue;
-    if (std::sscanf(line, "%1023s %d %d %d %d %d", key, &t, &c, &k, &ep, &mg) == 6 &&
-        (t == 256 || t == 512 || t == 1024) && c >= 0 && k >= -1 && ep >= 0 && ep <= 3 && mg >= 0)
-      g_tune[key] = TuneEntry{t, c, k, ep, mg};
+    if (std::sscanf(line, "%1023s %d %d %d %d %d %d", key, &t, &c, &k, &ep, &mg, &bb) == 7 &&
+        (t == 256 || t == 512 || t == 1024) && c >= 0 && k >= -1 && ep >= 0 && ep <= 3 && mg >= 0 &&
+        (bb == 0 || (bb > 4 && bb <= PASS_MAX_B)))
+      g_tune[key] = TuneEntry{t, c, k, ep, mg, bb};
   }
   std::fclose(f);
   return CCUT_OK;

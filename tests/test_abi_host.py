@@ -110,3 +110,36 @@ def test_error_codes():
         ccut.cut_plan(8, [Gate("CZ", 3, 4)] * 17, 2)     # c_i above the per-segment limit
     assert e.value.code == ccut.EUNSUPPORTED
     assert "limit" in str(e.value) or "max" in str(e.value)
+
+
+def test_block_bits_reschedule():
+    """The LDS block size reschedules the segment programs: smaller blocks mean
+    more passes and launches but the same fused program; the automatic choice
+    gives the first launch a workgroup per compute unit (256) when it can."""
+    q, n = 28, 2
+    g = brickwork(q, 20, n, 6, seed=0)
+    plan = ccut.cut_plan(q, g, n)
+    assert ccut.plan_get_block_bits(plan) == 13          # 128 variants x 2 blocks = 256 workgroups
+    arena0 = plan.info()["arena_bytes"]
+    stats = {}
+    for bits in (14, 13, 12, 9, 0):
+        ccut.plan_set_block_bits(plan, bits)
+        stats[bits] = ccut.plan_stats(plan)
+        assert plan.info()["arena_bytes"] >= arena0
+    assert ccut.plan_get_block_bits(plan) == 13
+    assert stats[14]["passes"] == 2 and stats[14]["launches"] == 1 and stats[14]["jobs"] == 128
+    assert stats[13]["passes"] > 2 and stats[12]["passes"] >= stats[13]["passes"]
+    assert stats[9]["passes"] > stats[12]["passes"]
+    for b in (13, 12, 9):
+        assert stats[b]["fused_ops"] == stats[14]["fused_ops"]
+        assert stats[b]["dense_ops"] == stats[14]["dense_ops"]
+        assert stats[b]["jobs"] == 128 * stats[b]["launches"]
+    # small segments fit one block at any size: one pass each
+    small = ccut.cut_plan(20, brickwork(20, 8, 2, 4, seed=1), 2)
+    for bits in (14, 12, 10):
+        ccut.plan_set_block_bits(small, bits)
+        assert ccut.plan_stats(small)["passes"] == 2
+    for bad in (-1, 1, 4, 15):
+        with pytest.raises(ccut.CcutError):
+            ccut.plan_set_block_bits(plan, bad)
+    assert ccut.plan_get_block_bits(plan) == 13

@@ -134,6 +134,49 @@ def test_multipass_subcircuits_q30(lib):
     assert np.max(np.abs(got - want)) < fp32_tol(q)
 
 
+_Q26 = {}
+
+
+def _q26_oracle():
+    """13 + 13 qubits, c_total = 4, d = 8: 16 variants per segment, oracle states cached."""
+    if not _Q26:
+        q, d, n, c = 26, 8, 2, 4
+        g = brickwork(q, d, n, c, seed=8)
+        sizes = [13, 13]
+        ocuts = cutting.find_cuts(q, g, sizes)
+        _Q26.update(g=g, sizes=sizes, ocuts=ocuts, ostates=cutting.variant_states(q, g, sizes, ocuts))
+    return _Q26
+
+
+@pytest.mark.parametrize("bits", [13, 12, 11, 9, 5])
+def test_block_bits_variants_match_oracle(lib, bits):
+    """Every LDS block size (one block per state, down to 2^5-amplitude blocks and
+    37 HBM passes per variant) gives the oracle's subcircuit states, and
+    the merged state agrees with the oracle on sampled amplitudes."""
+    ccut, pipeline = lib
+    o = _q26_oracle()
+    q = 26
+    run = pipeline.CutRun(q, o["g"], 2)
+    ccut.plan_set_block_bits(run.plan, bits)
+    assert ccut.plan_get_block_bits(run.plan) == bits
+    assert run.info["arena_bytes"] <= run.plan.info()["arena_bytes"] <= run.arena.numel()
+    st = ccut.plan_stats(run.plan)
+    print(f"bits {bits}: {st}", flush=True)
+    run.simulate_subcircuits()
+    torch.cuda.synchronize()
+    pcuts = run.plan.cuts()
+    for i in range(2):
+        for r in range(16):
+            ref = o["ostates"][oracle_key(pcuts, o["ocuts"], i, r)]
+            assert metrics.max_abs_error(ref, to_np(run.variant_state(i, r))) < fp32_tol(13), (bits, i, r)
+    psi = run.merge("fp32")
+    rng = np.random.default_rng(bits)
+    xs = sorted(set(int(x) for x in rng.integers(0, 2 ** q, size=300)) | {0, 2 ** q - 1, 2 ** 13, 2 ** 13 - 1})
+    want = cutting.amplitudes(xs, o["sizes"], o["ocuts"], o["ostates"])
+    got = to_np(psi[torch.tensor(xs, device=psi.device)])
+    assert np.max(np.abs(got - want)) < fp32_tol(q)
+
+
 def test_bench_config_sampled(lib):
     """The measured workload (q=28, 14+14, d=20, c_total=6): sampled amplitudes vs the oracle,
     unit norm, and the full cut state against the full uncut state on the GPU."""
