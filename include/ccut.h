@@ -165,6 +165,7 @@ int ccut_plan_prepare(ccut_plan_t* plan);
  * Subcircuit simulation, Algorithm 2 (Appendix B): for every segment i and
  * variant r in [0, 2^{c_i}), psi_i^{(r)} = (segment i's gates with the cut
  * slots set by r) |0...0>, written to the arena at the plan's layout.
+ * Complex64 states; the gate arithmetic follows ccut_plan_set_sim_precision.
  *
  *   d_arena      device buffer of at least info.arena_bytes bytes
  *   arena_bytes  its size
@@ -203,7 +204,8 @@ int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes
  * The uncut baseline T_orig (Sec. III.A): the whole circuit applied gate by
  * gate to |0...0> of q qubits, written to d_psi (2^q complex64).  The gate
  * list is compiled on the host (compiled programs are cached by content) and
- * run as LDS-blocked passes over the state in HBM.
+ * run as LDS-blocked passes over the state in HBM, with the default
+ * (CCUT_SIM_FP16X3) gate arithmetic of the subcircuit simulation.
  * Errors: CCUT_EINVAL, CCUT_ENOSPC, CCUT_ENOMEM, CCUT_EHIP.
  */
 int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, void* d_psi,
@@ -260,6 +262,23 @@ int ccut_plan_stats(const ccut_plan_t* plan, int64_t out[8]);
 int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap);
 /* The current (epilogue, grid_cap) of a plan (host-only). */
 int ccut_plan_get_merge(const ccut_plan_t* plan, int32_t out[2]);
+
+/* Gate arithmetic of the state-vector simulation (Algorithm 2 and the uncut baseline). */
+enum {
+  CCUT_SIM_FP32 = 0,    /* every gate in float32 on the vector ALUs */
+  CCUT_SIM_FP16X3 = 1   /* default: each register-stage group of single-qubit gates (one per
+                           register qubit, a 16x16 complex Kronecker product) as split-float16
+                           MFMA, hi.hi + hi.lo + lo.hi with float32 accumulation on a state
+                           scaled by 2^14; relative error per group ~1e-6; other ops float32 */
+};
+
+/*
+ * Gate arithmetic of a plan's subcircuit simulation (CCUT_SIM_*).  Host-only.
+ * Errors: CCUT_EINVAL.
+ */
+int ccut_plan_set_sim_precision(ccut_plan_t* plan, int32_t precision);
+/* The plan's current CCUT_SIM_* value (host-only). */
+int ccut_plan_get_sim_precision(const ccut_plan_t* plan, int32_t* out);
 
 /*
  * LDS block size of the subcircuit simulation (Algorithm 2): blocks of 2^bits

@@ -110,6 +110,8 @@ def _load():
         "ccut_plan_set_merge": [vp, i32, i32],
         "ccut_plan_get_merge": [vp, ctypes.POINTER(i32)],
         "ccut_plan_set_block_bits": [vp, i32],
+        "ccut_plan_set_sim_precision": [vp, i32],
+        "ccut_plan_get_sim_precision": [vp, ctypes.POINTER(i32)],
         "ccut_plan_get_block_bits": [vp, ctypes.POINTER(i32)],
         "ccut_plan_stats": [vp, ctypes.POINTER(i64)],
         "ccut_autotune": [vp, vp, u64, vp, u64, i32, vp, dp],
@@ -376,6 +378,21 @@ def plan_get_merge(plan: Plan) -> dict:
 def plan_set_block_bits(plan: Plan, bits: int) -> None:
     """LDS block size of the simulation (2^bits amplitudes; 0 = automatic)."""
     _check(_lib.ccut_plan_set_block_bits(plan.handle, int(bits)))
+
+
+SIM_PRECISIONS = {"fp32": 0, "fp16x3": 1}
+
+
+def plan_set_sim_precision(plan: Plan, precision) -> None:
+    """Gate arithmetic of the subcircuit simulation: "fp32" (vector ALUs) or "fp16x3" (MFMA groups)."""
+    p = SIM_PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(_lib.ccut_plan_set_sim_precision(plan.handle, p))
+
+
+def plan_get_sim_precision(plan: Plan) -> str:
+    out = ctypes.c_int32(0)
+    _check(_lib.ccut_plan_get_sim_precision(plan.handle, ctypes.byref(out)))
+    return {v: k for k, v in SIM_PRECISIONS.items()}[int(out.value)]
 
 
 def plan_get_block_bits(plan: Plan) -> int:

@@ -74,6 +74,7 @@ void pack_image(ccut_plan* P) {
   pack(P->image, P->stage_descs, P->img_stages);
   pack(P->image, P->jobs, P->img_jobs);
   pack(P->image, P->weights, P->img_weights);
+  pack(P->image, P->grefs, P->img_grefs);
   if (P->image.empty()) P->image.resize(256);
 }
 
@@ -104,7 +105,7 @@ int staged_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s) {
 
 // Copies a table image to a new device allocation (synchronous).
 int upload_tables(DeviceTables& t, const std::vector<unsigned char>& img, uint64_t o_ops, uint64_t o_pass,
-                  uint64_t o_stage, uint64_t o_jobs, uint64_t o_w) {
+                  uint64_t o_stage, uint64_t o_jobs, uint64_t o_w, uint64_t o_grefs) {
   int dev = 0;
   CCUT_HIP(hipGetDevice(&dev));
   if (t.device == dev) return 0;
@@ -123,6 +124,7 @@ int upload_tables(DeviceTables& t, const std::vector<unsigned char>& img, uint64
   t.stages = reinterpret_cast<StageDesc*>(b + o_stage);
   t.jobs = reinterpret_cast<SimJob*>(b + o_jobs);
   t.weights = reinterpret_cast<float*>(b + o_w);
+  t.grefs = reinterpret_cast<GroupRef*>(b + o_grefs);
   t.device = dev;
   return 0;
 }
@@ -139,6 +141,7 @@ int plan_tables(ccut_plan* P, char* arena, hipStream_t s, DeviceTables& out) {
     out.stages = P->dev.stages;
     out.jobs = P->dev.jobs;
     out.weights = P->dev.weights;
+    out.grefs = P->dev.grefs;
     return 0;
   }
   unsigned char* b = reinterpret_cast<unsigned char*>(arena + P->tables_off);
@@ -149,6 +152,7 @@ int plan_tables(ccut_plan* P, char* arena, hipStream_t s, DeviceTables& out) {
   out.stages = reinterpret_cast<StageDesc*>(b + P->img_stages);
   out.jobs = reinterpret_cast<SimJob*>(b + P->img_jobs);
   out.weights = reinterpret_cast<float*>(b + P->img_weights);
+  out.grefs = reinterpret_cast<GroupRef*>(b + P->img_grefs);
   return 0;
 }
 
@@ -177,9 +181,22 @@ struct UncutProg {
   std::vector<StageDesc> stages;
   std::vector<KOp> kops;
   std::vector<SimJob> jobs;  // one per pass
+  std::vector<GroupRef> grefs;
   DeviceTables dev;
+  uint4* gtab = nullptr;     // MFMA group tables (built once)
   uint64_t stamp = 0;
 };
+
+void release_uncut(UncutProg& U) {
+  if (U.gtab && U.dev.device >= 0) {
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != U.dev.device) (void)hipSetDevice(U.dev.device);
+    (void)hipFree(U.gtab);
+    if (cur != U.dev.device) (void)hipSetDevice(cur);
+  }
+  U.gtab = nullptr;
+  release_device(U.dev);
+}
 
 static std::mutex g_uncut_mu;
 static std::map<uint64_t, std::unique_ptr<UncutProg>> g_uncut;
@@ -211,7 +228,7 @@ int compile_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, UncutPro
   std::vector<Pass> passes;
   if (int rc = schedule_passes(pb.prog, PASS_MAX_B, 4, passes)) return rc;
   for (const Pass& p : passes) {
-    int pid = append_pass(p, q, U.descs, U.stages, U.kops);
+    int pid = append_pass(p, q, U.descs, U.stages, U.kops, U.grefs);
     SimJob j;
     std::memset(&j, 0, sizeof(j));
     j.pass_id = pid;
@@ -232,7 +249,7 @@ extern "C" int ccut_plan_prepare(ccut_plan_t* plan) {
   clear_error();
   if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
   return upload_tables(plan->dev, plan->image, plan->img_ops, plan->img_passes, plan->img_stages, plan->img_jobs,
-                       plan->img_weights);
+                       plan->img_weights, plan->img_grefs);
 }
 
 extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* stream) {
@@ -244,18 +261,24 @@ extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint6
   hipStream_t s = static_cast<hipStream_t>(stream);
   DeviceTables T;
   if (int rc = plan_tables(plan, static_cast<char*>(d_arena), s, T)) return rc;
+  const uint4* gtab = nullptr;
+  if (plan->sim_precision == CCUT_SIM_FP16X3 && !plan->grefs.empty()) {
+    uint4* g = reinterpret_cast<uint4*>(static_cast<char*>(d_arena) + plan->gtab_off);
+    if (int rc = launch_group_tables(T.ops, T.grefs, (int)plan->grefs.size(), g, s)) return rc;
+    gtab = g;
+  }
   for (const auto& L : plan->launches) {
     if (plan->sim_per_variant) {
       for (int j = 0; j < L.n_jobs; ++j) {
         const SimJob& job = plan->jobs[L.job_begin + j];
         const int nb = plan->pass_descs[job.pass_id].n_blocks;
-        if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, nb, job.wg_begin, T.passes, T.stages, T.ops,
+        if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, nb, job.wg_begin, T.passes, T.stages, T.ops, gtab,
                                 static_cast<float*>(d_arena), plan->bmax, plan->sim_threads, 0, s))
           return rc;
       }
       continue;
     }
-    if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, L.total_wg, 0, T.passes, T.stages, T.ops,
+    if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, L.total_wg, 0, T.passes, T.stages, T.ops, gtab,
                             static_cast<float*>(d_arena), plan->bmax, plan->sim_threads, plan->sim_grid_cap, s))
       return rc;
   }
@@ -350,18 +373,33 @@ extern "C" int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t 
     fresh->gates.assign(gates, gates + n_gates);
     if (int rc = compile_uncut(q, gates, n_gates, *fresh)) return rc;
     std::vector<unsigned char> img;
-    uint64_t o_ops, o_pass, o_stage, o_jobs, o_w;
+    uint64_t o_ops, o_pass, o_stage, o_jobs, o_w, o_g;
     pack(img, fresh->kops, o_ops);
     pack(img, fresh->descs, o_pass);
     pack(img, fresh->stages, o_stage);
     pack(img, fresh->jobs, o_jobs);
+    pack(img, fresh->grefs, o_g);
     o_w = img.size();
-    if (int rc = upload_tables(fresh->dev, img, o_ops, o_pass, o_stage, o_jobs, o_w)) return rc;
+    if (int rc = upload_tables(fresh->dev, img, o_ops, o_pass, o_stage, o_jobs, o_w, o_g)) return rc;
+    if (!fresh->grefs.empty()) {  // operand tables built once, before the program is first used
+      hipError_t e = hipMalloc((void**)&fresh->gtab, fresh->grefs.size() * GROUP_TABLE_UINT4 * sizeof(uint4));
+      if (e != hipSuccess) {
+        fresh->gtab = nullptr;
+        release_uncut(*fresh);
+        return hip_fail(e, "group table allocation");
+      }
+      int rc = launch_group_tables(fresh->dev.ops, fresh->dev.grefs, (int)fresh->grefs.size(), fresh->gtab, nullptr);
+      if (rc == 0 && (e = hipDeviceSynchronize()) != hipSuccess) rc = hip_fail(e, "group table build");
+      if (rc) {
+        release_uncut(*fresh);
+        return rc;
+      }
+    }
     if (g_uncut.size() >= UNCUT_CACHE) {
       auto oldest = g_uncut.begin();
       for (auto i = g_uncut.begin(); i != g_uncut.end(); ++i)
         if (i->second->stamp < oldest->second->stamp) oldest = i;
-      release_device(oldest->second->dev);
+      release_uncut(*oldest->second);
       g_uncut.erase(oldest);
     }
     U = fresh.get();
@@ -371,7 +409,7 @@ extern "C" int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t 
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (size_t p = 0; p < U->jobs.size(); ++p) {
     if (int rc = launch_sim(U->dev.jobs + p, 1, U->descs[p].n_blocks, 0, U->dev.passes, U->dev.stages, U->dev.ops,
-                            static_cast<float*>(d_psi), PASS_MAX_B, 1024, 0, s))
+                            U->gtab, static_cast<float*>(d_psi), PASS_MAX_B, U->gtab ? 512 : 1024, 0, s))
       return rc;
   }
   return CCUT_OK;

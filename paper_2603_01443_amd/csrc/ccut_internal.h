@@ -65,7 +65,9 @@ enum KOpType : int32_t {
                    // distinct qubits commute); the KOP_DENSE records of positions
                    // 0..REG_BITS-1 follow (identity where the group has no gate), and
                    // the header repeats their variant slots in b, slot, cond, nterms so
-                   // that one 32-byte read gives every matrix address
+                   // that one 32-byte read gives every matrix address.  pad[0]: first
+                   // MFMA operand table of the group, pad[1]: number of members with a
+                   // slot (the group has 2^pad[1] tables, one per choice of those slots)
 };
 
 constexpr int KOP_MAX_TERMS = 8;
@@ -101,6 +103,20 @@ struct StageDesc {
   int32_t pad[2];
 };
 static_assert(sizeof(StageDesc) == 160, "StageDesc layout");
+
+// MFMA form of a KOP_GROUP (split-float16 register-stage path).  The group's
+// gates form a 16x16 complex matrix G (Kronecker product, position p = bit p of
+// the row and column index) acting on a thread's 16 amplitudes.  As a real
+// 32x32 matrix on (Re x[0..15], Im x[0..15]) it is the A operand of two
+// v_mfma_f32_32x32x16_f16 steps (k = 0..15: real parts, 16..31: imaginary).
+// A table holds, per lane l (row m = l % 32, k half h = l / 32), four uint4:
+// hi and lo float16 parts of A[m][16 s + 8 h + e], e = 0..7, for s = 0, 1.
+struct GroupRef {
+  int32_t op;   // GROUP header in the op table
+  int32_t sel;  // bit j: slot choice of the group's j-th member with a slot
+};
+constexpr int GROUP_TABLE_UINT4 = 64 * 4;  // uint4 per table (4 KiB)
+constexpr float SIM_MFMA_SCALE = 16384.0f;  // 2^14: state scale inside a pass on the MFMA path
 
 // One LDS-blocked pass over a state: blocks of 2^b amplitudes spanning the
 // register qubits group[0..b); the other qubits are fixed per block.
@@ -162,6 +178,7 @@ struct DeviceTables {
   StageDesc* stages = nullptr;
   SimJob* jobs = nullptr;
   float* weights = nullptr;    // complex64 merge weights
+  GroupRef* grefs = nullptr;   // MFMA operand tables to build (one per group and slot choice)
 };
 
 // ---------------------------------------------------------------- timing
@@ -179,9 +196,14 @@ struct ProfScope {
 
 // Runs workgroups [wg_offset, wg_offset + total_wg) of a job list; grid_cap > 0
 // makes the launch persistent (each workgroup loops over several blocks).
+// gtab != nullptr selects the split-float16 MFMA path for register-stage groups
+// (operand tables built by launch_group_tables); nullptr keeps float32 VALU.
 int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
-               const StageDesc* d_stages, const KOp* d_ops, float* base, int bmax, int threads, int grid_cap,
-               hipStream_t s);
+               const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax,
+               int threads, int grid_cap, hipStream_t s);
+
+// Builds the n MFMA operand tables listed by refs into gtab (n * GROUP_TABLE_UINT4 uint4).
+int launch_group_tables(const KOp* d_ops, const GroupRef* d_refs, int n, uint4* gtab, hipStream_t s);
 
 int launch_merge_f32(const MergeStage& st, const float* A, const float* B, float* out,
                      const float* d_weights, hipStream_t s);

@@ -18,6 +18,16 @@
 // run their ops one at a time.  LDS is padded by one slot per 16 amplitudes
 // so that strided stage accesses spread over the banks.
 //
+// On the MFMA path (blocks of at least 2^10 amplitudes, so that every lane of
+// a wavefront holds a thread slot) a group (one 2x2 gate per register qubit, a
+// 16x16 complex Kronecker product) is applied to a wavefront's 64 x 16 amplitudes as a real
+// 32x32 by 32x64 product: two v_mfma_f32_32x32x16_f16 column tiles, each the
+// sum of hi.hi + hi.lo + lo.hi products of float16 halves (float32 accumulate).
+// The amplitudes stay in the lane that owns them: one lane-half swap puts the
+// B operand in MFMA order and one more brings each column's 32 results back to
+// its lane.  The state is scaled by 2^14 while a pass runs so that the low
+// halves of typical amplitudes stay normal float16 numbers.
+//
 // One launch covers a list of jobs (state, pass, variant); a grid-stride loop
 // over the job list makes the launch persistent when the grid is smaller than
 // the work.
@@ -39,6 +49,94 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cmadd2(float2 m0, float2 x, float2 m1, float2 y) {
   return make_float2(m0.x * x.x - m0.y * x.y + m1.x * y.x - m1.y * y.y,
                      m0.x * x.y + m0.y * x.x + m1.x * y.y + m1.y * y.x);
+}
+
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+// Swaps lanes 32..63 of x with lanes 0..31 of y.
+__device__ __forceinline__ void swap_halves(uint32_t& x, uint32_t& y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+__device__ __forceinline__ void swap_halves(float& x, float& y) {
+  uint32_t u = __float_as_uint(x), v = __float_as_uint(y);
+  swap_halves(u, v);
+  x = __uint_as_float(u);
+  y = __uint_as_float(v);
+}
+
+typedef __attribute__((ext_vector_type(2))) _Float16 f16x2;
+
+// hi = float16(x), lo = float16(x - hi) for a pair, both rounded to nearest
+// (v_cvt_pk_f16_f32: unbiased, so rounding errors do not drift the norm).
+__device__ __forceinline__ void split_pair(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+  const f16x2 h = {(_Float16)x0, (_Float16)x1};
+  const f16x2 l = {(_Float16)(x0 - (float)h[0]), (_Float16)(x1 - (float)h[1])};
+  hi = __builtin_bit_cast(uint32_t, h);
+  lo = __builtin_bit_cast(uint32_t, l);
+}
+
+__device__ __forceinline__ f32x16 mfma16(const uint4& a, uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3,
+                                         f32x16 c) {
+  const uint4 b = make_uint4(b0, b1, b2, b3);
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                               0, 0);
+}
+
+// y = G x for every lane's 16 amplitudes (the group's operand table gt: this
+// lane's four uint4, hi/lo for k-steps 0 (real parts) and 1 (imaginary parts)).
+__device__ __forceinline__ void group_mfma(float2 (&a)[R], const uint4* __restrict__ gt) {
+  const uint4 ghi0 = gt[0], ghi1 = gt[1], glo0 = gt[2], glo1 = gt[3];
+  // B operand planes: element e of re / im, float16 hi and lo, two per dword
+  uint32_t rh[8], rl[8], ih[8], il[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    split_pair(a[2 * j].x, a[2 * j + 1].x, rh[j], rl[j]);
+    split_pair(a[2 * j].y, a[2 * j + 1].y, ih[j], il[j]);
+  }
+  // dwords 0..3 (elements 0..7) become the operand of column tile 0 (lanes 0..31),
+  // dwords 4..7 (elements 8..15) that of tile 1 (lanes 32..63)
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    swap_halves(rh[j], rh[4 + j]);
+    swap_halves(rl[j], rl[4 + j]);
+    swap_halves(ih[j], ih[4 + j]);
+    swap_halves(il[j], il[4 + j]);
+  }
+  f32x16 c0, c1;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) c0[v] = c1[v] = 0.f;
+  c0 = mfma16(glo0, rh[0], rh[1], rh[2], rh[3], c0);
+  c0 = mfma16(ghi0, rl[0], rl[1], rl[2], rl[3], c0);
+  c0 = mfma16(glo1, ih[0], ih[1], ih[2], ih[3], c0);
+  c0 = mfma16(ghi1, il[0], il[1], il[2], il[3], c0);
+  c0 = mfma16(ghi0, rh[0], rh[1], rh[2], rh[3], c0);
+  c0 = mfma16(ghi1, ih[0], ih[1], ih[2], ih[3], c0);
+  c1 = mfma16(glo0, rh[4], rh[5], rh[6], rh[7], c1);
+  c1 = mfma16(ghi0, rl[4], rl[5], rl[6], rl[7], c1);
+  c1 = mfma16(glo1, ih[4], ih[5], ih[6], ih[7], c1);
+  c1 = mfma16(ghi1, il[4], il[5], il[6], il[7], c1);
+  c1 = mfma16(ghi0, rh[4], rh[5], rh[6], rh[7], c1);
+  c1 = mfma16(ghi1, ih[4], ih[5], ih[6], ih[7], c1);
+  // accumulator v of a lane holds row (v & 3) + 4 (lane / 32) + 8 (v / 4) of its
+  // tile's column lane % 32; after the swap c0[v] / c1[v] hold rows
+  // (v & 3) + 8 (v / 4) and that + 4 of the lane's own column
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    float x = c0[v], y = c1[v];
+    swap_halves(x, y);
+    c0[v] = x;
+    c1[v] = y;
+  }
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    const int vr = (e & 3) | ((e >> 3) << 2);              // row e      (real part)
+    const int vi = (e & 3) | ((2 + (e >> 3)) << 2);        // row 16 + e (imaginary part)
+    a[e].x = (e & 4) ? c1[vr] : c0[vr];
+    a[e].y = (e & 4) ? c1[vi] : c0[vi];
+  }
 }
 
 template <int K>
@@ -73,11 +171,33 @@ __device__ __forceinline__ const float* kop_matrix(const KOp* k, int slot, int v
 }
 
 // Applies the ops [o0, o1) of a register stage to one thread's amplitudes.
+// full_waves: every lane of the wavefront holds a thread slot (the MFMA path
+// exchanges data between lane halves, which needs both halves active).
+template <bool MFMA>
 __device__ __forceinline__ void run_stage_ops(float2 (&a)[R], const int (&idx)[R], const KOp* __restrict__ ops,
-                                              int o0, int o1, uint64_t blockbase, int variant) {
+                                              int o0, int o1, uint64_t blockbase, int variant,
+                                              const uint4* __restrict__ gtab, bool full_waves) {
   for (int o = o0; o < o1;) {
     const KOp* k = ops + o;
     const int type = k->type;
+    if (MFMA && full_waves && type == KOP_GROUP) {
+      // table of this choice of the members' slots: bit j = slot bit of the j-th slotted member
+      const int4 h = *reinterpret_cast<const int4*>(k);
+      const int s2 = k->cond, s3 = k->nterms;
+      const int slots[4] = {h.z, h.w, s2, s3};
+      int sel = 0, j = 0;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        if (slots[p] >= 0) {
+          sel |= ((variant >> slots[p]) & 1) << j;
+          ++j;
+        }
+      }
+      const uint4* gt = gtab + (uint64_t)(k->pad[0] + sel) * GROUP_TABLE_UINT4 + (threadIdx.x & 63) * 4;
+      group_mfma(a, gt);
+      o += 1 + REG_BITS;
+      continue;
+    }
     if (type == KOP_GROUP) {
       // one 2x2 gate per register position: every matrix address comes from the
       // header, the four matrices are fetched together, then straight-line arithmetic
@@ -189,11 +309,12 @@ __device__ __forceinline__ void run_ops_direct(float2* sh, int nb, const KOp* __
   }
 }
 
-template <int NT>
+template <int NT, bool MFMA>
 __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int n_jobs, int total_wg,
                                             int wg_offset, const PassDesc* __restrict__ passes,
                                             const StageDesc* __restrict__ stages, const KOp* __restrict__ ops,
-                                            float2* __restrict__ base) {
+                                            const uint4* __restrict__ gtab, float2* __restrict__ base) {
+  const float scale_in = MFMA ? SIM_MFMA_SCALE : 1.0f, scale_out = MFMA ? 1.0f / SIM_MFMA_SCALE : 1.0f;
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* lo_tab = reinterpret_cast<uint64_t*>(smem);
   uint64_t* hi_tab = lo_tab + TAB;
@@ -236,9 +357,12 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
     if (P->init) {
       for (int i = tid; i < nb; i += NT) sh[pad(i)] = make_float2(0.f, 0.f);
       __syncthreads();
-      if (tid == 0 && blockbase == 0) sh[0] = make_float2(1.f, 0.f);
+      if (tid == 0 && blockbase == 0) sh[0] = make_float2(scale_in, 0.f);
     } else {
-      for (int i = tid; i < nb; i += NT) sh[pad(i)] = st[blockbase + lo_tab[i & (TAB - 1)] + hi_tab[i >> 7]];
+      for (int i = tid; i < nb; i += NT) {
+        const float2 v = st[blockbase + lo_tab[i & (TAB - 1)] + hi_tab[i >> 7]];
+        sh[pad(i)] = make_float2(v.x * scale_in, v.y * scale_in);
+      }
     }
     __syncthreads();
 
@@ -264,7 +388,8 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
             idx[e] = tb | S->roff[e];
             a[e] = sh[pb + S->proff[e]];
           }
-          run_stage_ops(a, idx, ops, S->op_begin, S->op_begin + S->op_count, blockbase, job.variant);
+          run_stage_ops<MFMA>(a, idx, ops, S->op_begin, S->op_begin + S->op_count, blockbase, job.variant, gtab,
+                              (active & 63) == 0);
 #pragma unroll
           for (int e = 0; e < R; ++e) sh[pb + S->proff[e]] = a[e];
         }
@@ -272,7 +397,10 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
       }
     }
 
-    for (int i = tid; i < nb; i += NT) st[blockbase + lo_tab[i & (TAB - 1)] + hi_tab[i >> 7]] = sh[pad(i)];
+    for (int i = tid; i < nb; i += NT) {
+      const float2 v = sh[pad(i)];
+      st[blockbase + lo_tab[i & (TAB - 1)] + hi_tab[i >> 7]] = make_float2(v.x * scale_out, v.y * scale_out);
+    }
     __syncthreads();
   }
 }
@@ -281,41 +409,123 @@ constexpr size_t shmem_bytes(int bmax) {
   return 2 * TAB * sizeof(uint64_t) + sizeof(float2) * (((size_t)1 << bmax) + ((size_t)1 << bmax) / 16);
 }
 
-template <int NT>
+// One wavefront per (group, slot choice): lane l writes its four uint4 of the
+// real 32x32 A operand (row m = l % 32, columns 16 s + 8 (l / 32) + e).
+__global__ __launch_bounds__(64) void k_group_tables(const KOp* __restrict__ ops, const GroupRef* __restrict__ refs,
+                                                     uint4* __restrict__ gtab) {
+  const GroupRef ref = refs[blockIdx.x];
+  const KOp* g = ops + ref.op;
+  const int lane = threadIdx.x;
+  // 2x2 matrix of position p for this slot choice: u[p][2 * row + col]
+  float2 u[4][4];
+  int j = 0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const KOp* k = g + 1 + p;
+    int bit = 0;
+    if (k->slot >= 0) {
+      bit = (ref.sel >> j) & 1;
+      ++j;
+    }
+    const float* m = k->m + 8 * bit;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) u[p][t] = make_float2(m[2 * t], m[2 * t + 1]);
+  }
+  const int m = lane & 31, h = lane >> 5;
+  const int row = m & 15;
+  const bool imag_row = m >= 16;
+  uint32_t hi[2][4], lo[2][4];
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    float v0[2], v1[2];  // [k-step]
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int col = 8 * h + e + d;
+      float2 gv = make_float2(1.f, 0.f);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const bool rb = (row >> p) & 1, cb = (col >> p) & 1;  // selects, no indexed register array
+        const float2 f = rb ? (cb ? u[p][3] : u[p][2]) : (cb ? u[p][1] : u[p][0]);
+        gv = cmul(gv, f);
+      }
+      // rows 0..15: Re y = Re G Re x - Im G Im x;  rows 16..31: Im y = Im G Re x + Re G Im x
+      const float s0 = imag_row ? gv.y : gv.x;
+      const float s1 = imag_row ? gv.x : -gv.y;
+      if (d == 0) { v0[0] = s0; v0[1] = s1; } else { v1[0] = s0; v1[1] = s1; }
+    }
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      // float16 hi / lo of the float32 products: round to nearest for the table
+      const _Float16 h0 = (_Float16)v0[st], h1 = (_Float16)v1[st];
+      const _Float16 l0 = (_Float16)(v0[st] - (float)h0), l1 = (_Float16)(v1[st] - (float)h1);
+      hi[st][e / 2] = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+      lo[st][e / 2] = (uint32_t)__builtin_bit_cast(uint16_t, l0) | ((uint32_t)__builtin_bit_cast(uint16_t, l1) << 16);
+    }
+  }
+  uint4* out = gtab + (uint64_t)blockIdx.x * GROUP_TABLE_UINT4 + lane * 4;
+  out[0] = make_uint4(hi[0][0], hi[0][1], hi[0][2], hi[0][3]);
+  out[1] = make_uint4(hi[1][0], hi[1][1], hi[1][2], hi[1][3]);
+  out[2] = make_uint4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
+  out[3] = make_uint4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
+}
+
+template <int NT, bool MFMA>
 int launch_sim_t(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
-                 const StageDesc* d_stages, const KOp* d_ops, float* base, int bmax, int grid, hipStream_t s) {
+                 const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int grid,
+                 hipStream_t s) {
   const size_t shmem = shmem_bytes(bmax);
   static bool attr_set = false;
   if (!attr_set) {
-    CCUT_HIP(hipFuncSetAttribute((const void*)k_sim<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    CCUT_HIP(hipFuncSetAttribute((const void*)k_sim<NT, MFMA>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)shmem_bytes(PASS_MAX_B)));
     attr_set = true;
   }
   ProfScope prof(PROF_SIM, s);
-  hipLaunchKernelGGL(k_sim<NT>, dim3(grid), dim3(NT), shmem, s, d_jobs, n_jobs, total_wg, wg_offset, d_passes,
-                     d_stages, d_ops, reinterpret_cast<float2*>(base));
+  hipLaunchKernelGGL((k_sim<NT, MFMA>), dim3(grid), dim3(NT), shmem, s, d_jobs, n_jobs, total_wg, wg_offset,
+                     d_passes, d_stages, d_ops, gtab, reinterpret_cast<float2*>(base));
   CCUT_HIP(hipGetLastError());
   return 0;
+}
+
+template <bool MFMA>
+int launch_sim_m(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
+                 const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax,
+                 int threads, int grid, hipStream_t s) {
+  switch (threads) {
+    case 256:
+      return launch_sim_t<256, MFMA>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base,
+                                     bmax, grid, s);
+    case 512:
+      return launch_sim_t<512, MFMA>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base,
+                                     bmax, grid, s);
+    case 1024:
+      return launch_sim_t<1024, MFMA>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base,
+                                      bmax, grid, s);
+    default:
+      return fail(CCUT_EINVAL, "unsupported workgroup size %d", threads);
+  }
 }
 
 }  // namespace
 
 int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
-               const StageDesc* d_stages, const KOp* d_ops, float* base, int bmax, int threads, int grid_cap,
-               hipStream_t s) {
+               const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int threads,
+               int grid_cap, hipStream_t s) {
   if (total_wg <= 0 || n_jobs <= 0) return 0;
   if (bmax < 1 || bmax > PASS_MAX_B) return fail(CCUT_EINVAL, "bad block bits %d", bmax);
   const int grid = (grid_cap > 0 && grid_cap < total_wg) ? grid_cap : total_wg;
-  switch (threads) {
-    case 256:
-      return launch_sim_t<256>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, base, bmax, grid, s);
-    case 512:
-      return launch_sim_t<512>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, base, bmax, grid, s);
-    case 1024:
-      return launch_sim_t<1024>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, base, bmax, grid, s);
-    default:
-      return fail(CCUT_EINVAL, "unsupported workgroup size %d", threads);
-  }
+  if (gtab)
+    return launch_sim_m<true>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base, bmax,
+                              threads, grid, s);
+  return launch_sim_m<false>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, nullptr, base, bmax,
+                             threads, grid, s);
+}
+
+int launch_group_tables(const KOp* d_ops, const GroupRef* d_refs, int n, uint4* gtab, hipStream_t s) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(k_group_tables, dim3(n), dim3(64), 0, s, d_ops, d_refs, gtab);
+  CCUT_HIP(hipGetLastError());
+  return 0;
 }
 
 }  // namespace ccut

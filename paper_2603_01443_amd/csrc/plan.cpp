@@ -15,7 +15,7 @@ namespace ccut {
 uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<StageDesc>& stages,
-                std::vector<KOp>& kops) {
+                std::vector<KOp>& kops, std::vector<GroupRef>& grefs) {
   PassDesc d;
   std::memset(&d, 0, sizeof(d));
   d.b = (int32_t)p.group.size();
@@ -45,6 +45,17 @@ int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector
     d.op_count = (int32_t)sk.size();
     stages.insert(stages.end(), st.begin(), st.end());
     kops.insert(kops.end(), sk.begin(), sk.end());
+    // one MFMA operand table per group and choice of its members' slots
+    for (size_t i = base; i < kops.size(); ++i) {
+      KOp& g = kops[i];
+      if (g.type != KOP_GROUP) continue;
+      int nslot = 0;
+      for (int m = 1; m <= REG_BITS; ++m) nslot += kops[i + m].slot >= 0;
+      g.pad[0] = (int32_t)grefs.size();
+      g.pad[1] = nslot;
+      for (int sel = 0; sel < (1 << nslot); ++sel) grefs.push_back(GroupRef{(int32_t)i, sel});
+      i += REG_BITS;
+    }
   } else {
     kops.insert(kops.end(), p.kops.begin(), p.kops.end());
   }
@@ -74,6 +85,7 @@ int build_sim_tables(ccut_plan* P, bool first) {
   P->pass_descs.clear();
   P->stage_descs.clear();
   P->kops.clear();
+  P->grefs.clear();
   P->jobs.clear();
   P->launches.clear();
   for (auto& S : P->segs)
@@ -91,7 +103,7 @@ int build_sim_tables(ccut_plan* P, bool first) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P->segs[a].q > P->segs[b].q; });
     for (int i : order) {
       auto& S = P->segs[i];
-      int pid = append_pass(S.passes[p], S.q, P->pass_descs, P->stage_descs, P->kops);
+      int pid = append_pass(S.passes[p], S.q, P->pass_descs, P->stage_descs, P->kops, P->grefs);
       int nb = P->pass_descs[pid].n_blocks;
       for (int64_t r = 0; r < ((int64_t)1 << S.c); ++r) {
         SimJob j;
@@ -115,7 +127,13 @@ int build_sim_tables(ccut_plan* P, bool first) {
     P->retired.push_back(P->dev);
     P->dev = DeviceTables();
   }
-  P->tables_off = align256(P->split_off + P->split_bytes);
+  // arena: ... | split planes | MFMA group tables | table image; both reserved with room
+  // for rebuilds at other block sizes
+  const uint64_t gtab_bytes = (uint64_t)P->grefs.size() * GROUP_TABLE_UINT4 * 16;
+  if (first) P->gtab_reserve = align256(2 * gtab_bytes + 65536);
+  P->gtab_reserve = std::max<uint64_t>(P->gtab_reserve, align256(gtab_bytes));
+  P->gtab_off = align256(P->split_off + P->split_bytes);
+  P->tables_off = align256(P->gtab_off + P->gtab_reserve);
   if (first) P->tables_reserve = align256(4 * (uint64_t)P->image.size() + 65536);
   P->tables_reserve = std::max<uint64_t>(P->tables_reserve, align256(P->image.size()));
   P->total_arena = align256(P->tables_off + P->tables_reserve);

@@ -28,13 +28,15 @@ struct ccut_plan {
   std::vector<ccut::PassDesc> pass_descs;
   std::vector<ccut::StageDesc> stage_descs;
   std::vector<ccut::KOp> kops;
+  std::vector<ccut::GroupRef> grefs;  // MFMA operand tables of the register-stage groups
   std::vector<ccut::SimJob> jobs;
   struct Launch { int job_begin, n_jobs, total_wg; };
   std::vector<Launch> launches;
 
   // Packed table image (ops | passes | jobs | weights) and where it sits in the arena.
   std::vector<unsigned char> image;
-  uint64_t img_ops = 0, img_passes = 0, img_stages = 0, img_jobs = 0, img_weights = 0;
+  uint64_t img_ops = 0, img_passes = 0, img_stages = 0, img_jobs = 0, img_weights = 0, img_grefs = 0;
+  uint64_t gtab_off = 0, gtab_reserve = 0;  // arena region of the MFMA group tables
   uint64_t tables_off = 0;  // arena byte offset of the table region
   uint64_t tables_reserve = 0;  // bytes reserved for it
   uint64_t total_arena = 0; // bytes the caller's arena must hold
@@ -49,6 +51,7 @@ struct ccut_plan {
   int auto_mfma_min_k = -1;  // CCUT_PREC_AUTO threshold on K (-1: library default)
   int merge_epilogue = 1;    // MFMA merge store path: 0 direct, 1 through LDS
   int merge_grid_cap = 0;    // MFMA merge: 0 one workgroup per tile, > 0 persistent grid
+  int sim_precision = CCUT_SIM_FP16X3;  // register-stage gate groups: split-float16 MFMA or float32 VALU
 };
 
 namespace ccut {
@@ -60,7 +63,7 @@ int auto_block_bits(const ccut_plan* P);
 int build_sim_tables(ccut_plan* P, bool first);
 // Appends a pass to the device tables; returns its PassDesc index.
 int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<StageDesc>& stages,
-                std::vector<KOp>& kops);
+                std::vector<KOp>& kops, std::vector<GroupRef>& grefs);
 int gate_matrix(const ccut_gate_t& g, cd m[4]);
 void release_device(DeviceTables& t);
 // Packs the tables into one image with 256-byte aligned sections.

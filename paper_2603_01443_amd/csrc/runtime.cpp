@@ -162,6 +162,22 @@ extern "C" int ccut_plan_set_block_bits(ccut_plan_t* plan, int32_t bits) {
   return CCUT_OK;
 }
 
+extern "C" int ccut_plan_set_sim_precision(ccut_plan_t* plan, int32_t precision) {
+  clear_error();
+  if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
+  if (precision != CCUT_SIM_FP32 && precision != CCUT_SIM_FP16X3)
+    return fail(CCUT_EINVAL, "unknown simulation precision %d", precision);
+  plan->sim_precision = precision;
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_get_sim_precision(const ccut_plan_t* plan, int32_t* out) {
+  clear_error();
+  if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
+  *out = plan->sim_precision;
+  return CCUT_OK;
+}
+
 extern "C" int ccut_plan_get_block_bits(const ccut_plan_t* plan, int32_t* out) {
   clear_error();
   if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");

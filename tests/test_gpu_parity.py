@@ -177,6 +177,31 @@ def test_block_bits_variants_match_oracle(lib, bits):
     assert np.max(np.abs(got - want)) < fp32_tol(q)
 
 
+@pytest.mark.parametrize("prec,bits", [("fp32", 13), ("fp16x3", 13), ("fp32", 11), ("fp16x3", 11),
+                                       ("fp16x3", 9)])
+def test_sim_precisions_match_oracle(lib, prec, bits):
+    """Both gate arithmetics of the simulation (float32 vector ALUs, split-float16
+    MFMA groups) give the oracle's subcircuit states to the float32 tolerance."""
+    ccut, pipeline = lib
+    o = _q26_oracle()
+    run = pipeline.CutRun(26, o["g"], 2)
+    ccut.plan_set_sim_precision(run.plan, prec)
+    assert ccut.plan_get_sim_precision(run.plan) == prec
+    ccut.plan_set_block_bits(run.plan, bits)
+    run.simulate_subcircuits()
+    torch.cuda.synchronize()
+    pcuts = run.plan.cuts()
+    worst = 0.0
+    for i in range(2):
+        for r in range(16):
+            ref = o["ostates"][oracle_key(pcuts, o["ocuts"], i, r)]
+            got = to_np(run.variant_state(i, r))
+            worst = max(worst, metrics.max_abs_error(ref, got))
+            assert metrics.one_minus_fidelity(ref, got) < 1e-9, (prec, bits, i, r)
+    print(f"{prec} bits {bits}: worst max-abs {worst:.3e} (tol {fp32_tol(13):.1e})", flush=True)
+    assert worst < fp32_tol(13)
+
+
 def test_bench_config_sampled(lib):
     """The measured workload (q=28, 14+14, d=20, c_total=6): sampled amplitudes vs the oracle,
     unit norm, and the full cut state against the full uncut state on the GPU."""
