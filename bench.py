@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the merge GEMM from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by
 # a 1 GiB copy (2.0 x FETCH + 1.0 x WRITE); see profiles/.  Only valid for the kernel revision
 # it was measured on: set to None whenever that kernel changes.
-MEASURED_TRAFFIC = {"merge_gemm (fp16x2, v3)": 2.223e9}
+MEASURED_TRAFFIC = {"merge_gemm (fp16x2, v3)": 2.226e9}
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
 
@@ -123,22 +123,21 @@ def main():
     tuned_ms = ccut.autotune(plan0, arena, psi, reps=3, stream=stream)
     log(f"bench: autotuned launch {ccut.plan_get_launch(plan0)} ({tuned_ms:.3f} ms)")
 
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     t_pre = []
     keep = []
 
-    def step(i=None):
+    def step(marks=None):
         t0 = time.perf_counter()
         plan = ccut.cut_plan(Q, garr, NSEG, sizes)   # tables reach the device with the first call
         t_pre.append(time.perf_counter() - t0)
-        if i is not None:
-            ev[i][0].record(stream)
+        if marks:
+            marks[0].record(stream)
         ccut.simulate_subcircuits(plan, arena, stream=stream)
-        if i is not None:
-            ev[i][1].record(stream)
+        if marks:
+            marks[1].record(stream)
         ccut.merge_full_state(plan, arena, psi, prec, stream=stream)
-        if i is not None:
-            ev[i][2].record(stream)
+        if marks:
+            marks[2].record(stream)
         keep.append(plan)   # freed after the timed region (freeing syncs the device)
 
     for _ in range(args.warmup):
@@ -146,23 +145,42 @@ def main():
     torch.cuda.synchronize()
     keep.clear()
     t_pre.clear()
+    used = prec if prec != "auto" else ("fp16x2" if K >= 8 else "fp32")
+    kname = "merge_f32" if used == "fp32" else "merge_gemm"
     log(f"bench: warmup done, timing {args.steps} steps")
+    # Timed region: only the roofline kernel is bracketed by HIP events (on the stream it
+    # is launched on), so the other launches run unperturbed.
     ccut.profile_reset()
+    ccut.profile_mask([kname])
     ccut.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i)
+    for _ in range(args.steps):
+        step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ccut.profile_enable(False)
-    kprof = ccut.profile_read()
+    kprof_timed = ccut.profile_read()
     keep.clear()
     ms_step = 1e3 * wall / args.steps
-    t_sub = [ev[i][0].elapsed_time(ev[i][1]) for i in range(args.steps)]
-    t_merge = [ev[i][1].elapsed_time(ev[i][2]) for i in range(args.steps)]
-    log(f"bench: {ms_step:.3f} ms/step; sub {np.mean(t_sub):.3f} ms, merge {np.mean(t_merge):.3f} ms, "
-        f"pre {1e3 * np.mean(t_pre):.3f} ms")
+    t_pre_ms = 1e3 * float(np.mean(t_pre))
+
+    # Stage breakdown on further (untimed) steps: events between stages, every kernel timed.
+    nb = min(10, max(1, args.steps))
+    marks = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(nb)]
+    ccut.profile_reset()
+    ccut.profile_mask(None)
+    ccut.profile_enable(True)
+    for i in range(nb):
+        step(marks[i])
+    torch.cuda.synchronize()
+    ccut.profile_enable(False)
+    kprof = ccut.profile_read()
+    keep.clear()
+    t_sub = [m[0].elapsed_time(m[1]) for m in marks]
+    t_merge = [m[1].elapsed_time(m[2]) for m in marks]
+    log(f"bench: {ms_step:.3f} ms/step; breakdown (separate steps, all kernels timed): sub "
+        f"{np.mean(t_sub):.3f} ms, merge {np.mean(t_merge):.3f} ms, pre {t_pre_ms:.3f} ms")
 
     # uncut baseline on the same GPU
     ref = torch.empty_like(psi)
@@ -187,29 +205,36 @@ def main():
     merge_ms = float(np.mean(t_merge))
     merge_bytes = 8 * (1 << Q) + 8 * K * ((1 << sizes[0]) + (1 << sizes[1]))
     merge_flops = 8 * K * (1 << Q)
-    used = prec if prec != "auto" else ("fp16x2" if K >= 8 else "fp32")
     kernels_ms = {k: v[1] / v[0] for k, v in kprof.items() if v[0] > 0}
-    kernel_launches = {k: v[0] // args.steps for k, v in kprof.items() if v[0] > 0}
-    if used == "fp32":
-        kname = "merge_f32"
-        k_ms = kernels_ms[kname]
-        if K * 8 > FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9) * 8:
-            roof = {"bound": "alu", "achieved": merge_flops / (k_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
-                    "unit": "TFLOP/s"}
-        else:
-            roof = {"bound": "hbm", "achieved": merge_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s"}
+    kernel_launches = {k: v[0] // nb for k, v in kprof.items() if v[0] > 0}
+    k_launches, k_total = kprof_timed[kname]
+    k_ms = k_total / k_launches
+    if used == "fp32" and K * 8 > FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9) * 8:
+        roof = {"bound": "alu", "achieved": merge_flops / (k_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
     else:
-        kname = "merge_gemm"
-        k_ms = kernels_ms[kname]
         roof = {"bound": "hbm", "achieved": merge_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = f"{kname} ({used}, v{ccut.plan_get_merge(plan0)['variant']})"
     roof["traffic"] = MEASURED_TRAFFIC.get(roof["kernel"])
     roof["avg_ms"] = k_ms
+    roof["launches_timed"] = k_launches
     roof["algorithmic_bytes"] = merge_bytes
     roof["algorithmic_flops"] = merge_flops
+    # Second kernel: the subcircuit simulation, work counted as fused float32 2x2 gates
+    # (16 flop per amplitude per gate) on every variant of both (equal) segments.
+    stats = ccut.plan_stats(plan0)
+    sim_flops = 16.0 * stats["dense_ops"] * (1 << (CTOTAL if NSEG == 2 else 0)) * (1 << sizes[0])
+    sim_ms = kernels_ms.get("sim", 0.0) * kernel_launches.get("sim", 0)
+    roof_sim = None
+    if sim_ms > 0:
+        roof_sim = {"bound": "alu", "achieved": sim_flops / (sim_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "kernel": f"sim ({ccut.plan_get_sim_precision(plan0)} groups, "
+                    f"2^{ccut.plan_get_block_bits(plan0)} blocks)", "avg_ms_per_step": sim_ms,
+                    "algorithmic_flops": sim_flops,
+                    "note": "latency-bound (2 wavefronts per SIMD at this size); from the breakdown steps"}
+        roof_sim["frac"] = roof_sim["achieved"] / roof_sim["peak"]
     log(f"bench: kernels (avg ms per launch) {kernels_ms}")
 
     # achievable HBM bandwidth on this machine: a torch fill (write only) and copy of 2 GiB
@@ -246,12 +271,14 @@ def main():
         "dtype": "c64", "data": "synthetic",
         "config": {"workload": f"brickwork q={Q} n={NSEG} ({sizes[0]}+{sizes[1]}) d={D} c_total={CTOTAL} K={K}",
                    "q": Q, "d": D, "n_seg": NSEG, "c_total": CTOTAL, "seed": SEED, "merge_precision": prec},
-        "stages_ms": {"pre": 1e3 * float(np.mean(t_pre)), "sub": float(np.mean(t_sub)), "merge": merge_ms,
-                      "uncut": t_orig, "uncut_wall": t_orig_wall},
+        "stages_ms": {"pre": t_pre_ms, "sub": float(np.mean(t_sub)), "merge": merge_ms,
+                      "uncut": t_orig, "uncut_wall": t_orig_wall,
+                      "note": "sub/merge from separate steps with every kernel timed"},
         "merge_amps_per_s": (1 << Q) / (merge_ms * 1e-3),
         "cut_vs_uncut": {"speedup": t_orig / ms_step, "one_minus_F": one_minus_f,
                          "norm_drift": abs(stats["norm2"] - 1.0), "max_abs": stats["max_abs"]},
         "roofline": roof,
+        "roofline_sim": roof_sim,
         "kernels_ms": kernels_ms,
         "hbm_probe": probe,
         "kernel_launches_per_step": kernel_launches,

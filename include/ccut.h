@@ -408,6 +408,8 @@ int ccut_decide(int32_t q, int32_t d, int32_t c_total, const float* d_params, do
 int ccut_profile_enable(int32_t on);
 int ccut_profile_read(int32_t kernel, int64_t* launches, double* total_ms, const char** name);
 int ccut_profile_reset(void);
+/* Families timed while enabled: bit k set times family k (default: all). */
+int ccut_profile_mask(uint32_t mask);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* ccut_last_error(void);

@@ -132,6 +132,8 @@ def _load():
     lib.ccut_profile_read.restype = ctypes.c_int
     lib.ccut_profile_reset.argtypes = []
     lib.ccut_profile_reset.restype = ctypes.c_int
+    lib.ccut_profile_mask.argtypes = [ctypes.c_uint32]
+    lib.ccut_profile_mask.restype = ctypes.c_int
     lib.ccut_plan_free.argtypes = [vp]
     lib.ccut_plan_free.restype = None
     lib.ccut_last_error.restype = ctypes.c_char_p
@@ -342,6 +344,15 @@ def decide(q: int, d: int, c_total: int, params=None, budget_s: float = 0.0, mar
 
 def profile_enable(on: bool = True) -> None:
     _check(_lib.ccut_profile_enable(1 if on else 0))
+
+
+PROFILE_KERNELS = ("sim", "merge_f32", "split_R", "split_L", "merge_gemm", "reduce", "mlp")
+
+
+def profile_mask(kernels=None) -> None:
+    """Time only the named kernel families while profiling is on (None: all)."""
+    mask = 0xFFFFFFFF if kernels is None else sum(1 << PROFILE_KERNELS.index(k) for k in kernels)
+    _check(_lib.ccut_profile_mask(mask))
 
 
 def profile_reset() -> None:

@@ -1,7 +1,9 @@
-// Kernel timing.  When enabled, every kernel the library launches is bracketed
-// by a pair of HIP events recorded on the stream it is launched on; reading the
-// profile waits for those events and accumulates launches and milliseconds per
-// kernel family.  Events come from a pool and are reused.
+// Kernel timing.  When enabled, every kernel the library launches (of the
+// families selected by the mask) is bracketed by a pair of HIP events recorded
+// on the stream it is launched on; reading the profile waits for those events
+// and accumulates launches and milliseconds per kernel family.  Events come
+// from a pool and are reused.  Timing events add a little time between
+// launches, so timing only the kernel of interest keeps the rest unperturbed.
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -19,6 +21,7 @@ struct Record {
 
 std::mutex g_mu;
 bool g_on = false;
+uint32_t g_mask = ~0u;  // kernel families that are timed while profiling is on
 std::vector<Record> g_open;
 std::vector<hipEvent_t> g_pool;
 int64_t g_count[PROF_N] = {};
@@ -41,7 +44,7 @@ hipEvent_t take() {
 
 int prof_begin(int kernel, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);
-  if (!g_on) return -1;
+  if (!g_on || !((g_mask >> kernel) & 1u)) return -1;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
   Record r{kernel, take(), take()};
@@ -67,6 +70,13 @@ extern "C" int ccut_profile_enable(int32_t on) {
   clear_error();
   std::lock_guard<std::mutex> lk(g_mu);
   g_on = on != 0;
+  return CCUT_OK;
+}
+
+extern "C" int ccut_profile_mask(uint32_t mask) {
+  clear_error();
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_mask = mask;
   return CCUT_OK;
 }
 
