@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the merge GEMM from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by
 # a 1 GiB copy (2.0 x FETCH + 1.0 x WRITE); see profiles/.  Only valid for the kernel revision
 # it was measured on: set to None whenever that kernel changes.
-MEASURED_TRAFFIC = {"merge_gemm (fp16x2, v3)": 2.226e9}
+MEASURED_TRAFFIC = {"merge_gemm (fp16x2, v3)": 2.224e9}
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
 
@@ -224,8 +224,8 @@ def main():
     roof["algorithmic_flops"] = merge_flops
     # Second kernel: the subcircuit simulation, work counted as fused float32 2x2 gates
     # (16 flop per amplitude per gate) on every variant of both (equal) segments.
-    stats = ccut.plan_stats(plan0)
-    sim_flops = 16.0 * stats["dense_ops"] * (1 << (CTOTAL if NSEG == 2 else 0)) * (1 << sizes[0])
+    pstats = ccut.plan_stats(plan0)
+    sim_flops = 16.0 * pstats["dense_ops"] * (1 << (CTOTAL if NSEG == 2 else 0)) * (1 << sizes[0])
     sim_ms = kernels_ms.get("sim", 0.0) * kernel_launches.get("sim", 0)
     roof_sim = None
     if sim_ms > 0:

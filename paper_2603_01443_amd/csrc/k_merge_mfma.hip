@@ -256,7 +256,10 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
               const int row = (v & 3) + 4 * (lane >> 5) + 8 * ((v >> 2) & 1);
               my[row * EPI_LDS_ROW + c * 32 + (lane & 31)] = acc[r][c][v];
             }
-          __syncthreads();
+          // the slab is this wavefront's own: its LDS ops execute in order, so a
+          // wavefront-scope fence (no workgroup barrier) orders the writes and reads
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
           // lanes 0..31 cover one 128-float row, lanes 32..63 the next
           const uint64_t col0 = (uint64_t)cb0 * 32 + 4 * (lane & 31);
 #pragma unroll
@@ -267,7 +270,8 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
             const uint64_t grow = (uint64_t)(rb0 + r) * 32 + 16 * h + row;
             __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(ob + grow * ncols + col0));
           }
-          __syncthreads();
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
         }
       }
     }
