@@ -5,6 +5,7 @@
     python -m paper_2603_01443_amd.experiments batching   --out results/batching_q32_n3.json
     python -m paper_2603_01443_amd.experiments costmodel  --out results/cost_model.json
     python -m paper_2603_01443_amd.experiments gemm       --out results/merge_gemm_variants.json
+    python -m paper_2603_01443_amd.experiments paper      --out results/paper_family.json
 
 sweep      Random brickwork, q = 24 in two blocks of 12, d in {10, 20, 40},
            c_total in {0, 1, 2, 3, 4, 6} (extended to 12 when cutting still
@@ -25,6 +26,14 @@ costmodel  Timing grid q in {16, ..., 32} x d in {10, 20, 40} x n in {2, 3, 4} x
            network is trained on the GPU (seeds 0, 1, q < 32) and the learned
            cut/no-cut choice is compared with the closed-form rule on the held-out
            rows by measured wall clock.
+paper      The paper's own circuit family (Fig. 1: H layer, then one CX staircase
+           with T gates per cut): the Delta heat maps of Sec. V.B (n = 2: q = 2..24,
+           c_total = 1..10; n = 3: q = 3..24, c_total = 2..14), the depth sweep of
+           Sec. V.D (10^p T/X layers on the first and last qubit, p = 0, 2, 3, 4),
+           the runtime breakdown against depth (q = 24, c = 10, n = 2; App. C) and
+           the largest q that fits a (scaled) wall-clock budget, uncut and with a
+           two-way cut of c_total = 6 (Sec. V.D).  Each map gets a weighted linear
+           SVM boundary c_total = a q + b, set beside the closed-form threshold.
 
 Timings: host wall clock for T_pre (cut_plan); HIP events on the stream for the
 device stages; warm-up runs first, then the mean of the timed repeats.
@@ -47,7 +56,7 @@ if ROOT not in sys.path:
 
 import torch  # noqa: E402
 
-from inputs import brickwork, equal_blocks, split_cuts  # noqa: E402
+from inputs import brickwork, equal_blocks, split_cuts, staircase  # noqa: E402
 from paper_2603_01443_amd import ccut  # noqa: E402
 
 
@@ -434,9 +443,102 @@ def run_gemm(args):
     return out
 
 
+
+# ------------------------------------------------------------------ paper family
+def svm_boundary(rows):
+    """Weighted linear SVM on the sign of Delta over the (q, c_total) plane (the paper
+    fits one to each heat map; its weights are not given, here every point is weighted
+    by |Delta|).  Returns (a, b) of the boundary c_total = a q + b, or None when the
+    map has only one sign."""
+    from sklearn.svm import LinearSVC
+    pts = np.array([[r["q"], r["c_total"]] for r in rows], dtype=float)
+    y = np.array([1 if r["delta"] < 0 else 0 for r in rows])
+    if y.min() == y.max():
+        return None
+    w = np.array([max(abs(r["delta"]), 1e-3) for r in rows])
+    mu, sd = pts.mean(axis=0), pts.std(axis=0) + 1e-12
+    clf = LinearSVC(C=10.0, max_iter=200000).fit((pts - mu) / sd, y, sample_weight=w)
+    (wq, wc), b0 = clf.coef_[0] / sd, clf.intercept_[0] - float(np.dot(clf.coef_[0], mu / sd))
+    if abs(wc) < 1e-12:
+        return None
+    return float(-wq / wc), float(-b0 / wc)
+
+
+def paper_cut_row(q, n, c, tx, bufs, reps, t_orig_cache):
+    copies = c if n == 2 else c // (n - 1)
+    g = staircase(q, copies, tx_layers=tx)
+    sizes = equal_blocks(q, n)
+    key = (q, tx, copies)
+    if key not in t_orig_cache:
+        t_orig_cache[key] = time_uncut(q, g, bufs, reps=reps)
+    t_orig = t_orig_cache[key]
+    pre, sub, mer, plan = time_cut(q, g, n, sizes, bufs, reps=reps)
+    ct = plan.info()["c_total"]
+    assert ct == c, (q, n, c, ct)
+    t_cut = pre + sub + mer
+    return {"q": q, "n": n, "c_total": c, "tx_layers": tx, "gates": len(g), "T_pre": pre, "T_sub": sub,
+            "T_merge": mer, "T_cut": t_cut, "T_orig": t_orig, "delta": (t_cut - t_orig) / t_orig}
+
+
+def run_paper(args):
+    bufs = Buffers()
+    reps = args.reps
+    out = {"experiment": "paper circuit family (Fig. 1 staircase, CX cuts)", "heatmaps": {}, "depth_sweep": {}}
+    cache = {}
+    grids = {2: [(q, c) for q in range(2, 25, 2) for c in range(1, 11)],
+             3: [(q, c) for q in range(3, 25, 3) for c in range(2, 15, 2)]}
+    if args.quick:
+        grids = {2: [(q, c) for q in (4, 12, 20) for c in (1, 5, 10)], 3: [(q, c) for q in (6, 18) for c in (2, 8)]}
+    for n, grid in grids.items():
+        rows = []
+        for q, c in grid:
+            rows.append(paper_cut_row(q, n, c, 0, bufs, reps, cache))
+            log(f"paper heat n={n} q={q} c={c}: cut {rows[-1]['T_cut']*1e3:.3f} ms orig "
+                f"{rows[-1]['T_orig']*1e3:.3f} ms delta {rows[-1]['delta']:+.3f}")
+        qs = sorted({q for q, _ in grid})
+        out["heatmaps"][str(n)] = {
+            "rows": rows, "svm_boundary_a_b": svm_boundary(rows),
+            "closed_form_threshold": {str(q): ccut.threshold_ctotal(q, n) for q in qs},
+            "paper_svm_boundary_a_b": [0.70, -7.30] if n == 2 else [1.00, -11.50]}
+    # depth sweep: the n = 2 grid at 10^p padding layers
+    ps = (0, 2, 3, 4) if not args.quick else (0, 3)
+    for p in ps:
+        tx = 10 ** p
+        rows = []
+        for q, c in grids[2]:
+            rows.append(paper_cut_row(q, 2, c, tx, bufs, reps, cache))
+        out["depth_sweep"][str(p)] = {"tx_layers": tx, "rows": rows, "svm_boundary_a_b": svm_boundary(rows)}
+        log(f"paper depth p={p}: boundary {out['depth_sweep'][str(p)]['svm_boundary_a_b']}")
+    # runtime breakdown against depth, q = 24, c = 10, n = 2
+    bd = []
+    for tx in ((1, 10, 100, 300, 1000, 3000, 10000) if not args.quick else (1, 1000)):
+        r = paper_cut_row(24, 2, 10, tx, bufs, reps, cache)
+        bd.append(r)
+        log(f"paper breakdown tx={tx}: pre {r['T_pre']*1e3:.3f} sub {r['T_sub']*1e3:.3f} merge "
+            f"{r['T_merge']*1e3:.3f} orig {r['T_orig']*1e3:.3f} ms")
+    out["breakdown_q24_c10"] = bd
+    # largest q within a wall-clock budget: uncut vs two-way cut with c_total = 6
+    budget = args.budget_ms * 1e-3
+    feas = {}
+    for p in ps:
+        tx = 10 ** p
+        best = {"uncut": None, "cut_n2_c6": None}
+        for q in range(16, 33 if not args.quick else 21, 2):
+            r = paper_cut_row(q, 2, 6, tx, bufs, 1, cache)
+            if r["T_orig"] <= budget:
+                best["uncut"] = q
+            if r["T_cut"] <= budget:
+                best["cut_n2_c6"] = q
+        feas[str(p)] = best
+        log(f"paper budget {args.budget_ms} ms p={p}: {best}")
+    out["max_feasible_q"] = {"budget_ms": args.budget_ms, "by_p": feas,
+                             "paper_10min_cpu": {"uncut": "22-26", "cut_n2_c6": "28-30"}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["sweep", "precision", "batching", "costmodel", "gemm"])
+    ap.add_argument("which", choices=["sweep", "precision", "batching", "costmodel", "gemm", "paper"])
     ap.add_argument("--out", required=True)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--epochs", type=int, default=3000)
@@ -448,7 +550,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("experiments need a GPU")
     fn = {"sweep": run_sweep, "precision": run_precision, "batching": run_batching, "costmodel": run_costmodel,
-          "gemm": run_gemm}
+          "gemm": run_gemm, "paper": run_paper}
     res = fn[args.which](args)
     res["device"] = torch.cuda.get_device_name(0)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
