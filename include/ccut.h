@@ -296,17 +296,34 @@ int ccut_plan_set_block_bits(ccut_plan_t* plan, int32_t bits);
 int ccut_plan_get_block_bits(const ccut_plan_t* plan, int32_t* out);
 
 /*
- * Autotuner: times the simulation kernel over LDS block sizes (whole segment,
- * 2 and 4 blocks per state; sizes whose tables do not fit arena_bytes are
- * skipped) x workgroup sizes x persistent grid sizes, and the merge with the
+ * Prefix sharing in the subcircuit simulation (Algorithm 2 re-simulates the
+ * gates before a cut for every variant).  mode 1: each segment program is cut
+ * before each of its slotted ops (in program order); level l holds the 2^l
+ * states of the first l slot choices and level l + 1 applies the next chunk to
+ * each, once per choice of its slot, so the gates before a slot run once per
+ * prefix instead of once per variant.  One launch per level and LDS pass;
+ * levels below the last use a scratch region of the arena.  mode 0: every
+ * variant from |0...0> in one launch per pass.  mode -1 (default): on when the
+ * variants hold at least 2^23 amplitudes in all.  Results agree to float32
+ * rounding.  Host-only; reschedules the plan.  Errors: CCUT_EINVAL.
+ */
+int ccut_plan_set_prefix_sharing(ccut_plan_t* plan, int32_t mode);
+/* 1 if the plan's tables use prefix sharing, else 0 (host-only). */
+int ccut_plan_get_prefix_sharing(const ccut_plan_t* plan, int32_t* out);
+
+/*
+ * Autotuner: times the simulation kernel over prefix sharing off / on x LDS
+ * block sizes (whole segment, 2 and 4 blocks per state; sizes whose tables do
+ * not fit arena_bytes are skipped) x workgroup sizes x persistent grid sizes,
+ * and the merge with the
  * float32 kernel against the split-precision MFMA GEMM over its variants and
  * grids (median of `reps` runs, HIP events on `stream`), applies the fastest
  * to the plan and records it in a process-wide cache keyed by (architecture,
  * plan shape); later plans of the same shape start from it.  Overwrites the
  * arena and d_psi.  *best_ms (nullable) receives the tuned simulation + merge
  * time.  ccut_autotune_save / _load write and read the cache as text (one
- * "key threads grid_cap mfma_min_terms epilogue merge_grid block_bits" line
- * per entry).
+ * "key threads grid_cap mfma_min_terms epilogue merge_grid block_bits prefix"
+ * line per entry).
  * Errors: CCUT_EINVAL, CCUT_ENOSPC, CCUT_EHIP.
  */
 int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* d_psi, uint64_t psi_bytes,

@@ -111,6 +111,8 @@ def _load():
         "ccut_plan_get_merge": [vp, ctypes.POINTER(i32)],
         "ccut_plan_set_block_bits": [vp, i32],
         "ccut_plan_set_sim_precision": [vp, i32],
+        "ccut_plan_set_prefix_sharing": [vp, i32],
+        "ccut_plan_get_prefix_sharing": [vp, ctypes.POINTER(i32)],
         "ccut_plan_get_sim_precision": [vp, ctypes.POINTER(i32)],
         "ccut_plan_get_block_bits": [vp, ctypes.POINTER(i32)],
         "ccut_plan_stats": [vp, ctypes.POINTER(i64)],
@@ -404,6 +406,17 @@ def plan_get_sim_precision(plan: Plan) -> str:
     out = ctypes.c_int32(0)
     _check(_lib.ccut_plan_get_sim_precision(plan.handle, ctypes.byref(out)))
     return {v: k for k, v in SIM_PRECISIONS.items()}[int(out.value)]
+
+
+def plan_set_prefix_sharing(plan: Plan, mode: int) -> None:
+    """Prefix sharing in the subcircuit simulation: 0 off, 1 on, -1 automatic."""
+    _check(_lib.ccut_plan_set_prefix_sharing(plan.handle, int(mode)))
+
+
+def plan_get_prefix_sharing(plan: Plan) -> bool:
+    out = ctypes.c_int32(0)
+    _check(_lib.ccut_plan_get_prefix_sharing(plan.handle, ctypes.byref(out)))
+    return bool(out.value)
 
 
 def plan_get_block_bits(plan: Plan) -> int:

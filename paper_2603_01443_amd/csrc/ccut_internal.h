@@ -131,24 +131,29 @@ struct PassDesc {
   int32_t stage_count;
   int32_t group[24]; // local bit j -> register qubit
   int32_t fixed[24]; // j-th non-group qubit (ascending), takes bit j of the block id
+  int32_t from_src;  // 1: read the job's source state (SimJob::src_off) instead of its own
+  int32_t pad;
 };
 
 struct Pass {
   std::vector<int32_t> group;  // size b, low qubits first
   std::vector<KOp> kops;       // block-level ops (local bits)
   bool init = false;
+  bool from_src = false;
 };
 
 // Splits a pass's block-level ops into register stages (stage-level op encoding).
 void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& stages, std::vector<KOp>& out);
 
 // Schedule a program into LDS-blocked passes of at most 2^bmax amplitudes.
-// Low qubits [0, low_bits) sit in every block (coalesced runs).
-int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out);
+// Low qubits [0, low_bits) sit in every block (coalesced runs).  The first pass
+// starts from |0...0> (from_zero) or from a source state the job names.
+int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out, bool from_zero = true);
 
 // A launch entry: one state (or a batch position) processed by one pass.
 struct SimJob {
   uint64_t state_off;  // complex64 elements from the launch base pointer
+  uint64_t src_off;    // state read by a from_src pass (prefix sharing: the parent state)
   int32_t pass_id;     // into the PassDesc table
   int32_t variant;
   int32_t wg_begin;    // first workgroup of this job in the launch

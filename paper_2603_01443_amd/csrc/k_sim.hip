@@ -28,6 +28,9 @@
 // its lane.  The state is scaled by 2^14 while a pass runs so that the low
 // halves of typical amplitudes stay normal float16 numbers.
 //
+// A pass may start from another state than the one it writes (prefix sharing:
+// a variant's chunk applied to its parent's state).
+//
 // One launch covers a list of jobs (state, pass, variant); a grid-stride loop
 // over the job list makes the launch persistent when the grid is smaller than
 // the work.
@@ -338,6 +341,7 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
     uint64_t blockbase = 0;
     for (int j = 0; j < nfix; ++j) blockbase |= (uint64_t)((blk >> j) & 1u) << P->fixed[j];
     float2* st = base + job.state_off;
+    const float2* src = P->from_src ? base + job.src_off : st;  // prefix sharing: the parent state
 
     // offset tables: scatter of local bits 0..6 and 7..b-1 into register positions
     const int blo = b < 7 ? b : 7;
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
       if (tid == 0 && blockbase == 0) sh[0] = make_float2(scale_in, 0.f);
     } else {
       for (int i = tid; i < nb; i += NT) {
-        const float2 v = st[blockbase + lo_tab[i & (TAB - 1)] + hi_tab[i >> 7]];
+        const float2 v = src[blockbase + lo_tab[i & (TAB - 1)] + hi_tab[i >> 7]];
         sh[pad(i)] = make_float2(v.x * scale_in, v.y * scale_in);
       }
     }

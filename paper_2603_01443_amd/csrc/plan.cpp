@@ -23,6 +23,7 @@ int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector
   d.op_begin = (int32_t)kops.size();
   d.op_count = (int32_t)p.kops.size();
   d.init = p.init ? 1 : 0;
+  d.from_src = p.from_src ? 1 : 0;
   d.n_blocks = 1 << (nq - d.b);
   std::vector<uint8_t> in(nq, 0);
   for (int j = 0; j < d.b; ++j) {
@@ -76,12 +77,100 @@ int auto_block_bits(const ccut_plan* P) {
   return b;
 }
 
+// Prefix sharing pays once the variants carry enough work to fill the device by
+// themselves (then the stage is throughput-bound and shared prefixes are saved
+// work); below that the sequential gate chain of one state sets the time.
+bool auto_prefix(const ccut_plan* P) {
+  uint64_t amps = 0;
+  bool any = false;
+  for (const auto& S : P->segs) {
+    amps += ((uint64_t)1 << S.c) << S.q;
+    any = any || S.c > 0;
+  }
+  return any && amps >= ((uint64_t)1 << AUTO_PREFIX_LOG2_AMPS);
+}
+
+// Prefix sharing (a tree over the slots in program order): level l holds the 2^l
+// states of the first l slot choices; level l + 1 applies chunk l + 1 (which
+// starts at slot l + 1's op) to each of them, once per choice of that slot.
+// Levels below c live in a ping-pong scratch, level c is the arena layout.
+int build_tree_launches(ccut_plan* P) {
+  const int n_seg = P->n_seg;
+  int max_c = 0;
+  for (auto& S : P->segs) {
+    S.chunk_passes.clear();
+    S.chunk_slot.clear();
+    std::vector<int> pos;
+    for (int o = 0; o < (int)S.prog.ops.size(); ++o)
+      if (S.prog.ops[o].slot >= 0) {
+        pos.push_back(o);
+        S.chunk_slot.push_back(S.prog.ops[o].slot);
+      }
+    if ((int)pos.size() != S.c) return fail(CCUT_EINVAL, "segment program has %zu slotted ops for %d cuts",
+                                            pos.size(), S.c);
+    for (int l = 0; l <= S.c; ++l) {
+      Program chunk;
+      chunk.nq = S.prog.nq;
+      const int begin = l == 0 ? 0 : pos[l - 1];
+      const int end = l < S.c ? pos[l] : (int)S.prog.ops.size();
+      chunk.ops.assign(S.prog.ops.begin() + begin, S.prog.ops.begin() + end);
+      std::vector<Pass> passes;
+      if (int rc = schedule_passes(chunk, P->bmax, P->low_bits, passes, l == 0)) return rc;
+      S.chunk_passes.push_back(std::move(passes));
+    }
+    max_c = std::max(max_c, S.c);
+  }
+  for (int l = 0; l <= max_c; ++l) {
+    size_t max_passes = 0;
+    for (auto& S : P->segs)
+      if (l <= S.c) max_passes = std::max(max_passes, S.chunk_passes[l].size());
+    for (size_t p = 0; p < max_passes; ++p) {
+      ccut_plan::Launch L{(int)P->jobs.size(), 0, 0};
+      std::vector<int> order;
+      for (int i = 0; i < n_seg; ++i)
+        if (l <= P->segs[i].c && P->segs[i].chunk_passes[l].size() > p) order.push_back(i);
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P->segs[a].q > P->segs[b].q; });
+      for (int i : order) {
+        auto& S = P->segs[i];
+        int pid = append_pass(S.chunk_passes[l][p], S.q, P->pass_descs, P->stage_descs, P->kops, P->grefs);
+        int nb = P->pass_descs[pid].n_blocks;
+        const uint64_t half = S.c > 0 ? ((uint64_t)1 << (S.c - 1)) << S.q : 0;  // elements per ping-pong half
+        for (int64_t u = 0; u < ((int64_t)1 << l); ++u) {
+          int32_t variant = 0;
+          for (int j = 0; j < l; ++j) variant |= (int32_t)(((u >> j) & 1) << S.chunk_slot[j]);
+          SimJob j;
+          std::memset(&j, 0, sizeof(j));
+          j.state_off = l == S.c ? S.arena_off / 8 + ((uint64_t)variant << S.q)
+                                 : S.tree_off / 8 + (uint64_t)(l % 2) * half + ((uint64_t)u << S.q);
+          if (l > 0) {
+            const int64_t parent = u & ((int64_t(1) << (l - 1)) - 1);
+            j.src_off = S.tree_off / 8 + (uint64_t)((l - 1) % 2) * half + ((uint64_t)parent << S.q);
+          } else {
+            j.src_off = j.state_off;
+          }
+          j.pass_id = pid;
+          j.variant = variant;
+          j.wg_begin = L.total_wg;
+          if ((int64_t)L.total_wg + nb > ((int64_t)1 << 31) - 1)
+            return fail(CCUT_EUNSUPPORTED, "simulation launch exceeds 2^31 workgroups");
+          L.total_wg += nb;
+          P->jobs.push_back(j);
+          L.n_jobs++;
+        }
+      }
+      P->launches.push_back(L);
+    }
+  }
+  return 0;
+}
+
 // Schedules every segment program into LDS passes of at most 2^bmax amplitudes
 // and rebuilds the simulation launches and the packed table image.  The table
 // region of the arena is reserved at plan creation with room for later
 // rebuilds at other block sizes; a rebuild that outgrows it enlarges the arena.
 int build_sim_tables(ccut_plan* P, bool first) {
   P->bmax = P->block_bits > 0 ? P->block_bits : auto_block_bits(P);
+  P->prefix_on = P->prefix_mode == 1 || (P->prefix_mode < 0 && auto_prefix(P));
   P->pass_descs.clear();
   P->stage_descs.clear();
   P->kops.clear();
@@ -91,6 +180,9 @@ int build_sim_tables(ccut_plan* P, bool first) {
   for (auto& S : P->segs)
     if (int rc = schedule_passes(S.prog, P->bmax, P->low_bits, S.passes)) return rc;
   const int n_seg = P->n_seg;
+  if (P->prefix_on) {
+    if (int rc = build_tree_launches(P)) return rc;
+  } else {
   // Simulation launches: pass p of every segment that has one, all variants.
   size_t max_passes = 0;
   for (auto& S : P->segs) max_passes = std::max(max_passes, S.passes.size());
@@ -121,6 +213,7 @@ int build_sim_tables(ccut_plan* P, bool first) {
     }
     P->launches.push_back(L);
   }
+  }
 
   pack_image(P);
   if (P->dev.blob) {  // a captured graph may still read the old copy: keep it until the plan is freed
@@ -132,7 +225,8 @@ int build_sim_tables(ccut_plan* P, bool first) {
   const uint64_t gtab_bytes = (uint64_t)P->grefs.size() * GROUP_TABLE_UINT4 * 16;
   if (first) P->gtab_reserve = align256(2 * gtab_bytes + 65536);
   P->gtab_reserve = std::max<uint64_t>(P->gtab_reserve, align256(gtab_bytes));
-  P->gtab_off = align256(P->split_off + P->split_bytes);
+  P->tree_off = align256(P->split_off + P->split_bytes);
+  P->gtab_off = align256(P->tree_off + P->tree_bytes);
   P->tables_off = align256(P->gtab_off + P->gtab_reserve);
   if (first) P->tables_reserve = align256(4 * (uint64_t)P->image.size() + 65536);
   P->tables_reserve = std::max<uint64_t>(P->tables_reserve, align256(P->image.size()));
@@ -345,6 +439,14 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
     const uint64_t r_batch = st.a_bstride ? (uint64_t)st.batch : 1;
     const uint64_t u4 = (uint64_t)st.batch * mfma_l_plane(st.qy, S) + r_batch * mfma_r_plane(st.qx, S);
     P->split_bytes = std::max(P->split_bytes, align256(2 * 16 * u4));
+  }
+  // Prefix-sharing scratch: two ping-pong halves of 2^(c_i - 1) states per segment
+  // (reserved in both modes, so that switching the mode keeps the arena size).
+  P->tree_off = align256(P->split_off + P->split_bytes);
+  P->tree_bytes = 0;
+  for (auto& S : P->segs) {
+    S.tree_off = P->tree_off + P->tree_bytes;
+    if (S.c > 0) P->tree_bytes = align256(P->tree_bytes + (((uint64_t)8 << S.q) << S.c));
   }
 
   // MFMA merge tile: 64-row tiles while operand loads are light (K <= 64), else 128-row

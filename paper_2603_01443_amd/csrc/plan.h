@@ -11,6 +11,11 @@ struct ccut_plan {
     uint64_t arena_off = 0;       // bytes
     ccut::Program prog;
     std::vector<ccut::Pass> passes;
+    // prefix sharing: the program cut before each slotted op (level l >= 1 starts at the
+    // op of slot chunk_slot[l - 1]); chunk_passes[l] are the LDS passes of chunk l
+    std::vector<std::vector<ccut::Pass>> chunk_passes;
+    std::vector<int32_t> chunk_slot;
+    uint64_t tree_off = 0;  // bytes: ping-pong scratch of the prefix levels 0..c-1
   };
   int32_t q = 0, n_seg = 0, n_gates = 0;
   std::vector<Seg> segs;
@@ -25,6 +30,8 @@ struct ccut_plan {
   // simulation launches: one per pass index, jobs for every (segment, variant)
   int bmax = ccut::PASS_MAX_B, low_bits = 4;  // bmax: block bits in use
   int block_bits = 0;                         // requested block bits, 0: automatic
+  int prefix_mode = -1;                       // prefix sharing: 0 off, 1 on, -1 automatic
+  bool prefix_on = false;                     // in use by the current tables
   std::vector<ccut::PassDesc> pass_descs;
   std::vector<ccut::StageDesc> stage_descs;
   std::vector<ccut::KOp> kops;
@@ -37,6 +44,7 @@ struct ccut_plan {
   std::vector<unsigned char> image;
   uint64_t img_ops = 0, img_passes = 0, img_stages = 0, img_jobs = 0, img_weights = 0, img_grefs = 0;
   uint64_t gtab_off = 0, gtab_reserve = 0;  // arena region of the MFMA group tables
+  uint64_t tree_off = 0, tree_bytes = 0;    // arena region of the prefix-sharing scratch
   uint64_t tables_off = 0;  // arena byte offset of the table region
   uint64_t tables_reserve = 0;  // bytes reserved for it
   uint64_t total_arena = 0; // bytes the caller's arena must hold
@@ -57,6 +65,8 @@ struct ccut_plan {
 namespace ccut {
 constexpr int AUTO_TARGET_WG = 256;      // workgroups the first simulation launch should reach (one per CU)
 constexpr int AUTO_MIN_BLOCK_BITS = 12;  // smallest block the automatic choice goes down to
+constexpr int AUTO_PREFIX_LOG2_AMPS = 23;  // automatic prefix sharing from 2^23 variant amplitudes on
+bool auto_prefix(const ccut_plan* P);
 uint64_t align256(uint64_t x);
 int auto_block_bits(const ccut_plan* P);
 // (Re)schedules the simulation at the plan's block size and repacks its tables.

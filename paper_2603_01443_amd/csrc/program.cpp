@@ -352,7 +352,7 @@ void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& sta
   }
 }
 
-int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out) {
+int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out, bool from_zero) {
   out.clear();
   const int nq = prog.nq;
   std::vector<int> pending(prog.ops.size());
@@ -360,7 +360,8 @@ int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pas
   if (nq <= bmax) {
     Pass p;
     for (int j = 0; j < nq; ++j) p.group.push_back(j);
-    p.init = true;
+    p.init = from_zero;
+    p.from_src = !from_zero;
     localize(prog, pending, p.group, p.kops);
     out.push_back(std::move(p));
     return 0;
@@ -405,7 +406,8 @@ int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pas
     if (take.empty() && !first) return fail(CCUT_EINVAL, "pass scheduler made no progress");
     Pass p;
     p.group = group;
-    p.init = first;
+    p.init = first && from_zero;
+    p.from_src = first && !from_zero;
     localize(prog, take, group, p.kops);
     out.push_back(std::move(p));
     pending.swap(keep);

@@ -29,6 +29,7 @@ struct TuneEntry {
   int epilogue = 0;
   int merge_grid = 0;
   int block_bits = 0;
+  int prefix = -1;
 };
 
 std::mutex g_tune_mu;
@@ -91,6 +92,7 @@ void apply_tuned(ccut_plan* P) {
   P->merge_epilogue = it->second.epilogue;
   P->merge_grid_cap = it->second.merge_grid;
   P->block_bits = it->second.block_bits;
+  P->prefix_mode = it->second.prefix;
 }
 
 }  // namespace ccut
@@ -178,6 +180,27 @@ extern "C" int ccut_plan_get_sim_precision(const ccut_plan_t* plan, int32_t* out
   return CCUT_OK;
 }
 
+extern "C" int ccut_plan_set_prefix_sharing(ccut_plan_t* plan, int32_t mode) {
+  clear_error();
+  if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
+  if (mode < -1 || mode > 1) return fail(CCUT_EINVAL, "prefix sharing mode %d (0 off, 1 on, -1 automatic)", mode);
+  const int saved = plan->prefix_mode;
+  plan->prefix_mode = mode;
+  if (int rc = build_sim_tables(plan, false)) {
+    plan->prefix_mode = saved;
+    (void)build_sim_tables(plan, false);
+    return rc;
+  }
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_get_prefix_sharing(const ccut_plan_t* plan, int32_t* out) {
+  clear_error();
+  if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
+  *out = plan->prefix_on ? 1 : 0;
+  return CCUT_OK;
+}
+
 extern "C" int ccut_plan_get_block_bits(const ccut_plan_t* plan, int32_t* out) {
   clear_error();
   if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
@@ -211,19 +234,24 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   const int saved_pv = plan->sim_per_variant;
   plan->sim_per_variant = 0;
   float best = 1e30f;
-  int bt = plan->sim_threads, bg = plan->sim_grid_cap, bb = plan->bmax;
-  const int saved_bits = plan->block_bits;
+  int bt = plan->sim_threads, bg = plan->sim_grid_cap, bb = plan->bmax, bpre = plan->prefix_on ? 1 : 0;
+  const int saved_bits = plan->block_bits, saved_prefix = plan->prefix_mode;
+  bool any_cut = false;
+  for (const auto& S : plan->segs) any_cut = any_cut || S.c > 0;
   const int threads[3] = {256, 512, 1024};
   const int caps[5] = {0, 256, 512, 1024, 2048};
   int qmax = 0;
   for (const auto& S : plan->segs) qmax = std::max(qmax, S.q);
-  // block sizes: whole segment states in LDS, then 2 and 4 blocks per state
+  // prefix sharing off / on x block sizes: whole segment states in LDS, then 2 and 4 blocks
+  for (int pre = 0; pre <= (any_cut ? 1 : 0); ++pre)
   for (int bits = std::min(qmax, PASS_MAX_B); bits >= std::max(plan->low_bits + 1, std::min(qmax, PASS_MAX_B) - 2);
        --bits) {
     plan->block_bits = bits;
+    plan->prefix_mode = pre;
     if (int rc = build_sim_tables(plan, false)) {
       plan->sim_per_variant = saved_pv;
       plan->block_bits = saved_bits;
+      plan->prefix_mode = saved_prefix;
       (void)build_sim_tables(plan, false);
       return rc;
     }
@@ -240,16 +268,18 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
         if (rc) {
           plan->sim_per_variant = saved_pv;
           plan->block_bits = saved_bits;
+          plan->prefix_mode = saved_prefix;
           (void)build_sim_tables(plan, false);
           return rc;
         }
-        if (ms < best) { best = ms; bt = t; bg = c; bb = bits; }
+        if (ms < best) { best = ms; bt = t; bg = c; bb = bits; bpre = pre; }
       }
     }
   }
   plan->sim_threads = bt;
   plan->sim_grid_cap = bg;
   plan->block_bits = bb;
+  plan->prefix_mode = bpre;
   if (int rc = build_sim_tables(plan, false)) {
     plan->sim_per_variant = saved_pv;
     return rc;
@@ -283,7 +313,7 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   plan->auto_mfma_min_k = tmf < t32 ? 1 : kmax + 1;
   if (best_ms) *best_ms = best + std::min(t32, tmf);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[arch_name() + "|" + signature(plan)] = TuneEntry{bt, bg, plan->auto_mfma_min_k, best_epi, best_grid, bb};
+  g_tune[arch_name() + "|" + signature(plan)] = TuneEntry{bt, bg, plan->auto_mfma_min_k, best_epi, best_grid, bb, bpre};
   return CCUT_OK;
 }
 
@@ -293,10 +323,11 @@ extern "C" int ccut_autotune_save(const char* path) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(CCUT_EINVAL, "cannot write %s", path);
-  std::fprintf(f, "# ccut autotune cache: key threads grid_cap mfma_min_k epilogue merge_grid block_bits\n");
+  std::fprintf(f, "# ccut autotune cache: key threads grid_cap mfma_min_k epilogue merge_grid block_bits prefix\n");
   for (const auto& kv : g_tune)
-    std::fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.threads, kv.second.grid_cap,
-                 kv.second.mfma_min_k, kv.second.epilogue, kv.second.merge_grid, kv.second.block_bits);
+    std::fprintf(f, "%s %d %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.threads, kv.second.grid_cap,
+                 kv.second.mfma_min_k, kv.second.epilogue, kv.second.merge_grid, kv.second.block_bits,
+                 kv.second.prefix);
   std::fclose(f);
   return CCUT_OK;
 }
@@ -307,15 +338,15 @@ extern "C" int ccut_autotune_load(const char* path) {
   FILE* f = std::fopen(path, "r");
   if (!f) return fail(CCUT_EINVAL, "cannot read %s", path);
   char key[1024];
-  int t, c, k, ep, mg, bb;
+  int t, c, k, ep, mg, bb, pf;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   char line[1200];
   while (std::fgets(line, sizeof(line), f)) {
     if (line[0] == '#') continue;
-    if (std::sscanf(line, "%1023s %d %d %d %d %d %d", key, &t, &c, &k, &ep, &mg, &bb) == 7 &&
+    if (std::sscanf(line, "%1023s %d %d %d %d %d %d %d", key, &t, &c, &k, &ep, &mg, &bb, &pf) == 8 &&
         (t == 256 || t == 512 || t == 1024) && c >= 0 && k >= -1 && ep >= 0 && ep <= 3 && mg >= 0 &&
-        (bb == 0 || (bb > 4 && bb <= PASS_MAX_B)))
-      g_tune[key] = TuneEntry{t, c, k, ep, mg, bb};
+        (bb == 0 || (bb > 4 && bb <= PASS_MAX_B)) && pf >= -1 && pf <= 1)
+      g_tune[key] = TuneEntry{t, c, k, ep, mg, bb, pf};
   }
   std::fclose(f);
   return CCUT_OK;

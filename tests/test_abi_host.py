@@ -143,3 +143,28 @@ def test_block_bits_reschedule():
         with pytest.raises(ccut.CcutError):
             ccut.plan_set_block_bits(plan, bad)
     assert ccut.plan_get_block_bits(plan) == 13
+
+
+def test_prefix_sharing_tree_shape():
+    """Prefix sharing: one launch per tree level (single-pass segments), 2^l jobs per
+    segment at level l, final level at the variants; automatic mode by total size."""
+    q, n = 20, 2
+    g = brickwork(q, 10, n, 4, seed=3)
+    plan = ccut.cut_plan(q, g, n)
+    assert not ccut.plan_get_prefix_sharing(plan)        # 2 x 16 x 2^10 amplitudes: below the automatic bar
+    flat = ccut.plan_stats(plan)
+    arena = plan.info()["arena_bytes"]
+    ccut.plan_set_prefix_sharing(plan, 1)
+    assert ccut.plan_get_prefix_sharing(plan)
+    tree = ccut.plan_stats(plan)
+    assert plan.info()["arena_bytes"] == arena             # scratch is reserved in both modes
+    assert tree["launches"] == 4 + 1 and flat["launches"] == 1
+    assert tree["jobs"] == 2 * sum(2 ** l for l in range(5)) and flat["jobs"] == 2 * 16
+    assert tree["fused_ops"] == flat["fused_ops"] and tree["dense_ops"] == flat["dense_ops"]
+    ccut.plan_set_prefix_sharing(plan, 0)
+    assert ccut.plan_stats(plan) == flat
+    big = ccut.cut_plan(24, brickwork(24, 20, 2, 12, seed=0), 2)   # 2 x 4096 x 2^12 = 2^25 amplitudes
+    assert ccut.plan_get_prefix_sharing(big)
+    for bad in (-2, 2):
+        with pytest.raises(ccut.CcutError):
+            ccut.plan_set_prefix_sharing(plan, bad)

@@ -202,6 +202,43 @@ def test_sim_precisions_match_oracle(lib, prec, bits):
     assert worst < fp32_tol(13)
 
 
+@pytest.mark.parametrize("prec,bits", [("fp16x3", 13), ("fp32", 13), ("fp16x3", 11), ("fp32", 9)])
+def test_prefix_sharing_matches_oracle(lib, prec, bits):
+    """Prefix sharing (a tree over the slots: each chunk of the segment program run once
+    per prefix of slot choices) gives the oracle's subcircuit states, multi-pass too."""
+    ccut, pipeline = lib
+    o = _q26_oracle()
+    run = pipeline.CutRun(26, o["g"], 2)
+    ccut.plan_set_sim_precision(run.plan, prec)
+    ccut.plan_set_block_bits(run.plan, bits)
+    ccut.plan_set_prefix_sharing(run.plan, 1)
+    assert ccut.plan_get_prefix_sharing(run.plan)
+    run.arena.zero_()
+    run.simulate_subcircuits()
+    torch.cuda.synchronize()
+    pcuts = run.plan.cuts()
+    for i in range(2):
+        for r in range(16):
+            ref = o["ostates"][oracle_key(pcuts, o["ocuts"], i, r)]
+            got = to_np(run.variant_state(i, r))
+            assert metrics.max_abs_error(ref, got) < fp32_tol(13), (prec, bits, i, r)
+            assert metrics.one_minus_fidelity(ref, got) < 1e-9, (prec, bits, i, r)
+
+
+@pytest.mark.parametrize("q,n,c,kind", [(20, 2, 8, "brickwork"), (12, 3, 4, "staircase"), (15, 3, 6, "brickwork")])
+def test_prefix_sharing_full_pipeline(lib, q, n, c, kind):
+    """Tree simulation + merge against the oracle's plain sum, many cuts per segment,
+    three segments with interleaved boundary slots, and CX cuts (H S H on targets)."""
+    ccut, pipeline = lib
+    g = brickwork(q, 12, n, c, seed=q + c) if kind == "brickwork" else staircase(q, c // (n - 1))
+    sizes = equal_blocks(q, n)
+    run = pipeline.CutRun(q, g, n, sizes)
+    ccut.plan_set_prefix_sharing(run.plan, 1)
+    psi = to_np(run.run("fp32"))
+    ref = cutting.cut_simulate(q, g, sizes)
+    check_state(ref, psi, q, f"tree q{q} n{n} c{c} {kind}")
+
+
 def test_bench_config_sampled(lib):
     """The measured workload (q=28, 14+14, d=20, c_total=6): sampled amplitudes vs the oracle,
     unit norm, and the full cut state against the full uncut state on the GPU."""
