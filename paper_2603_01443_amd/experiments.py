@@ -8,11 +8,12 @@
     python -m paper_2603_01443_amd.experiments paper      --out results/paper_family.json
 
 sweep      Random brickwork, q = 24 in two blocks of 12, d in {10, 20, 40},
-           c_total in {0, 1, 2, 3, 4, 6} (extended to 12 when cutting still
-           pays): T_pre, T_sub, T_merge and the uncut T_orig on the same GPU,
-           Delta = (T_cut - T_orig) / T_orig (Sec. V.A.3), and the first c_total
-           where Delta >= 0, beside the closed-form threshold c_total < q/2
-           (Eq. threshold_n2).
+           c_total in {0, 1, 2, 3, 4, 6} (extended by 2 up to --cmax while cutting
+           still pays): T_pre, T_sub, T_merge and the uncut T_orig on the same
+           GPU, Delta = (T_cut - T_orig) / T_orig (Sec. V.A.3) with the default
+           (automatic prefix sharing) and the flat simulation, and the first
+           c_total where Delta >= 0, beside the closed-form threshold
+           c_total < q/2 (Eq. threshold_n2).
 precision  q = 30 (15 + 15), d = 20, c_total in {2, 4, 6, 8}: merge time for the
            float32, split-bfloat16, split-float16 and unsplit-bfloat16 merges,
            their norm drift and 1 - F against the uncut state; accuracy against
@@ -86,8 +87,9 @@ def events(n):
     return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
 
 
-def time_cut(q, gates, n, sizes, bufs, precision="auto", warm=1, reps=3):
-    """(T_pre, T_sub, T_merge) in seconds, means over reps."""
+def time_cut(q, gates, n, sizes, bufs, precision="auto", warm=1, reps=3, prefix=None):
+    """(T_pre, T_sub, T_merge) in seconds, means over reps.  prefix: None keeps the plan's
+    automatic prefix-sharing choice, 0 / 1 forces it (the rebuild counts in T_pre)."""
     garr = ccut.gate_array(gates)
     s = torch.cuda.current_stream()
     pre, sub, mer = [], [], []
@@ -95,6 +97,8 @@ def time_cut(q, gates, n, sizes, bufs, precision="auto", warm=1, reps=3):
     for it in range(warm + reps):
         t0 = time.perf_counter()
         plan = ccut.cut_plan(q, garr, n, sizes)
+        if prefix is not None:
+            ccut.plan_set_prefix_sharing(plan, prefix)
         t1 = time.perf_counter()
         info = plan.info()
         arena = bufs.get("arena", info["arena_bytes"])
@@ -149,21 +153,29 @@ def run_sweep(args):
             g = brickwork(q, d, n, c, seed=0)
             if t_orig is None:
                 t_orig = time_uncut(q, g, bufs, reps=args.reps)
-            pre, sub, mer, _ = time_cut(q, g, n, sizes, bufs, reps=args.reps)
-            t_cut = pre + sub + mer
+            pre, sub, mer, plan = time_cut(q, g, n, sizes, bufs, reps=args.reps)
+            tree = ccut.plan_get_prefix_sharing(plan)
+            fpre, fsub, fmer, _ = time_cut(q, g, n, sizes, bufs, reps=args.reps, prefix=0)
+            t_cut, t_flat = pre + sub + mer, fpre + fsub + fmer
             rows.append({"q": q, "d": d, "c_total": c, "T_pre": pre, "T_sub": sub, "T_merge": mer,
-                         "T_cut": t_cut, "T_orig": t_orig, "delta": (t_cut - t_orig) / t_orig})
-            log(f"sweep d={d} c={c}: pre {pre*1e3:.3f} sub {sub*1e3:.3f} merge {mer*1e3:.3f} "
-                f"orig {t_orig*1e3:.3f} ms  delta {rows[-1]['delta']:+.3f}")
-            cmax = min(12, d)   # at most one cut per boundary and layer
-            if i == len(cs) - 1 and rows[-1]["delta"] < 0 and c < cmax:
+                         "T_cut": t_cut, "T_orig": t_orig, "delta": (t_cut - t_orig) / t_orig,
+                         "prefix_sharing": tree, "T_sub_flat": fsub, "T_cut_flat": t_flat,
+                         "delta_flat": (t_flat - t_orig) / t_orig})
+            log(f"sweep d={d} c={c}: pre {pre*1e3:.3f} sub {sub*1e3:.3f} (flat {fsub*1e3:.3f}) merge "
+                f"{mer*1e3:.3f} orig {t_orig*1e3:.3f} ms  delta {rows[-1]['delta']:+.3f} "
+                f"(flat {rows[-1]['delta_flat']:+.3f}){' tree' if tree else ''}")
+            cmax = min(args.cmax, d)   # at most one cut per boundary and layer
+            if i == len(cs) - 1 and min(rows[-1]["delta"], rows[-1]["delta_flat"]) < 0 and c < cmax:
                 cs.append(min(c + 2, cmax))   # extend until cutting stops paying
             i += 1
-    cross = {}
+    cross, cross_flat = {}, {}
     for d in (10, 20, 40):
         bad = [r["c_total"] for r in rows if r["d"] == d and r["delta"] >= 0]
         cross[str(d)] = min(bad) if bad else None
+        bad = [r["c_total"] for r in rows if r["d"] == d and r["delta_flat"] >= 0]
+        cross_flat[str(d)] = min(bad) if bad else None
     return {"experiment": "threshold sweep", "rows": rows, "first_c_without_speedup": cross,
+            "first_c_without_speedup_flat_simulation": cross_flat,
             "closed_form_threshold_c_total_lt": ccut.threshold_ctotal(q, 2)}
 
 
@@ -546,6 +558,7 @@ def main():
     ap.add_argument("--budget-ms", type=float, default=20.0)
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--margin", type=float, default=0.2)
+    ap.add_argument("--cmax", type=int, default=16, help="sweep: largest c_total tried")
     args = ap.parse_args()
     if not torch.cuda.is_available():
         raise SystemExit("experiments need a GPU")
