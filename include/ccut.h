@@ -44,6 +44,8 @@ extern "C" {
 /* ------------------------------------------------------------------ limits */
 #define CCUT_MAX_SEG 8          /* segments per plan */
 #define CCUT_MAX_Q 35           /* 2^35 complex64 = 256 GiB, the largest state one GPU holds */
+#define CCUT_MAX_PLAN_Q 60      /* a plan's q when no merged state is formed (expectation values);
+                                   every segment still holds at most CCUT_MAX_Q qubits */
 #define CCUT_MAX_CUTS_PER_SEG 16 /* c_i <= 16: at most 65536 variants per segment */
 
 /* ------------------------------------------------------------------ status */
@@ -93,8 +95,9 @@ typedef struct ccut_plan_info {
   int64_t n_terms;                     /* 2^{c_total} global merge terms   (Algorithm 3) */
   uint64_t seg_state_offset[CCUT_MAX_SEG]; /* byte offset of segment i's variant 0 in the arena */
   uint64_t state_bytes;                /* bytes of all subcircuit states */
-  uint64_t arena_bytes;                /* state_bytes + merge workspace: size the arena to this */
+  uint64_t arena_bytes;                /* the whole pipeline (simulation + merge workspace): size the arena to this */
   uint64_t psi_bytes;                  /* 8 * 2^q, the merged state */
+  uint64_t sim_arena_bytes;            /* enough for ccut_simulate_subcircuits and ccut_expectation_pauli */
 } ccut_plan_info_t;
 
 typedef struct ccut_cut_info {
@@ -116,7 +119,8 @@ typedef struct ccut_cut_info {
  * Algorithm 1 are these programs with the slots fixed by the variant index;
  * they are never copied out).  Host-only; touches no GPU.
  *
- *   q          total qubits, 1..CCUT_MAX_Q
+ *   q          total qubits, 1..CCUT_MAX_PLAN_Q (ccut_merge_full_state needs
+ *              q <= CCUT_MAX_Q); every segment at most CCUT_MAX_Q qubits
  *   gates      n_gates gates (host memory, read during the call only)
  *   n_seg      number of segments n, 1..CCUT_MAX_SEG
  *   seg_sizes  n_seg contiguous block sizes adding up to q, or NULL for
@@ -221,6 +225,26 @@ int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, vo
  * Errors: CCUT_EINVAL, CCUT_EHIP.
  */
 int ccut_norm_fidelity(const void* d_psi, const void* d_ref, int32_t q, double out[5], void* stream);
+
+/*
+ * Expectation value of a Pauli string on the cut state, from the subcircuit
+ * states alone (the setting the paper's closing section names, Sec. VI: no
+ * O(2^q) merge and no 2^q buffer).  With O = P_{n-1} x ... x P_0 split by the
+ * segments, <Psi|O|Psi> = sum_{b,b'} conj(alpha_b) alpha_b' prod_i G_i[r_i(b)][r_i(b')]
+ * where G_i[r][r'] = <psi_i^{(r)}| P_i |psi_i^{(r')}> is formed on the GPU
+ * (float32 products, float64 sums) and the sum over the cut bits is contracted
+ * boundary by boundary in float64 on the host.  Work: sum_i 4^{c_i} 2^{q_i}.
+ *
+ *   d_arena    the arena after ccut_simulate_subcircuits (read only)
+ *   pauli      q characters from "IXYZ"; character j acts on qubit j
+ *   d_work     device workspace of ccut_expectation_work_bytes() bytes
+ *   out        host: real and imaginary part (the latter ~0 for a Pauli string)
+ * Synchronises `stream`.  Errors: CCUT_EINVAL (label), CCUT_ENOSPC,
+ * CCUT_EUNSUPPORTED (more than 20 cuts on a segment), CCUT_EHIP.
+ */
+int ccut_expectation_work_bytes(const ccut_plan_t* plan, uint64_t* bytes);
+int ccut_expectation_pauli(ccut_plan_t* plan, const void* d_arena, uint64_t arena_bytes, const char* pauli,
+                           void* d_work, uint64_t work_bytes, double out[2], void* stream);
 
 /* ------------------------------------------------- launches, graphs, tuning */
 /*
@@ -419,9 +443,9 @@ int ccut_decide(int32_t q, int32_t d, int32_t c_total, const float* d_params, do
  * family `kernel` (0 <= kernel < CCUT_PROF_KERNELS), the number of launches
  * and their summed device milliseconds since the last reset, plus the family
  * name ("sim", "merge_f32", "split_R", "split_L", "merge_gemm", "reduce",
- * "mlp"; a static string, pass NULL to skip).  Errors: CCUT_EINVAL, CCUT_EHIP.
+ * "mlp", "expect"; a static string, pass NULL to skip).  Errors: CCUT_EINVAL, CCUT_EHIP.
  */
-#define CCUT_PROF_KERNELS 7
+#define CCUT_PROF_KERNELS 8
 int ccut_profile_enable(int32_t on);
 int ccut_profile_read(int32_t kernel, int64_t* launches, double* total_ms, const char** name);
 int ccut_profile_reset(void);

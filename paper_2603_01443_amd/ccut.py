@@ -54,6 +54,7 @@ class PlanInfo(ctypes.Structure):
         ("n_sub", ctypes.c_int64), ("n_terms", ctypes.c_int64),
         ("seg_state_offset", ctypes.c_uint64 * MAX_SEG),
         ("state_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64), ("psi_bytes", ctypes.c_uint64),
+        ("sim_arena_bytes", ctypes.c_uint64),
     ]
 
 
@@ -84,6 +85,8 @@ def _load():
         "ccut_merge_full_state": [vp, vp, u64, vp, u64, i32, vp],
         "ccut_simulate_uncut": [i32, vp, i64, vp, u64, vp],
         "ccut_norm_fidelity": [vp, vp, i32, ctypes.POINTER(ctypes.c_double), vp],
+        "ccut_expectation_work_bytes": [vp, ctypes.POINTER(u64)],
+        "ccut_expectation_pauli": [vp, vp, u64, ctypes.c_char_p, vp, u64, ctypes.POINTER(ctypes.c_double), vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -214,6 +217,7 @@ class Plan:
             "n_sub": inf.n_sub, "n_terms": inf.n_terms,
             "seg_state_offset": list(inf.seg_state_offset[:n]),
             "state_bytes": inf.state_bytes, "arena_bytes": inf.arena_bytes, "psi_bytes": inf.psi_bytes,
+            "sim_arena_bytes": inf.sim_arena_bytes,
         }
 
     def cuts(self) -> List[dict]:
@@ -285,8 +289,23 @@ def norm_fidelity(psi, ref, q: int, stream=None) -> dict:
     return res
 
 
-PROF_KERNELS = 7
+PROF_KERNELS = 8
 MLP_PARAMS = 4675
+
+
+def expectation_work_bytes(plan: Plan) -> int:
+    out = ctypes.c_uint64(0)
+    _check(_lib.ccut_expectation_work_bytes(plan.handle, ctypes.byref(out)))
+    return int(out.value)
+
+
+def expectation_pauli(plan: Plan, arena, pauli: str, work, arena_bytes: Optional[int] = None,
+                      work_bytes: Optional[int] = None, stream=None) -> complex:
+    """<Psi|P|Psi> of the cut state from the subcircuit states (character j of `pauli` on qubit j)."""
+    out = (ctypes.c_double * 2)()
+    _check(_lib.ccut_expectation_pauli(plan.handle, _ptr(arena), _nbytes(arena, arena_bytes), pauli.encode(),
+                                       _ptr(work), _nbytes(work, work_bytes), out, _stream(stream)))
+    return complex(out[0], out[1])
 
 
 def threshold_ctotal(q: int, n: int) -> float:
@@ -348,7 +367,7 @@ def profile_enable(on: bool = True) -> None:
     _check(_lib.ccut_profile_enable(1 if on else 0))
 
 
-PROFILE_KERNELS = ("sim", "merge_f32", "split_R", "split_L", "merge_gemm", "reduce", "mlp")
+PROFILE_KERNELS = ("sim", "merge_f32", "split_R", "split_L", "merge_gemm", "reduce", "mlp", "expect")
 
 
 def profile_mask(kernels=None) -> None:

@@ -255,9 +255,9 @@ extern "C" int ccut_plan_prepare(ccut_plan_t* plan) {
 extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* stream) {
   clear_error();
   if (!plan || !d_arena) return fail(CCUT_EINVAL, "NULL argument");
-  if (arena_bytes < plan->total_arena)
-    return fail(CCUT_ENOSPC, "arena has %llu bytes, plan needs %llu", (unsigned long long)arena_bytes,
-                (unsigned long long)plan->total_arena);
+  if (arena_bytes < plan->sim_bytes)
+    return fail(CCUT_ENOSPC, "arena has %llu bytes, the simulation needs %llu", (unsigned long long)arena_bytes,
+                (unsigned long long)plan->sim_bytes);
   hipStream_t s = static_cast<hipStream_t>(stream);
   DeviceTables T;
   if (int rc = plan_tables(plan, static_cast<char*>(d_arena), s, T)) return rc;
@@ -289,6 +289,9 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
                                      uint64_t psi_bytes, int32_t precision, void* stream) {
   clear_error();
   if (!plan || !d_arena || !d_psi) return fail(CCUT_EINVAL, "NULL argument");
+  if (!plan->merge_ok)
+    return fail(CCUT_EUNSUPPORTED, "q=%d: the merged state exceeds one GPU (q <= %d); expectation values "
+                "need no merge", plan->q, CCUT_MAX_Q);
   if (arena_bytes < plan->total_arena) return fail(CCUT_ENOSPC, "arena too small");
   if (psi_bytes < plan->psi_bytes)
     return fail(CCUT_ENOSPC, "psi has %llu bytes, needs %llu", (unsigned long long)psi_bytes,

@@ -1,0 +1,148 @@
+// Pauli-string expectation values of the cut state from the subcircuit states
+// (no merge): per-segment matrices G_i on the GPU, then the contraction over
+// the cut bits in float64 on the host, boundary by boundary:
+//   E_0[u][u']  = W_0[u][u'] G_0[u][u']
+//   E_i[v][v']  = W_i[v][v'] sum_{u,u'} E_{i-1}[u][u'] G_i[u + 2^{c_{i-1}} v][u' + 2^{c_{i-1}} v']
+//   <O>         = sum_{u,u'} E_{n-2}[u][u'] G_{n-1}[u][u']
+// with W_b[u][u'] = prod over the cuts j of boundary b of conj(s_{u_j}) s_{u'_j}
+// (s_0 = 1/(1+i), s_1 = i/(1+i), Eq. CZ) and segment i's variant index
+// r = (lower-boundary bits) + 2^{c_{i-1}} (upper-boundary bits).
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "plan.h"
+
+namespace ccut {
+int gram_splits(int V, uint64_t N);
+int launch_gram(const float2* states, int V, uint64_t N, uint32_t flip, uint32_t zy, int splits, double2* part,
+                hipStream_t s);
+}  // namespace ccut
+
+using namespace ccut;
+
+namespace {
+
+uint64_t work_bytes(const ccut_plan* P) {
+  uint64_t b = 0;
+  for (const auto& S : P->segs) {
+    const uint64_t V = (uint64_t)1 << S.c;
+    b += (uint64_t)gram_splits((int)V, (uint64_t)1 << S.q) * V * V * sizeof(double2);
+    b = (b + 255) & ~uint64_t(255);
+  }
+  return b;
+}
+
+// W_b for a boundary with c cuts: 2^c x 2^c
+std::vector<cd> boundary_weights(int c) {
+  const cd s[2] = {cd(0.5, -0.5), cd(0.5, 0.5)};
+  const int64_t V = (int64_t)1 << c;
+  std::vector<cd> w((size_t)(V * V));
+  for (int64_t u = 0; u < V; ++u)
+    for (int64_t v = 0; v < V; ++v) {
+      cd a = 1.0;
+      for (int j = 0; j < c; ++j) a *= std::conj(s[(u >> j) & 1]) * s[(v >> j) & 1];
+      w[(size_t)(u * V + v)] = a;
+    }
+  return w;
+}
+
+}  // namespace
+
+extern "C" int ccut_expectation_work_bytes(const ccut_plan_t* plan, uint64_t* bytes) {
+  clear_error();
+  if (!plan || !bytes) return fail(CCUT_EINVAL, "NULL argument");
+  *bytes = work_bytes(plan);
+  return CCUT_OK;
+}
+
+extern "C" int ccut_expectation_pauli(ccut_plan_t* plan, const void* d_arena, uint64_t arena_bytes,
+                                      const char* pauli, void* d_work, uint64_t work_bytes_in, double out[2],
+                                      void* stream) {
+  clear_error();
+  if (!plan || !d_arena || !pauli || !d_work || !out) return fail(CCUT_EINVAL, "NULL argument");
+  if (arena_bytes < plan->state_bytes) return fail(CCUT_ENOSPC, "arena smaller than the plan's states");
+  if (std::strlen(pauli) != (size_t)plan->q)
+    return fail(CCUT_EINVAL, "Pauli label has %zu characters for q=%d", std::strlen(pauli), plan->q);
+  for (int j = 0; j < plan->q; ++j)
+    if (!std::strchr("IXYZ", pauli[j]) || pauli[j] == 0)
+      return fail(CCUT_EINVAL, "Pauli label character %d is '%c' (I, X, Y or Z)", j, pauli[j]);
+  const uint64_t need = work_bytes(plan);
+  if (work_bytes_in < need)
+    return fail(CCUT_ENOSPC, "work buffer has %llu bytes, needs %llu", (unsigned long long)work_bytes_in,
+                (unsigned long long)need);
+  for (const auto& S : plan->segs)
+    if (S.c > 20) return fail(CCUT_EUNSUPPORTED, "expectation values need at most 20 cuts per segment");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const char* base = static_cast<const char*>(d_arena);
+  std::vector<uint64_t> woff(plan->n_seg);
+  std::vector<int> splits(plan->n_seg);
+  std::vector<cd> phase(plan->n_seg);
+  uint64_t off = 0;
+  for (int i = 0; i < plan->n_seg; ++i) {
+    const auto& S = plan->segs[i];
+    uint32_t flip = 0, zy = 0;
+    int ny = 0;
+    for (int t = 0; t < S.q; ++t) {
+      const char p = pauli[S.off + t];
+      if (p == 'X' || p == 'Y') flip |= 1u << t;
+      if (p == 'Z' || p == 'Y') zy |= 1u << t;
+      ny += p == 'Y';
+    }
+    cd ph = 1.0;
+    for (int k = 0; k < ny; ++k) ph *= cd(0, -1);  // Y = -i X Z on each Y qubit
+    phase[i] = ph;
+    const int V = 1 << S.c;
+    const uint64_t N = (uint64_t)1 << S.q;
+    splits[i] = gram_splits(V, N);
+    woff[i] = off;
+    double2* part = reinterpret_cast<double2*>(static_cast<char*>(d_work) + off);
+    if (int rc = launch_gram(reinterpret_cast<const float2*>(base + S.arena_off), V, N, flip, zy, splits[i], part, s))
+      return rc;
+    off = (off + (uint64_t)splits[i] * V * V * sizeof(double2) + 255) & ~uint64_t(255);
+  }
+  std::vector<double2> host(off / sizeof(double2));
+  CCUT_HIP(hipMemcpyAsync(host.data(), d_work, off, hipMemcpyDeviceToHost, s));
+  CCUT_HIP(hipStreamSynchronize(s));
+  // per-segment G (partials summed in split order)
+  std::vector<std::vector<cd>> G(plan->n_seg);
+  for (int i = 0; i < plan->n_seg; ++i) {
+    const int64_t V = (int64_t)1 << plan->segs[i].c;
+    G[i].assign((size_t)(V * V), cd(0));
+    const double2* p = host.data() + woff[i] / sizeof(double2);
+    for (int sp = 0; sp < splits[i]; ++sp)
+      for (int64_t e = 0; e < V * V; ++e) G[i][(size_t)e] += cd(p[sp * V * V + e].x, p[sp * V * V + e].y);
+    for (auto& g : G[i]) g *= phase[i];
+  }
+  cd result;
+  const int n = plan->n_seg;
+  if (n == 1) {
+    result = G[0][0];
+  } else {
+    int cprev = plan->c_b[0];
+    int64_t U = (int64_t)1 << cprev;
+    std::vector<cd> E = boundary_weights(cprev);
+    for (int64_t e = 0; e < U * U; ++e) E[(size_t)e] *= G[0][(size_t)e];
+    for (int i = 1; i + 1 < n; ++i) {
+      const int cnext = plan->c_b[i];
+      const int64_t Vn = (int64_t)1 << cnext, Vi = U * Vn;
+      std::vector<cd> W = boundary_weights(cnext), En((size_t)(Vn * Vn), cd(0));
+      for (int64_t v = 0; v < Vn; ++v)
+        for (int64_t vp = 0; vp < Vn; ++vp) {
+          cd acc = 0.0;
+          for (int64_t u = 0; u < U; ++u)
+            for (int64_t up = 0; up < U; ++up)
+              acc += E[(size_t)(u * U + up)] * G[i][(size_t)((u + U * v) * Vi + (up + U * vp))];
+          En[(size_t)(v * Vn + vp)] = W[(size_t)(v * Vn + vp)] * acc;
+        }
+      E.swap(En);
+      U = Vn;
+    }
+    cd acc = 0.0;
+    for (int64_t e = 0; e < U * U; ++e) acc += E[(size_t)e] * G[n - 1][(size_t)e];
+    result = acc;
+  }
+  out[0] = result.real();
+  out[1] = result.imag();
+  return CCUT_OK;
+}

@@ -225,12 +225,16 @@ int build_sim_tables(ccut_plan* P, bool first) {
   const uint64_t gtab_bytes = (uint64_t)P->grefs.size() * GROUP_TABLE_UINT4 * 16;
   if (first) P->gtab_reserve = align256(2 * gtab_bytes + 65536);
   P->gtab_reserve = std::max<uint64_t>(P->gtab_reserve, align256(gtab_bytes));
-  P->tree_off = align256(P->split_off + P->split_bytes);
+  // arena: states | prefix scratch | MFMA group tables | table image || merge temps | split planes
   P->gtab_off = align256(P->tree_off + P->tree_bytes);
   P->tables_off = align256(P->gtab_off + P->gtab_reserve);
   if (first) P->tables_reserve = align256(4 * (uint64_t)P->image.size() + 65536);
   P->tables_reserve = std::max<uint64_t>(P->tables_reserve, align256(P->image.size()));
-  P->total_arena = align256(P->tables_off + P->tables_reserve);
+  P->sim_bytes = align256(P->tables_off + P->tables_reserve);
+  P->temp_off[0] = P->sim_bytes;
+  P->temp_off[1] = align256(P->temp_off[0] + P->temp_bytes[0]);
+  P->split_off = align256(P->temp_off[1] + P->temp_bytes[1]);
+  P->total_arena = align256(P->split_off + P->split_bytes);
   return 0;
 }
 
@@ -261,7 +265,7 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
   clear_error();
   if (!plan_out) return fail(CCUT_EINVAL, "plan_out is NULL");
   *plan_out = nullptr;
-  if (q < 1 || q > CCUT_MAX_Q) return fail(CCUT_EINVAL, "q=%d outside [1, %d]", q, CCUT_MAX_Q);
+  if (q < 1 || q > CCUT_MAX_PLAN_Q) return fail(CCUT_EINVAL, "q=%d outside [1, %d]", q, CCUT_MAX_PLAN_Q);
   if (n_seg < 1 || n_seg > CCUT_MAX_SEG || n_seg > q)
     return fail(CCUT_EINVAL, "n_seg=%d outside [1, min(q, %d)]", n_seg, CCUT_MAX_SEG);
   if (n_gates < 0 || (n_gates > 0 && !gates)) return fail(CCUT_EINVAL, "bad gate array");
@@ -278,6 +282,7 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
   for (int i = 0; i < n_seg; ++i) {
     int s = seg_sizes ? seg_sizes[i] : q / n_seg + (i >= n_seg - q % n_seg ? 1 : 0);
     if (s < 1) return fail(CCUT_EINVAL, "segment %d has size %d", i, s);
+    if (s > CCUT_MAX_Q) return fail(CCUT_EINVAL, "segment %d has %d qubits (max %d)", i, s, CCUT_MAX_Q);
     P->segs[i].q = s;
     P->segs[i].off = acc;
     acc += s;
@@ -382,6 +387,7 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
     off = align256(off + ((uint64_t)8 << S.q) * ((uint64_t)1 << S.c));
   }
   P->state_bytes = off;
+  P->merge_ok = q <= CCUT_MAX_Q;
   P->psi_bytes = (uint64_t)8 << q;
 
   // Merge stages (Algorithm 3 contracted boundary by boundary).
@@ -420,21 +426,19 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
       P->weights.push_back((float)w.real());
       P->weights.push_back((float)w.imag());
     }
-    if (!last) {
+    if (!last && P->merge_ok) {
       uint64_t bytes = ((uint64_t)8 << (qacc + Sn.q)) * (uint64_t)st.batch;
       if (k % 2 == 0) ping = std::max(ping, bytes); else pong = std::max(pong, bytes);
     }
     qacc += Sn.q;
     P->stages.push_back(st);
   }
-  P->temp_off[0] = P->state_bytes;
-  P->temp_off[1] = align256(P->temp_off[0] + ping);
-  P->arena_bytes = align256(P->temp_off[1] + pong);
+  P->temp_bytes[0] = ping;
+  P->temp_bytes[1] = pong;
   // Split-precision planes of the MFMA merge (reused stage after stage).
-  P->split_off = P->arena_bytes;
   P->split_bytes = 0;
   for (const MergeStage& st : P->stages) {
-    if (!merge_mfma_supported(st.qx, st.qy)) continue;
+    if (!P->merge_ok || !merge_mfma_supported(st.qx, st.qy)) continue;
     const int S = mfma_steps(st.K);
     const uint64_t r_batch = st.a_bstride ? (uint64_t)st.batch : 1;
     const uint64_t u4 = (uint64_t)st.batch * mfma_l_plane(st.qy, S) + r_batch * mfma_r_plane(st.qx, S);
@@ -442,7 +446,7 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
   }
   // Prefix-sharing scratch: two ping-pong halves of 2^(c_i - 1) states per segment
   // (reserved in both modes, so that switching the mode keeps the arena size).
-  P->tree_off = align256(P->split_off + P->split_bytes);
+  P->tree_off = align256(P->state_bytes);
   P->tree_bytes = 0;
   for (auto& S : P->segs) {
     S.tree_off = P->tree_off + P->tree_bytes;
@@ -482,6 +486,7 @@ extern "C" int ccut_plan_info(const ccut_plan_t* plan, ccut_plan_info_t* info) {
   info->n_terms = (int64_t)1 << info->c_total;
   info->state_bytes = plan->state_bytes;
   info->arena_bytes = plan->total_arena;
+  info->sim_arena_bytes = plan->sim_bytes;
   info->psi_bytes = plan->psi_bytes;
   return CCUT_OK;
 }

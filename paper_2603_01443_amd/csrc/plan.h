@@ -23,6 +23,9 @@ struct ccut_plan {
   std::vector<int32_t> c_b;
   uint64_t state_bytes = 0, arena_bytes = 0, psi_bytes = 0;
   uint64_t temp_off[2] = {0, 0};  // ping / pong temp regions of the chain merge (bytes)
+  uint64_t temp_bytes[2] = {0, 0};
+  bool merge_ok = true;           // the merged 2^q state fits (q <= CCUT_MAX_Q)
+  uint64_t sim_bytes = 0;         // arena prefix used by the simulation (states, scratch, tables)
   uint64_t split_off = 0, split_bytes = 0;  // split-precision planes of the last merge stage
   std::vector<ccut::MergeStage> stages;
   std::vector<float> weights;     // complex64 merge weights, per stage

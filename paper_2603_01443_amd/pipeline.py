@@ -21,14 +21,16 @@ def _stream():
 
 class CutRun:
     def __init__(self, q: int, gates, n_seg: int, seg_sizes: Optional[Sequence[int]] = None,
-                 device: str = "cuda:0", psi: Optional[torch.Tensor] = None):
+                 device: str = "cuda:0", psi: Optional[torch.Tensor] = None, sim_only: bool = False):
         self.q = q
         self.device = torch.device(device)
         self.gates = ccut.gate_array(gates)
         self.plan = ccut.cut_plan(q, self.gates, n_seg, seg_sizes)
         self.info = self.plan.info()
         with torch.cuda.device(self.device):
-            self.arena = torch.empty(max(self.info["arena_bytes"], 8), dtype=torch.uint8, device=self.device)
+            # sim_only: room for the simulation (and expectation values) only, no merge workspace
+            size = self.info["sim_arena_bytes"] if sim_only else self.info["arena_bytes"]
+            self.arena = torch.empty(max(size, 8), dtype=torch.uint8, device=self.device)
             self.psi = psi if psi is not None else torch.empty(1 << q, dtype=torch.complex64, device=self.device)
             ccut.plan_prepare(self.plan)
 

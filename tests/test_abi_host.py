@@ -168,3 +168,16 @@ def test_prefix_sharing_tree_shape():
     for bad in (-2, 2):
         with pytest.raises(ccut.CcutError):
             ccut.plan_set_prefix_sharing(plan, bad)
+
+
+def test_expectation_argument_checks():
+    """Label and workspace errors come back before anything touches the GPU."""
+    plan = ccut.cut_plan(12, brickwork(12, 4, 2, 2, seed=0), 2)
+    need = ccut.expectation_work_bytes(plan)
+    assert need >= 2 * 4 * 4 * 16        # two segments, 4 x 4 complex128 entries at least
+    fake = 1 << 20                         # never dereferenced: every call below fails its checks first
+    for label in ("Z" * 11, "Z" * 13, "ZZZZZZZZZZZQ", "zzzzzzzzzzzz"):
+        with pytest.raises(ccut.CcutError):
+            ccut.expectation_pauli(plan, fake, label, fake, arena_bytes=1 << 30, work_bytes=need)
+    with pytest.raises(ccut.CcutError, match="work buffer"):
+        ccut.expectation_pauli(plan, fake, "IXYZ" * 3, fake, arena_bytes=1 << 30, work_bytes=need - 1)

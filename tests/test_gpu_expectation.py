@@ -1,0 +1,95 @@
+"""Pauli expectation values from the subcircuit states (no merge) against the
+oracle's full-state definition, through the C-ABI.
+
+Tolerance: the states are complex64 (relative error ~1e-6 after ~10^2-10^3
+gates) and the matrix elements are summed in float64, so a Pauli expectation
+(a number in [-1, 1]) carries an absolute error of a few 1e-6 at most; the
+tests require 2e-5.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from inputs import brickwork, equal_blocks, staircase  # noqa: E402
+from oracle import statevector  # noqa: E402
+from oracle.expectation import expval  # noqa: E402
+
+TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_01443_amd import ccut, pipeline
+    return ccut, pipeline
+
+
+def cut_expectations(ccut, pipeline, q, g, n, sizes, labels, prefix=-1):
+    run = pipeline.CutRun(q, g, n, sizes, psi=torch.empty(8, dtype=torch.complex64, device="cuda"), sim_only=True)
+    ccut.plan_set_prefix_sharing(run.plan, prefix)
+    run.simulate_subcircuits()
+    work = torch.empty(max(ccut.expectation_work_bytes(run.plan), 8), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+    return [ccut.expectation_pauli(run.plan, run.arena, lab, work, stream=s) for lab in labels]
+
+
+@pytest.mark.parametrize("q,n,c,kind,prefix", [
+    (12, 2, 2, "brickwork", -1), (20, 2, 6, "brickwork", -1), (20, 2, 6, "brickwork", 1),
+    (15, 3, 4, "brickwork", -1), (12, 3, 4, "staircase", 1), (16, 4, 3, "brickwork", -1), (10, 1, 0, "brickwork", -1)])
+def test_pauli_expectations_match_oracle(lib, q, n, c, kind, prefix):
+    ccut, pipeline = lib
+    g = brickwork(q, 8, n, c, seed=q + n) if kind == "brickwork" else staircase(q, c // (n - 1))
+    sizes = equal_blocks(q, n)
+    ref = statevector.simulate(q, g)
+    rng = np.random.default_rng(q * 10 + n)
+    labels = ["I" * q, "Z" * q, "X" * q] + ["".join(rng.choice(list("IXYZ"), q)) for _ in range(8)]
+    # low-weight strings too (the random ones have expectations near 0)
+    for j in range(0, q, max(1, q // 4)):
+        lab = ["I"] * q
+        lab[j] = "Z"
+        labels.append("".join(lab))
+        lab[(j + 1) % q] = "X"
+        labels.append("".join(lab))
+    got = cut_expectations(ccut, pipeline, q, g, n, sizes, labels, prefix)
+    worst = 0.0
+    for lab, v in zip(labels, got):
+        want = expval(ref, q, lab)
+        worst = max(worst, abs(v - want))
+        assert abs(v - want) < TOL, (lab, v, want)
+    print(f"q{q} n{n} c{c} {kind}: worst |err| {worst:.2e} over {len(labels)} strings", flush=True)
+
+
+def test_q40_partitions_agree():
+    """q = 40 (a 2^40 state would be 8 TiB): the same circuit cut at two different
+    boundaries, and into three segments, gives the same expectations, and <I> = 1."""
+    ccut, pipeline = None, None
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_01443_amd import ccut, pipeline
+    q = 40
+    g = brickwork(q, 8, 2, 4, seed=7)
+    rng = np.random.default_rng(40)
+    labels = ["I" * q]
+    for _ in range(4):
+        lab = ["I"] * q
+        for j in rng.choice(q, 4, replace=False):
+            lab[j] = rng.choice(list("XYZ"))
+        labels.append("".join(lab))
+    labels.append("Z" * q)
+    res = {}
+    for sizes in ([20, 20], [18, 22], [13, 13, 14]):
+        n = len(sizes)
+        plan = ccut.cut_plan(q, ccut.gate_array(g), n, sizes)
+        print(sizes, plan.info()["c_boundary"][: n - 1], flush=True)
+        res[tuple(sizes)] = cut_expectations(ccut, pipeline, q, g, n, sizes, labels)
+    a = res[(20, 20)]
+    assert abs(a[0] - 1) < TOL
+    for key, b in res.items():
+        for lab, x, y in zip(labels, a, b):
+            assert abs(x - y) < TOL, (key, lab, x, y)
+            assert abs(x.imag) < TOL and abs(x.real) <= 1 + TOL
+    print("q40 expectations:", [f"{v.real:+.6f}" for v in a], flush=True)
