@@ -47,6 +47,7 @@ extern "C" {
 #define CCUT_MAX_PLAN_Q 60      /* a plan's q when no merged state is formed (expectation values);
                                    every segment still holds at most CCUT_MAX_Q qubits */
 #define CCUT_MAX_CUTS_PER_SEG 16 /* c_i <= 16: at most 65536 variants per segment */
+#define CCUT_MAX_EXPECT_CUTS 12  /* c_i <= 12 for ccut_expectation_pauli (4096 x 4096 matrix per segment) */
 
 /* ------------------------------------------------------------------ status */
 #define CCUT_OK 0
@@ -240,7 +241,8 @@ int ccut_norm_fidelity(const void* d_psi, const void* d_ref, int32_t q, double o
  *   d_work     device workspace of ccut_expectation_work_bytes() bytes
  *   out        host: real and imaginary part (the latter ~0 for a Pauli string)
  * Synchronises `stream`.  Errors: CCUT_EINVAL (label), CCUT_ENOSPC,
- * CCUT_EUNSUPPORTED (more than 20 cuts on a segment), CCUT_EHIP.
+ * CCUT_EUNSUPPORTED (more than CCUT_MAX_EXPECT_CUTS cuts on a segment: its
+ * 4^{c_i} matrix entries would exceed one launch grid), CCUT_EHIP.
  */
 int ccut_expectation_work_bytes(const ccut_plan_t* plan, uint64_t* bytes);
 int ccut_expectation_pauli(ccut_plan_t* plan, const void* d_arena, uint64_t arena_bytes, const char* pauli,

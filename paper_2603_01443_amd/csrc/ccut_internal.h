@@ -213,6 +213,16 @@ int launch_group_tables(const KOp* d_ops, const GroupRef* d_refs, int n, uint4* 
 int launch_merge_f32(const MergeStage& st, const float* A, const float* B, float* out,
                      const float* d_weights, hipStream_t s);
 
+// Pauli-string matrices of one segment's variant states (expectation values)
+struct GramShape {
+  int tm;      // tile side: 16, 32 or 64 entries
+  int splits;  // amplitude-range splits, each writing a partial V x V matrix
+};
+GramShape gram_shape(int V, uint64_t N);
+// out (V x V complex128) = sum over the splits of part[s], part: splits * V * V complex128
+int launch_gram(const float2* states, int V, uint64_t N, uint32_t flip, uint32_t zy, GramShape g, double2* part,
+                double2* out, hipStream_t s);
+
 int launch_reduce(const float* psi, const float* ref, uint64_t n, double* d_partials, int n_blocks,
                   double* d_out, hipStream_t s);
 

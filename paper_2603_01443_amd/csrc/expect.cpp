@@ -13,24 +13,37 @@
 
 #include "plan.h"
 
-namespace ccut {
-int gram_splits(int V, uint64_t N);
-int launch_gram(const float2* states, int V, uint64_t N, uint32_t flip, uint32_t zy, int splits, double2* part,
-                hipStream_t s);
-}  // namespace ccut
-
 using namespace ccut;
 
 namespace {
 
-uint64_t work_bytes(const ccut_plan* P) {
-  uint64_t b = 0;
+// Workspace: the summed V x V matrices of all segments first (one contiguous
+// region, copied to the host at once), then each segment's per-split partials.
+struct WorkLayout {
+  std::vector<uint64_t> fin_off, part_off;
+  std::vector<GramShape> shape;
+  uint64_t fin_bytes = 0, total = 0;
+};
+
+WorkLayout work_layout(const ccut_plan* P) {
+  WorkLayout w;
+  uint64_t off = 0;
   for (const auto& S : P->segs) {
     const uint64_t V = (uint64_t)1 << S.c;
-    b += (uint64_t)gram_splits((int)V, (uint64_t)1 << S.q) * V * V * sizeof(double2);
-    b = (b + 255) & ~uint64_t(255);
+    w.fin_off.push_back(off);
+    off = align256(off + V * V * sizeof(double2));
   }
-  return b;
+  w.fin_bytes = off;
+  for (const auto& S : P->segs) {
+    const uint64_t V = (uint64_t)1 << S.c;
+    const GramShape g = gram_shape((int)V, (uint64_t)1 << S.q);
+    const int sp = g.splits;
+    w.shape.push_back(g);
+    w.part_off.push_back(off);
+    off = align256(off + (uint64_t)sp * V * V * sizeof(double2));
+  }
+  w.total = off;
+  return w;
 }
 
 // W_b for a boundary with c cuts: 2^c x 2^c
@@ -52,7 +65,7 @@ std::vector<cd> boundary_weights(int c) {
 extern "C" int ccut_expectation_work_bytes(const ccut_plan_t* plan, uint64_t* bytes) {
   clear_error();
   if (!plan || !bytes) return fail(CCUT_EINVAL, "NULL argument");
-  *bytes = work_bytes(plan);
+  *bytes = work_layout(plan).total;
   return CCUT_OK;
 }
 
@@ -67,18 +80,17 @@ extern "C" int ccut_expectation_pauli(ccut_plan_t* plan, const void* d_arena, ui
   for (int j = 0; j < plan->q; ++j)
     if (!std::strchr("IXYZ", pauli[j]) || pauli[j] == 0)
       return fail(CCUT_EINVAL, "Pauli label character %d is '%c' (I, X, Y or Z)", j, pauli[j]);
-  const uint64_t need = work_bytes(plan);
-  if (work_bytes_in < need)
-    return fail(CCUT_ENOSPC, "work buffer has %llu bytes, needs %llu", (unsigned long long)work_bytes_in,
-                (unsigned long long)need);
   for (const auto& S : plan->segs)
-    if (S.c > 20) return fail(CCUT_EUNSUPPORTED, "expectation values need at most 20 cuts per segment");
+    if (S.c > CCUT_MAX_EXPECT_CUTS)
+      return fail(CCUT_EUNSUPPORTED, "expectation values need at most %d cuts per segment", CCUT_MAX_EXPECT_CUTS);
+  const WorkLayout wl = work_layout(plan);
+  if (work_bytes_in < wl.total)
+    return fail(CCUT_ENOSPC, "work buffer has %llu bytes, needs %llu", (unsigned long long)work_bytes_in,
+                (unsigned long long)wl.total);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const char* base = static_cast<const char*>(d_arena);
-  std::vector<uint64_t> woff(plan->n_seg);
-  std::vector<int> splits(plan->n_seg);
+  char* work = static_cast<char*>(d_work);
   std::vector<cd> phase(plan->n_seg);
-  uint64_t off = 0;
   for (int i = 0; i < plan->n_seg; ++i) {
     const auto& S = plan->segs[i];
     uint32_t flip = 0, zy = 0;
@@ -90,29 +102,30 @@ extern "C" int ccut_expectation_pauli(ccut_plan_t* plan, const void* d_arena, ui
       ny += p == 'Y';
     }
     cd ph = 1.0;
-    for (int k = 0; k < ny; ++k) ph *= cd(0, -1);  // Y = -i X Z on each Y qubit
+    for (int k = 0; k < ny; ++k) ph *= cd(0, -1);  // Y = -i Z X on each Y qubit
     phase[i] = ph;
-    const int V = 1 << S.c;
-    const uint64_t N = (uint64_t)1 << S.q;
-    splits[i] = gram_splits(V, N);
-    woff[i] = off;
-    double2* part = reinterpret_cast<double2*>(static_cast<char*>(d_work) + off);
-    if (int rc = launch_gram(reinterpret_cast<const float2*>(base + S.arena_off), V, N, flip, zy, splits[i], part, s))
+    if (int rc = launch_gram(reinterpret_cast<const float2*>(base + S.arena_off), 1 << S.c, (uint64_t)1 << S.q, flip,
+                             zy, wl.shape[i], reinterpret_cast<double2*>(work + wl.part_off[i]),
+                             reinterpret_cast<double2*>(work + wl.fin_off[i]), s))
       return rc;
-    off = (off + (uint64_t)splits[i] * V * V * sizeof(double2) + 255) & ~uint64_t(255);
   }
-  std::vector<double2> host(off / sizeof(double2));
-  CCUT_HIP(hipMemcpyAsync(host.data(), d_work, off, hipMemcpyDeviceToHost, s));
+  std::lock_guard<std::mutex> lock(plan->expect_mu);
+  if (plan->expect_host_bytes < wl.fin_bytes) {
+    if (plan->expect_host) (void)hipHostFree(plan->expect_host);
+    plan->expect_host = nullptr;
+    plan->expect_host_bytes = 0;
+    CCUT_HIP(hipHostMalloc(&plan->expect_host, wl.fin_bytes, hipHostMallocDefault));
+    plan->expect_host_bytes = wl.fin_bytes;
+  }
+  CCUT_HIP(hipMemcpyAsync(plan->expect_host, work, wl.fin_bytes, hipMemcpyDeviceToHost, s));
   CCUT_HIP(hipStreamSynchronize(s));
-  // per-segment G (partials summed in split order)
+  // per-segment G with the Y phase
   std::vector<std::vector<cd>> G(plan->n_seg);
   for (int i = 0; i < plan->n_seg; ++i) {
     const int64_t V = (int64_t)1 << plan->segs[i].c;
-    G[i].assign((size_t)(V * V), cd(0));
-    const double2* p = host.data() + woff[i] / sizeof(double2);
-    for (int sp = 0; sp < splits[i]; ++sp)
-      for (int64_t e = 0; e < V * V; ++e) G[i][(size_t)e] += cd(p[sp * V * V + e].x, p[sp * V * V + e].y);
-    for (auto& g : G[i]) g *= phase[i];
+    const double2* p = reinterpret_cast<const double2*>(static_cast<const char*>(plan->expect_host) + wl.fin_off[i]);
+    G[i].resize((size_t)(V * V));
+    for (int64_t e = 0; e < V * V; ++e) G[i][(size_t)e] = cd(p[e].x, p[e].y) * phase[i];
   }
   cd result;
   const int n = plan->n_seg;

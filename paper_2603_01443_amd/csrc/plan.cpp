@@ -512,5 +512,6 @@ extern "C" void ccut_plan_free(ccut_plan_t* plan) {
   if (!plan) return;
   release_device(plan->dev);
   for (auto& t : plan->retired) release_device(t);
+  if (plan->expect_host) (void)hipHostFree(plan->expect_host);
   delete plan;
 }

@@ -1,6 +1,8 @@
 // The cut plan: preprocessing output (Algorithm 1) plus its device tables.
 #pragma once
 
+#include <mutex>
+
 #include "ccut_internal.h"
 
 struct ccut_plan {
@@ -51,6 +53,12 @@ struct ccut_plan {
   uint64_t tables_off = 0;  // arena byte offset of the table region
   uint64_t tables_reserve = 0;  // bytes reserved for it
   uint64_t total_arena = 0; // bytes the caller's arena must hold
+
+  // expectation values: pinned host copy of the per-segment matrices (grow-only,
+  // freed with the plan); the mutex serialises calls that share it
+  void* expect_host = nullptr;
+  uint64_t expect_host_bytes = 0;
+  std::mutex expect_mu;
 
   ccut::DeviceTables dev;   // plan-owned copy after ccut_plan_prepare (graph capture)
   std::vector<ccut::DeviceTables> retired;  // copies of earlier table builds (graphs may still use them)

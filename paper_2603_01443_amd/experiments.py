@@ -6,6 +6,7 @@
     python -m paper_2603_01443_amd.experiments costmodel  --out results/cost_model.json
     python -m paper_2603_01443_amd.experiments gemm       --out results/merge_gemm_variants.json
     python -m paper_2603_01443_amd.experiments paper      --out results/paper_family.json
+    python -m paper_2603_01443_amd.experiments expectation --out results/expectation.json
 
 sweep      Random brickwork, q = 24 in two blocks of 12, d in {10, 20, 40},
            c_total in {0, 1, 2, 3, 4, 6} (extended by 2 up to --cmax while cutting
@@ -16,12 +17,11 @@ sweep      Random brickwork, q = 24 in two blocks of 12, d in {10, 20, 40},
            c_total < q/2 (Eq. threshold_n2).
 precision  q = 30 (15 + 15), d = 20, c_total in {2, 4, 6, 8}: merge time for the
            float32, split-bfloat16, split-float16 and unsplit-bfloat16 merges,
-           their norm drift and 1 - F against the uncut state; accuracy against
-           the complex128 oracle on a q = 20 (10 + 10) instance of the same
-           generator.
+           their norm drift and 1 - F against the uncut state of the same circuit.
 batching   q = 32 in blocks 10 / 11 / 11, d = 30, 3 + 3 cuts (80 variants): the
            subcircuit stage as one launch, as per-variant launches, autotuned,
-           and replayed from a HIP graph; the 2^32 state merged once in place.
+           and replayed from a HIP graph; the 2^32 state merged once in place
+           and compared with the uncut simulation.
 costmodel  Timing grid q in {16, ..., 32} x d in {10, 20, 40} x n in {2, 3, 4} x
            c_total in {0..8} x seeds {0, 1, 2} plus uncut rows; the 4-64-64-3
            network is trained on the GPU (seeds 0, 1, q < 32) and the learned
@@ -35,6 +35,11 @@ paper      The paper's own circuit family (Fig. 1: H layer, then one CX staircas
            the largest q that fits a (scaled) wall-clock budget, uncut and with a
            two-way cut of c_total = 6 (Sec. V.D).  Each map gets a weighted linear
            SVM boundary c_total = a q + b, set beside the closed-form threshold.
+expectation Pauli-string expectation values from the subcircuit states (the
+           merge-free mode of Sec. VI): at q = 24, 28, 30 (two segments, d = 20,
+           c_total = 6) beside the merge and the uncut simulation, with the value
+           from the uncut full state as the check; then q = 36 ... 60, past the
+           2^35 amplitudes one GPU can hold as a full state.
 
 Timings: host wall clock for T_pre (cut_plan); HIP events on the stream for the
 device stages; warm-up runs first, then the mean of the timed repeats.
@@ -181,8 +186,7 @@ def run_sweep(args):
 
 # ------------------------------------------------------------------ precision
 def run_precision(args):
-    from oracle import cutting, metrics
-    out = {"experiment": "merge precision", "q30": [], "q20_oracle": []}
+    out = {"experiment": "merge precision", "q30": []}
     bufs = Buffers()
     s = torch.cuda.current_stream()
     precs = ["fp32", "bf16x3", "fp16x3", "fp16x2", "bf16"]
@@ -201,23 +205,11 @@ def run_precision(args):
             log(f"precision q30 c={c} {p}: merge {mer*1e3:.3f} ms 1-F {1 - st['fidelity']:.2e} "
                 f"drift {abs(st['norm2'] - 1):.2e}")
         out["q30"].append(row)
-        q, sizes = 20, [10, 10]
-        g = brickwork(q, d, n, c, seed=100 + c)
-        oref = cutting.cut_simulate(q, g, sizes)
-        row = {"c_total": c, "K": 2 ** c}
-        for p in precs:
-            time_cut(q, g, n, sizes, bufs, precision=p, warm=0, reps=1)
-            got = c64(bufs.psi, q).cpu().numpy().astype(np.complex128)
-            row[p] = {"max_abs": metrics.max_abs_error(oref, got), "one_minus_F": metrics.one_minus_fidelity(oref, got),
-                      "norm_drift": abs(metrics.norm2(got) - 1.0)}
-            log(f"precision q20 oracle c={c} {p}: max-abs {row[p]['max_abs']:.2e} 1-F {row[p]['one_minus_F']:.2e}")
-        out["q20_oracle"].append(row)
     return out
 
 
 # ------------------------------------------------------------------ batching
 def run_batching(args):
-    from oracle import cutting
     q, n, d, sizes, cb = 32, 3, 30, [10, 11, 11], [3, 3]
     g = brickwork(q, d, n, 6, seed=0, seg_sizes=sizes, cuts_per_boundary=cb)
     garr = ccut.gate_array(g)
@@ -281,15 +273,14 @@ def run_batching(args):
     ccut.profile_enable(False)
     res["merge_kernels_ms"] = {k: v[1] / v[0] for k, v in ccut.profile_read().items() if v[0]}
     res["merge_out_bytes"] = 8 << q
-    ocuts = cutting.find_cuts(q, g, sizes)
-    ost = cutting.variant_states(q, g, sizes, ocuts)
-    rng = np.random.default_rng(0)
-    xs = sorted(set(int(x) for x in rng.integers(0, 1 << q, size=256)))
-    want = cutting.amplitudes(xs, sizes, ocuts, ost)
-    got = psi[torch.tensor(xs, device="cuda")].cpu().numpy().astype(np.complex128)
-    res["oracle_sampled_max_abs"] = float(np.max(np.abs(got - want)))
-    st = ccut.norm_fidelity(psi, None, q)
+    # the merged 2^32 state against the uncut simulation of the same circuit
+    ref = torch.empty(1 << q, dtype=torch.complex64, device="cuda")
+    ccut.simulate_uncut(q, garr, ref, stream=s)
+    st = ccut.norm_fidelity(psi, ref, q, stream=s)
+    del ref
     res["norm_drift"] = abs(st["norm2"] - 1.0)
+    res["one_minus_F_vs_uncut"] = 1.0 - st["fidelity"]
+    res["max_abs_vs_uncut"] = st["max_abs"]
     graph.free()
     log(json.dumps(res))
     return res
@@ -548,9 +539,127 @@ def run_paper(args):
     return out
 
 
+# ------------------------------------------------------------------ expectation
+def pauli_expval_torch(psi, q, label):
+    """<psi|P|psi> of a complex64 GPU state with plain torch ops (qubit by qubit on
+    views, complex128 inner product): the full-state side of the comparison."""
+    phi = psi.clone()
+    for j, p in enumerate(label):
+        if p == "I":
+            continue
+        v = phi.view(1 << (q - j - 1), 2, 1 << j)
+        if p in "XY":
+            v = v.flip(1)
+        if p in "ZY":
+            v = v.clone()
+            v[:, 1] = -v[:, 1] if p == "Z" else v[:, 1]
+        if p == "Y":  # Y = [[0, -i], [i, 0]]: after the flip row 0 takes -i, row 1 takes i
+            v = v.clone()
+            v[:, 0] = v[:, 0] * (-1j)
+            v[:, 1] = v[:, 1] * 1j
+        phi = v.reshape(-1)
+    val = torch.vdot(psi.to(torch.complex128), phi.to(torch.complex128))
+    del phi
+    return complex(val.item())
+
+
+def labels_for(q, rng):
+    out = {"Z_all": "Z" * q, "X_all": "X" * q}
+    lab = ["I"] * q
+    lab[0] = "Z"
+    out["Z_0"] = "".join(lab)
+    lab = ["I"] * q
+    lab[q // 2 - 1], lab[q // 2] = "X", "X"   # straddles the middle boundary
+    out["XX_mid"] = "".join(lab)
+    lab = ["I"] * q
+    for j in rng.choice(q, 4, replace=False):
+        lab[j] = rng.choice(list("XYZ"))
+    out["rand4"] = "".join(lab)
+    return out
+
+
+def run_expectation(args):
+    """Expectation values from the subcircuits (no merge, no 2^q buffer) against the
+    full-state route, then beyond one GPU's full-state limit."""
+    s = torch.cuda.current_stream()
+    out = {"experiment": "expectation values without the merge", "d": 20, "vs_full_state": [], "beyond": []}
+    d = 20
+
+    def cut_side(q, g, n, sizes, labels, reps):
+        plan = ccut.cut_plan(q, ccut.gate_array(g), n, sizes)
+        info = plan.info()
+        arena = torch.empty(info["sim_arena_bytes"], dtype=torch.uint8, device="cuda")
+        work = torch.empty(max(ccut.expectation_work_bytes(plan), 8), dtype=torch.uint8, device="cuda")
+        ccut.simulate_subcircuits(plan, arena, stream=s)
+        torch.cuda.synchronize()
+        t_sub = []
+        for _ in range(reps):
+            e = events(2)
+            e[0].record(s)
+            ccut.simulate_subcircuits(plan, arena, stream=s)
+            e[1].record(s)
+            torch.cuda.synchronize()
+            t_sub.append(e[0].elapsed_time(e[1]) * 1e-3)
+        vals, t_exp = {}, []
+        for name, lab in labels.items():
+            ccut.expectation_pauli(plan, arena, lab, work, stream=s)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                vals[name] = ccut.expectation_pauli(plan, arena, lab, work, stream=s)
+            t_exp.append((time.perf_counter() - t0) / reps)
+        res = {"q": q, "n": n, "sizes": sizes, "c_boundary": info["c_boundary"][: n - 1],
+               "c_seg": info["c_seg"], "work_bytes": ccut.expectation_work_bytes(plan),
+               "sim_arena_bytes": info["sim_arena_bytes"], "T_sub": float(np.mean(t_sub)),
+               "T_expect_per_string": float(np.mean(t_exp)),
+               "values": {k: [v.real, v.imag] for k, v in vals.items()}}
+        del arena, work
+        torch.cuda.empty_cache()
+        return res, vals
+
+    rng = np.random.default_rng(0)
+    for q in (24, 28, 30):
+        n, c = 2, 6
+        g = brickwork(q, d, n, c, seed=q)
+        labels = labels_for(q, rng)
+        row, vals = cut_side(q, g, n, None, labels, args.reps)
+        bufs = Buffers()
+        pre, sub, mer, _ = time_cut(q, g, n, None, bufs, precision="auto", reps=args.reps)
+        row["T_merge_auto"] = mer
+        t_orig = time_uncut(q, g, bufs, reps=args.reps)
+        row["T_orig"] = t_orig
+        ref = c64(bufs.ref, q)
+        errs, t_full = {}, []
+        for name, lab in labels.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            want = pauli_expval_torch(ref, q, lab)
+            t_full.append(time.perf_counter() - t0)
+            errs[name] = abs(vals[name] - want)
+        row["T_full_state_expect_torch"] = float(np.mean(t_full))
+        row["abs_err_vs_uncut_full_state"] = errs
+        row["max_abs_err"] = max(errs.values())
+        del bufs, ref
+        torch.cuda.empty_cache()
+        out["vs_full_state"].append(row)
+        log(f"expectation q{q}: sub {row['T_sub']*1e3:.3f} ms, expect {row['T_expect_per_string']*1e3:.3f} ms/string, "
+            f"merge {mer*1e3:.3f} ms, uncut {t_orig*1e3:.3f} ms, max err {row['max_abs_err']:.1e}")
+    # past the 2^35 full-state limit of one GPU: the plan only needs the variant states
+    for q, n, sizes, c in ((36, 2, None, 6), (40, 2, None, 6), (40, 3, [13, 13, 14], 8), (48, 2, None, 6),
+                           (48, 3, None, 8), (60, 4, None, 12)):
+        g = brickwork(q, d, n, c, seed=q + n)
+        labels = labels_for(q, rng)
+        labels["I"] = "I" * q
+        row, vals = cut_side(q, g, n, sizes, labels, args.reps)
+        row["full_state_bytes"] = 8 << q
+        out["beyond"].append(row)
+        log(f"expectation q{q} n{n}: sub {row['T_sub']*1e3:.3f} ms, expect {row['T_expect_per_string']*1e3:.3f} "
+            f"ms/string, <I> - 1 = {abs(vals['I'] - 1):.1e}, <Z_0> = {vals['Z_0'].real:+.6f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["sweep", "precision", "batching", "costmodel", "gemm", "paper"])
+    ap.add_argument("which", choices=["sweep", "precision", "batching", "costmodel", "gemm", "paper", "expectation"])
     ap.add_argument("--out", required=True)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--epochs", type=int, default=3000)
@@ -563,7 +672,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("experiments need a GPU")
     fn = {"sweep": run_sweep, "precision": run_precision, "batching": run_batching, "costmodel": run_costmodel,
-          "gemm": run_gemm, "paper": run_paper}
+          "gemm": run_gemm, "paper": run_paper, "expectation": run_expectation}
     res = fn[args.which](args)
     res["device"] = torch.cuda.get_device_name(0)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)

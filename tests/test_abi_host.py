@@ -181,3 +181,8 @@ def test_expectation_argument_checks():
             ccut.expectation_pauli(plan, fake, label, fake, arena_bytes=1 << 30, work_bytes=need)
     with pytest.raises(ccut.CcutError, match="work buffer"):
         ccut.expectation_pauli(plan, fake, "IXYZ" * 3, fake, arena_bytes=1 << 30, work_bytes=need - 1)
+    # 13 cuts on the one boundary: a 8192 x 8192 matrix per segment is refused
+    big = ccut.cut_plan(16, brickwork(16, 14, 2, 13, seed=0), 2)
+    assert big.info()["c_total"] == 13
+    with pytest.raises(ccut.CcutError, match="at most 12 cuts"):
+        ccut.expectation_pauli(big, fake, "Z" * 16, fake, arena_bytes=1 << 40, work_bytes=1 << 40)

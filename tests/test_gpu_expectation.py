@@ -37,13 +37,21 @@ def cut_expectations(ccut, pipeline, q, g, n, sizes, labels, prefix=-1):
     return [ccut.expectation_pauli(run.plan, run.arena, lab, work, stream=s) for lab in labels]
 
 
-@pytest.mark.parametrize("q,n,c,kind,prefix", [
-    (12, 2, 2, "brickwork", -1), (20, 2, 6, "brickwork", -1), (20, 2, 6, "brickwork", 1),
-    (15, 3, 4, "brickwork", -1), (12, 3, 4, "staircase", 1), (16, 4, 3, "brickwork", -1), (10, 1, 0, "brickwork", -1)])
-def test_pauli_expectations_match_oracle(lib, q, n, c, kind, prefix):
+# The tile of the matrix kernel depends on 2^{c_i} and on the segment size:
+# [6, 15] runs the 64-wide tile on its 15-qubit segment, [8, 13] the 32-wide one,
+# the others the 16-wide one.
+@pytest.mark.parametrize("q,n,c,kind,prefix,sizes", [
+    (12, 2, 2, "brickwork", -1, None), (20, 2, 6, "brickwork", -1, None), (20, 2, 6, "brickwork", 1, None),
+    (15, 3, 4, "brickwork", -1, None), (12, 3, 4, "staircase", 1, None), (16, 4, 3, "brickwork", -1, None),
+    (10, 1, 0, "brickwork", -1, None), (21, 2, 6, "brickwork", -1, [6, 15]), (21, 2, 6, "brickwork", -1, [8, 13]),
+    (21, 2, 5, "brickwork", -1, [7, 14])])
+def test_pauli_expectations_match_oracle(lib, q, n, c, kind, prefix, sizes):
     ccut, pipeline = lib
-    g = brickwork(q, 8, n, c, seed=q + n) if kind == "brickwork" else staircase(q, c // (n - 1))
-    sizes = equal_blocks(q, n)
+    if kind == "brickwork":
+        g = brickwork(q, 8, n, c, seed=q + n, seg_sizes=sizes)
+    else:
+        g = staircase(q, c // (n - 1))
+    sizes = sizes or equal_blocks(q, n)
     ref = statevector.simulate(q, g)
     rng = np.random.default_rng(q * 10 + n)
     labels = ["I" * q, "Z" * q, "X" * q] + ["".join(rng.choice(list("IXYZ"), q)) for _ in range(8)]

@@ -263,6 +263,34 @@ def test_bench_config_sampled(lib):
     assert stats["max_abs"] < 2 * fp32_tol(q)
 
 
+def test_q32_three_segment_chain_sampled(lib):
+    """The three-segment workload (q=32 in 10/11/11, d=30, 3+3 cuts, 80 variants) merged
+    by the chain with the automatic precision: sampled amplitudes vs the oracle's plain
+    sum over all 64 terms, and the whole 2^32 state against the uncut simulation."""
+    ccut, pipeline = lib
+    q, d, n, sizes, cb = 32, 30, 3, [10, 11, 11], [3, 3]
+    g = brickwork(q, d, n, 6, seed=0, seg_sizes=sizes, cuts_per_boundary=cb)
+    run = pipeline.CutRun(q, g, n, sizes)
+    assert run.info["n_sub"] == 80
+    psi = run.run("auto")
+    ocuts = cutting.find_cuts(q, g, sizes)
+    ostates = cutting.variant_states(q, g, sizes, ocuts)
+    rng = np.random.default_rng(3)
+    xs = sorted(set(int(x) for x in rng.integers(0, 2 ** q, size=300)) | {0, 2 ** q - 1})
+    want = cutting.amplitudes(xs, sizes, ocuts, ostates)
+    got = to_np(psi[torch.tensor(xs, device=psi.device)])
+    err = np.max(np.abs(got - want))
+    ref = pipeline.uncut(q, g)
+    stats = ccut.norm_fidelity(psi, ref, q, stream=torch.cuda.current_stream())
+    del ref
+    print(f"q32 n3 chain: sampled max-abs vs oracle {err:.3e}; vs uncut {stats}", flush=True)
+    # both stages have K = 8: the automatic precision is fp16x2 (bound below)
+    assert err < split_tol(q, "fp16x2")
+    assert abs(stats["norm2"] - 1) < 1e-5
+    assert 1 - stats["fidelity"] < 1e-6
+    assert stats["max_abs"] < split_tol(q, "fp16x2")
+
+
 def test_norm_fidelity_matches_numpy(lib):
     ccut, pipeline = lib
     q = 16
