@@ -14,7 +14,9 @@
  * Every cross-segment CZ is cut with the rank-2 decomposition of Eq. (CZ),
  *   CZ = (S (x) S + i S^dag (x) S^dag) / (1 + i),   S = diag(1, i),
  * and every cross-segment CX through CX = (I (x) H) CZ (I (x) H) (Sec. II.A.2),
- * so the target side of a cut CX receives H S H or H S^dag H.
+ * so the target side of a cut CX receives H S H or H S^dag H.  The other
+ * two-qubit kinds (SWAP, iSWAP, RXX, RYY, RZZ) are cut through their
+ * operator-Schmidt decomposition, Eq. (schmidt), with k = 2 or 4 terms.
  *
  * Conventions shared by every call:
  *  - Qubit j is bit j of the amplitude index (little-endian, as in Qiskit,
@@ -52,7 +54,7 @@ extern "C" {
 /* ------------------------------------------------------------------ status */
 #define CCUT_OK 0
 #define CCUT_EINVAL (-1)        /* bad argument (q, sizes, gate kind, qubit index, NULL) */
-#define CCUT_EUNCUTTABLE (-2)   /* a gate other than CZ/CX crosses a segment boundary */
+#define CCUT_EUNCUTTABLE (-2)   /* a two-qubit gate joins two non-adjacent segments */
 #define CCUT_ENOSPC (-3)        /* a caller buffer is smaller than required */
 #define CCUT_ENOMEM (-4)        /* host or device allocation failed */
 #define CCUT_EHIP (-5)          /* a HIP runtime call failed */
@@ -67,7 +69,14 @@ enum {
   CCUT_GATE_RZ = 10,  /* exp(-i p0 Z / 2) */
   CCUT_GATE_RYRZ = 11,/* Ry(p0) . Rz(p1): Rz acts first */
   CCUT_GATE_CZ = 16,  /* symmetric in q0, q1 */
-  CCUT_GATE_CX = 17   /* q0 = control, q1 = target */
+  CCUT_GATE_CX = 17,  /* q0 = control, q1 = target */
+  /* Schmidt-rank-4 (and rank-2 Pauli-rotation) two-qubit gates, all symmetric
+     in q0, q1; each is exp(-i/2 (tx XX + ty YY + tz ZZ)) up to a phase: */
+  CCUT_GATE_SWAP = 18,  /* e^{i pi/4} exp(-i pi/4 (XX + YY + ZZ)) */
+  CCUT_GATE_ISWAP = 19, /* |01> -> i|10>, |10> -> i|01>: exp(+i pi/4 (XX + YY)) */
+  CCUT_GATE_RXX = 20,   /* exp(-i p0 XX / 2) */
+  CCUT_GATE_RYY = 21,   /* exp(-i p0 YY / 2) */
+  CCUT_GATE_RZZ = 22    /* exp(-i p0 ZZ / 2) */
 };
 
 /* One gate.  Single-qubit kinds ignore q1 (set it to -1); 32 bytes. */
@@ -90,10 +99,11 @@ typedef struct ccut_plan_info {
   int32_t n_gates;                     /* gates in the input circuit */
   int32_t seg_size[CCUT_MAX_SEG];      /* q_i */
   int32_t seg_offset[CCUT_MAX_SEG];    /* first qubit of segment i */
-  int32_t c_seg[CCUT_MAX_SEG];         /* c_i: cuts adjacent to segment i */
-  int32_t c_boundary[CCUT_MAX_SEG];    /* c_b: cuts between segments b and b+1 */
-  int64_t n_sub;                       /* N_sub = sum_i 2^{c_i}            (Sec. III.A) */
-  int64_t n_terms;                     /* 2^{c_total} global merge terms   (Algorithm 3) */
+  int32_t c_seg[CCUT_MAX_SEG];         /* c_i: variant bits of segment i (one per adjacent
+                                          rank-2 cut, two per rank-4 cut) */
+  int32_t c_boundary[CCUT_MAX_SEG];    /* c_b: variant bits of the cuts between segments b and b+1 */
+  int64_t n_sub;                       /* N_sub = sum_i 2^{c_i} = sum_i k^{cuts_i}  (Sec. III.A) */
+  int64_t n_terms;                     /* 2^{sum_b c_b} global merge terms (Algorithm 3) */
   uint64_t seg_state_offset[CCUT_MAX_SEG]; /* byte offset of segment i's variant 0 in the arena */
   uint64_t state_bytes;                /* bytes of all subcircuit states */
   uint64_t arena_bytes;                /* the whole pipeline (simulation + merge workspace): size the arena to this */
@@ -102,14 +112,16 @@ typedef struct ccut_plan_info {
 } ccut_plan_info_t;
 
 typedef struct ccut_cut_info {
-  int32_t gate_index; /* position in the input gate list */
-  int32_t kind;       /* CCUT_GATE_CZ or CCUT_GATE_CX */
+  int32_t gate_index; /* position in the input gate list (the first gate of a fused run) */
+  int32_t kind;       /* gate kind (of the first gate of a fused run) */
   int32_t boundary;   /* b: the cut joins segments b and b+1 */
   int32_t q_low;      /* its qubit in segment b */
   int32_t q_high;     /* its qubit in segment b+1 */
   int32_t target_high;/* CX only: 1 if the target sits in segment b+1 */
-  int32_t bit_low;    /* bit of this cut in segment b's variant index */
-  int32_t bit_high;   /* bit of this cut in segment b+1's variant index */
+  int32_t bit_low;    /* first bit of this cut in segment b's variant index */
+  int32_t bit_high;   /* first bit of this cut in segment b+1's variant index */
+  int32_t n_bits;     /* variant bits of the cut: 1 (rank 2), 2 (rank 4) */
+  int32_t n_gates;    /* gates fused into this cut (1 unless a run of Pauli-rotation gates) */
 } ccut_cut_info_t;
 
 /*
@@ -128,16 +140,31 @@ typedef struct ccut_cut_info {
  *              floor(q/n) per block with the remainder on the last blocks
  *   plan_out   receives the plan; free it with ccut_plan_free
  *
+ * Cut decompositions (Sec. II.A.2, Eqs. CZ and schmidt): CZ and CX use the
+ * rank-2 form of Eq. (CZ), one variant bit (0: S term, 1: S^dag term).  The
+ * other two-qubit kinds are cut through their operator-Schmidt decomposition:
+ * every one of them is c * exp(-i/2 (tx XX + ty YY + tz ZZ)), which expands
+ * exactly as sum_P c_P P (x) P over P in {I, X, Y, Z} (the Pauli products are
+ * orthogonal, so this is the Schmidt form).  With two nonzero c_P (RXX, RYY,
+ * RZZ alone) the cut has rank 2: one bit choosing between the two Paulis on
+ * both sides.  Otherwise (SWAP, iSWAP, products) it has rank 4: two bits
+ * (b0, b1) apply X^{b0} Z^{b1} on both sides with weights (c_I, c_X, c_Z,
+ * -c_Y) for b0 + 2 b1 = 0..3 (Y = i X Z).  Consecutive Pauli-rotation gates
+ * on the same cross-boundary pair, with nothing in between on either qubit,
+ * commute and are fused into one cut: a general two-qubit unitary written as
+ * local gates around RXX RYY RZZ costs one rank-4 cut.
+ *
  * Cuts are numbered boundary by boundary (lowest boundary first) and in gate
- * order within a boundary.  Variant index r of segment i: its bits [0, c_{i-1})
- * select the cuts on the boundary below it, the next c_i' bits those on the
- * boundary above it (bit = 0: S term, 1: S^dag term).
+ * order within a boundary; each takes n_bits consecutive variant bits.
+ * Variant index r of segment i: its bits [0, c_{i-1}) select the terms of the
+ * cuts on the boundary below it, the next c_i' bits those on the boundary
+ * above it.
  * Arena layout: segment-major, then variant r, each state 2^{q_i} complex64
  * at seg_state_offset[i] + r * 8 * 2^{q_i} (256-byte aligned bases).
  *
  * Errors: CCUT_EINVAL (bad q, sizes, qubit or kind), CCUT_EUNCUTTABLE (a
- * non-CZ/CX gate, or a CZ/CX between non-adjacent segments, crosses a
- * boundary), CCUT_EUNSUPPORTED (some c_i > CCUT_MAX_CUTS_PER_SEG).
+ * two-qubit gate between non-adjacent segments), CCUT_EUNSUPPORTED (some
+ * c_i > CCUT_MAX_CUTS_PER_SEG variant bits).
  */
 int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gates, int32_t n_seg,
                   const int32_t* seg_sizes, ccut_plan_t** plan_out);
@@ -154,6 +181,15 @@ int ccut_plan_cut(const ccut_plan_t* plan, int32_t j, ccut_cut_info_t* out);
  * over all cuts.  Writes (re, im) in float64 to out[0..1].  Host-only.
  */
 int ccut_cut_weight(int32_t bit, double out[2]);
+
+/*
+ * Weights of the 2^{n_bits} terms of cut j (term t = its variant bits read as
+ * an integer), (re, im) in float64 to w[2t], w[2t+1]; w holds 8 doubles.  For
+ * CZ / CX these are s_0, s_1 of Eq. (CZ); for the other kinds the Schmidt
+ * coefficients described at ccut_cut_plan.  The weight alpha_m of a global
+ * combination is the product over all cuts.  Host-only.
+ */
+int ccut_plan_cut_terms(const ccut_plan_t* plan, int32_t j, double w[8]);
 
 /* Frees a plan and its device tables.  NULL is ignored. */
 void ccut_plan_free(ccut_plan_t* plan);

@@ -45,7 +45,11 @@ GATE_KINDS = {
     "H": 0, "X": 1, "Y": 2, "Z": 3, "S": 4, "SDG": 5, "T": 6, "TDG": 7,
     "RX": 8, "RY": 9, "RZ": 10, "RYRZ": 11,
     "CZ": 16, "CX": 17,
+    "SWAP": 18, "ISWAP": 19, "RXX": 20, "RYY": 21, "RZZ": 22,
 }
+# Two-qubit kinds; all but CX are symmetric in (q0, q1).
+#   SWAP, ISWAP (|01> -> i|10>, |10> -> i|01>), RXX/RYY/RZZ: exp(-i p0 PP / 2).
+TWO_QUBIT = ("CZ", "CX", "SWAP", "ISWAP", "RXX", "RYY", "RZZ")
 
 
 class Gate(NamedTuple):
@@ -102,10 +106,28 @@ def boundary_qubits(seg_sizes: Sequence[int]) -> List[int]:
     return out
 
 
+def _pair_gates(kind: str, a: int, b: int, rng: "SplitMix64") -> List[Gate]:
+    """The gates placed on pair (a, b): one gate of ``kind``, or for "CAN" the run
+    RXX, RYY, RZZ with three drawn angles (a general two-qubit interaction)."""
+    if kind in ("CZ", "CX", "SWAP", "ISWAP"):
+        return [Gate(kind, a, b)]
+    if kind in ("RXX", "RYY", "RZZ"):
+        return [Gate(kind, a, b, TWO_PI * rng.uniform())]
+    if kind == "CAN":
+        return [Gate(k, a, b, TWO_PI * rng.uniform()) for k in ("RXX", "RYY", "RZZ")]
+    raise ValueError(f"unknown pair gate {kind}")
+
+
 def brickwork(q: int, d: int, n: int, c_total: int, seed: int,
               seg_sizes: Optional[Sequence[int]] = None,
-              cuts_per_boundary: Optional[Sequence[int]] = None) -> List[Gate]:
-    """Random Ry.Rz + CZ brickwork with exactly c_b CZs across boundary b."""
+              cuts_per_boundary: Optional[Sequence[int]] = None,
+              boundary_gate: str = "CZ", bulk_gate: str = "CZ") -> List[Gate]:
+    """Random Ry.Rz + CZ brickwork with exactly c_b two-qubit gates across boundary b.
+
+    ``boundary_gate`` / ``bulk_gate`` replace the CZ on the boundary pairs / on the
+    other pairs by another two-qubit kind ("CAN": an RXX, RYY, RZZ run).  Angles of
+    those gates are drawn right after the layer's single-qubit angles, pair by pair;
+    with the CZ defaults nothing extra is drawn."""
     sizes = list(seg_sizes) if seg_sizes is not None else equal_blocks(q, n)
     if len(sizes) != n or sum(sizes) != q or min(sizes) < 1:
         raise ValueError(f"bad segment sizes {sizes} for q={q}, n={n}")
@@ -126,10 +148,10 @@ def brickwork(q: int, d: int, n: int, c_total: int, seed: int,
             gates.append(Gate("RYRZ", j, -1, theta, phi))
         for i in range(layer % 2, q - 1, 2):
             if (i, i + 1) not in boundary_pairs:
-                gates.append(Gate("CZ", i, i + 1))
+                gates += _pair_gates(bulk_gate, i, i + 1, rng)
         for b, beta in enumerate(betas):
             if layer in cut_layers[b]:
-                gates.append(Gate("CZ", beta - 1, beta))
+                gates += _pair_gates(boundary_gate, beta - 1, beta, rng)
     return gates
 
 

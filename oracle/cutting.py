@@ -22,6 +22,14 @@ Reading taken where the paper is loose: Algorithm 3 and Table I count
 2^{c_total} (they coincide for n <= 3).  This oracle sums all 2^{c_total}
 combinations, which is what the exact identity requires.
 
+Other two-qubit gates (SWAP, iSWAP, RXX, RYY, RZZ) are cut through the
+operator-Schmidt decomposition of Eq. (schmidt): U = sum_l s_l A_l (x) B_l.
+This oracle obtains it from the singular value decomposition of the 4x4
+matrix realigned so that rows index qubit q0's (row, column) pair and columns
+qubit q1's; the rank k (1, 2 or 4) is the number of nonzero singular values
+and every cut contributes k terms.  A variant key then lists, per adjacent
+cut, the index of its term (0/1 = S / S^dagger for CZ and CX).
+
 Segment 0 holds the lowest-index qubits; the Kronecker product places
 segment 0 in the least significant position (little-endian, Qiskit order).
 """
@@ -33,8 +41,8 @@ from typing import Dict, List, NamedTuple, Sequence, Tuple
 
 import numpy as np
 
-from .gates import H, S, SDG
-from .statevector import apply_1q, simulate
+from .gates import H, S, SDG, two_qubit_matrix
+from .statevector import apply_1q, apply_2q, simulate
 
 S0 = 1.0 / (1.0 + 1.0j)      # weight of the S (x) S term, Eq. (CZ)
 S1 = 1.0j / (1.0 + 1.0j)     # weight of the S^dagger (x) S^dagger term, Eq. (CZ)
@@ -42,9 +50,35 @@ S1 = 1.0j / (1.0 + 1.0j)     # weight of the S^dagger (x) S^dagger term, Eq. (CZ
 
 class Cut(NamedTuple):
     gate_index: int
-    kind: str          # "CZ" or "CX"
+    kind: str          # gate kind ("CZ", "CX", "SWAP", ...)
     qubits: Tuple[int, int]   # (q0, q1) as in the gate (CX: control, target)
     segs: Tuple[int, int]     # segment of q0, segment of q1
+    p0: float = 0.0           # angle of RXX / RYY / RZZ
+
+
+def schmidt_terms(u: np.ndarray, tol: float = 1e-12) -> List[Tuple[complex, np.ndarray, np.ndarray]]:
+    """Operator-Schmidt decomposition (Eq. schmidt) of a 4x4 matrix acting on (q0, q1)
+    with index bit(q0) + 2 bit(q1): terms (s_l, A_l on q0, B_l on q1), nonzero s_l only.
+
+    u[(a0 + 2 a1), (b0 + 2 b1)] = sum_l s_l A_l[a0, b0] B_l[a1, b1]; realigning to
+    R[(a0, b0), (a1, b1)] turns this into the singular value decomposition of R."""
+    u4 = np.asarray(u, dtype=np.complex128).reshape(2, 2, 2, 2)      # [a1, a0, b1, b0]
+    r = u4.transpose(1, 3, 0, 2).reshape(4, 4)                         # [(a0, b0), (a1, b1)]
+    left, sv, right = np.linalg.svd(r)
+    return [(complex(sv[l]), left[:, l].reshape(2, 2), right[l, :].reshape(2, 2))
+            for l in range(4) if sv[l] > tol * sv[0]]
+
+
+def cut_terms(c: Cut) -> List[Tuple[complex, np.ndarray, np.ndarray]]:
+    """The terms (weight, matrix on q0, matrix on q1) a cut contributes.
+
+    CZ and CX: Eq. (CZ), S (x) S with s_0 and S^dagger (x) S^dagger with s_1 (H S H
+    on the target of a CX).  Other kinds: the Schmidt terms of their matrix."""
+    if c.kind == "CZ":
+        return [(S0, S, S), (S1, SDG, SDG)]
+    if c.kind == "CX":
+        return [(S0, S, H @ S @ H), (S1, SDG, H @ SDG @ H)]
+    return schmidt_terms(two_qubit_matrix(c.kind, c.p0))
 
 
 class LocalGate(NamedTuple):
@@ -83,9 +117,9 @@ def find_cuts(q: int, gates: Sequence, sizes: Sequence[int]) -> List[Cut]:
         sa, sb = seg[g.q0], seg[g.q1]
         if sa == sb:
             continue
-        if g.kind not in ("CZ", "CX"):
-            raise ValueError(f"gate {k} ({g.kind}) crosses a boundary and is not CZ/CX")
-        cuts.append(Cut(k, g.kind, (g.q0, g.q1), (sa, sb)))
+        if abs(sa - sb) != 1:
+            raise ValueError(f"gate {k} ({g.kind}) joins non-adjacent segments")
+        cuts.append(Cut(k, g.kind, (g.q0, g.q1), (sa, sb), g.p0))
     return cuts
 
 
@@ -95,16 +129,24 @@ def adjacent_cuts(cuts: Sequence[Cut], i: int) -> List[int]:
 
 
 def n_subcircuits(cuts: Sequence[Cut], n: int) -> int:
-    """N_sub = sum_i 2^{c_i} (Sec. III.A with Schmidt rank k = 2)."""
-    return sum(2 ** len(adjacent_cuts(cuts, i)) for i in range(n))
+    """N_sub = sum_i prod over the cuts adjacent to segment i of their rank k_j
+    (Sec. III.A: sum_i k^{c_i} when every cut has rank k)."""
+    total = 0
+    for i in range(n):
+        v = 1
+        for j in adjacent_cuts(cuts, i):
+            v *= len(cut_terms(cuts[j]))
+        total += v
+    return total
 
 
 def subcircuit(gates: Sequence, sizes: Sequence[int], i: int, cuts: Sequence[Cut],
                bits: Dict[int, int]) -> List[LocalGate]:
-    """Algorithm 1: the gate list of segment i for one assignment of its cut bits.
+    """Algorithm 1: the gate list of segment i for one assignment of its cut terms.
 
-    ``bits`` maps a cut index (into ``cuts``) to 0 (S term) or 1 (S^dagger term).
-    Qubits are renumbered to the segment's local register.
+    ``bits`` maps a cut index (into ``cuts``) to the index of its term (for CZ and
+    CX: 0 = S term, 1 = S^dagger term).  Qubits are renumbered to the segment's
+    local register.
     """
     off = segment_offsets(sizes)[i]
     seg = segment_of_qubit(sizes)
@@ -118,16 +160,13 @@ def subcircuit(gates: Sequence, sizes: Sequence[int], i: int, cuts: Sequence[Cut
                 continue
             side = 0 if c.segs[0] == i else 1
             local = c.qubits[side] - off
-            phase = S if bits[j] == 0 else SDG
-            if c.kind == "CX" and side == 1:          # target of a cut CX: H S H
-                out.append(LocalGate("U", local, matrix=H @ phase @ H))
-            else:
-                out.append(LocalGate("U", local, matrix=phase))
+            _, a, b = cut_terms(c)[bits[j]]
+            out.append(LocalGate("U", local, matrix=a if side == 0 else b))
             continue
         if seg[g.q0] != i:
             continue
         if g.q1 >= 0:
-            out.append(LocalGate(g.kind, g.q0 - off, g.q1 - off))
+            out.append(LocalGate(g.kind, g.q0 - off, g.q1 - off, g.p0))
         else:
             out.append(LocalGate(g.kind, g.q0 - off, -1, g.p0, g.p1))
     return out
@@ -146,6 +185,8 @@ def simulate_local(nq: int, local: Sequence[LocalGate]) -> np.ndarray:
             psi = apply_cz(psi, nq, g.q0, g.q1)
         elif g.kind == "CX":
             psi = apply_cx(psi, nq, g.q0, g.q1)
+        elif g.q1 >= 0:
+            psi = apply_2q(psi, nq, g.q0, g.q1, two_qubit_matrix(g.kind, g.p0))
         else:
             psi = apply_1q(psi, nq, g.q0, one_qubit_matrix(g.kind, g.p0, g.p1))
     return psi
@@ -153,37 +194,47 @@ def simulate_local(nq: int, local: Sequence[LocalGate]) -> np.ndarray:
 
 def variant_states(q: int, gates: Sequence, sizes: Sequence[int],
                    cuts: Sequence[Cut] | None = None) -> Dict[Tuple[int, Tuple[int, ...]], np.ndarray]:
-    """Algorithm 2: every subcircuit state, keyed by (segment, bits of its adjacent cuts in gate order)."""
+    """Algorithm 2: every subcircuit state, keyed by (segment, term indices of its adjacent cuts in gate order)."""
     if cuts is None:
         cuts = find_cuts(q, gates, sizes)
     out = {}
     for i, nq in enumerate(sizes):
         adj = adjacent_cuts(cuts, i)
-        for b in itertools.product((0, 1), repeat=len(adj)):
+        for b in itertools.product(*[range(len(cut_terms(cuts[j]))) for j in adj]):
             bits = dict(zip(adj, b))
             out[(i, tuple(b))] = simulate_local(nq, subcircuit(gates, sizes, i, cuts, bits))
     return out
 
 
-def alpha(bits: Sequence[int]) -> complex:
-    """alpha_m = product over cuts of s_{b_j}, from Eq. (CZ)."""
+def alpha(bits: Sequence[int], cuts: Sequence[Cut] | None = None) -> complex:
+    """alpha_m = product over cuts of the weight of the chosen term: s_{b_j} from
+    Eq. (CZ) for CZ / CX (the default when ``cuts`` is omitted), the Schmidt
+    coefficient for the other kinds."""
     a = 1.0 + 0.0j
-    for b in bits:
-        a *= S0 if b == 0 else S1
+    for j, b in enumerate(bits):
+        if cuts is None:
+            a *= S0 if b == 0 else S1
+        else:
+            a *= cut_terms(cuts[j])[b][0]
     return a
 
 
+def combinations(cuts: Sequence[Cut]):
+    """Every global combination m: one term index per cut."""
+    return itertools.product(*[range(len(cut_terms(c))) for c in cuts])
+
+
 def merge(sizes: Sequence[int], cuts: Sequence[Cut], states) -> np.ndarray:
-    """Algorithm 3: plain sum over all 2^{c_total} global combinations."""
+    """Algorithm 3: plain sum over all global combinations (2^{c_total} for rank-2 cuts)."""
     n = len(sizes)
     adj = [adjacent_cuts(cuts, i) for i in range(n)]
     psi = None
-    for m in itertools.product((0, 1), repeat=len(cuts)):
+    for m in combinations(cuts):
         phi = np.ones(1, dtype=np.complex128)
         for i in range(n):                      # segment 0 ends up least significant
             r = tuple(m[j] for j in adj[i])
             phi = np.kron(states[(i, r)], phi)
-        term = alpha(m) * phi
+        term = alpha(m, cuts) * phi
         psi = term if psi is None else psi + term
     return psi
 
@@ -201,12 +252,13 @@ def amplitudes(xs: Sequence[int], sizes: Sequence[int], cuts: Sequence[Cut], sta
     off = segment_offsets(sizes)
     adj = [adjacent_cuts(cuts, i) for i in range(n)]
     out = np.zeros(len(xs), dtype=np.complex128)
-    combos = list(itertools.product((0, 1), repeat=len(cuts)))
+    combos = list(combinations(cuts))
+    weights = [alpha(m, cuts) for m in combos]
     for t, x in enumerate(xs):
         local = [(int(x) >> off[i]) & ((1 << sizes[i]) - 1) for i in range(n)]
         acc = 0.0 + 0.0j
-        for m in combos:
-            term = alpha(m)
+        for m, w in zip(combos, weights):
+            term = w
             for i in range(n):
                 term *= states[(i, tuple(m[j] for j in adj[i]))][local[i]]
             acc += term

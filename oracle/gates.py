@@ -52,4 +52,37 @@ def one_qubit_matrix(kind: str, p0: float = 0.0, p1: float = 0.0) -> np.ndarray:
     raise ValueError(f"not a single-qubit gate kind: {kind}")
 
 
-TWO_QUBIT_KINDS = ("CZ", "CX")
+TWO_QUBIT_KINDS = ("CZ", "CX", "SWAP", "ISWAP", "RXX", "RYY", "RZZ")
+
+# Two-qubit matrices act on (q0, q1) with row/column index i = bit(q0) + 2 bit(q1).
+SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], dtype=np.complex128)
+# iSWAP: |01> -> i|10>, |10> -> i|01>, |00> and |11> unchanged
+ISWAP = np.array([[1, 0, 0, 0], [0, 0, 1j, 0], [0, 1j, 0, 0], [0, 0, 0, 1]], dtype=np.complex128)
+CZ4 = np.diag([1, 1, 1, -1]).astype(np.complex128)
+# CX with control q0 (bit 0) and target q1 (bit 1): flips bit 1 where bit 0 is set
+CX4 = np.array([[1, 0, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0], [0, 1, 0, 0]], dtype=np.complex128)
+
+
+def pauli_rotation(p: np.ndarray, t: float) -> np.ndarray:
+    """exp(-i t P(x)P / 2) = cos(t/2) I - i sin(t/2) P(x)P, since (P(x)P)^2 = I."""
+    pp = np.kron(p, p)
+    return np.cos(t / 2) * np.eye(4, dtype=np.complex128) - 1j * np.sin(t / 2) * pp
+
+
+def two_qubit_matrix(kind: str, p0: float = 0.0) -> np.ndarray:
+    """4x4 matrix of a two-qubit gate kind (index bit(q0) + 2 bit(q1))."""
+    if kind == "CZ":
+        return CZ4
+    if kind == "CX":
+        return CX4
+    if kind == "SWAP":
+        return SWAP
+    if kind == "ISWAP":
+        return ISWAP
+    if kind == "RXX":
+        return pauli_rotation(X, p0)
+    if kind == "RYY":
+        return pauli_rotation(Y, p0)
+    if kind == "RZZ":
+        return pauli_rotation(Z, p0)
+    raise ValueError(f"not a two-qubit gate kind: {kind}")

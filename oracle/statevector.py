@@ -13,7 +13,7 @@ from typing import Iterable
 
 import numpy as np
 
-from .gates import one_qubit_matrix
+from .gates import one_qubit_matrix, two_qubit_matrix
 
 
 def zero_state(q: int) -> np.ndarray:
@@ -44,11 +44,25 @@ def apply_cx(psi: np.ndarray, q: int, c: int, t: int) -> np.ndarray:
     return psi[src]
 
 
+def apply_2q(psi: np.ndarray, q: int, a: int, b: int, u: np.ndarray) -> np.ndarray:
+    """Apply a 4x4 matrix to qubits (a, b), its index being bit a + 2 bit b."""
+    idx = np.arange(1 << q, dtype=np.int64)
+    ba, bb = (idx >> a) & 1, (idx >> b) & 1
+    rest = idx & ~((1 << a) | (1 << b))
+    out = np.zeros_like(psi)
+    for j in range(4):                      # source column: bits (j & 1, j >> 1) on (a, b)
+        src = rest | ((j & 1) << a) | ((j >> 1) << b)
+        out += u[ba + 2 * bb, j] * psi[src]
+    return out
+
+
 def apply_gate(psi: np.ndarray, q: int, g) -> np.ndarray:
     if g.kind == "CZ":
         return apply_cz(psi, q, g.q0, g.q1)
     if g.kind == "CX":
         return apply_cx(psi, q, g.q0, g.q1)
+    if g.q1 >= 0:
+        return apply_2q(psi, q, g.q0, g.q1, two_qubit_matrix(g.kind, g.p0))
     return apply_1q(psi, q, g.q0, one_qubit_matrix(g.kind, g.p0, g.p1))
 
 

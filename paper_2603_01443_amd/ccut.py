@@ -33,6 +33,7 @@ PRECISIONS = {"auto": PREC_AUTO, "fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "fp16
 GATE_KIND = {
     "H": 0, "X": 1, "Y": 2, "Z": 3, "S": 4, "SDG": 5, "T": 6, "TDG": 7,
     "RX": 8, "RY": 9, "RZ": 10, "RYRZ": 11, "CZ": 16, "CX": 17,
+    "SWAP": 18, "ISWAP": 19, "RXX": 20, "RYY": 21, "RZZ": 22,
 }
 
 GATE_DTYPE = np.dtype([("kind", "<i4"), ("q0", "<i4"), ("q1", "<i4"), ("reserved", "<i4"),
@@ -60,7 +61,8 @@ class PlanInfo(ctypes.Structure):
 
 class CutInfo(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int32) for name in
-                ("gate_index", "kind", "boundary", "q_low", "q_high", "target_high", "bit_low", "bit_high")]
+                ("gate_index", "kind", "boundary", "q_low", "q_high", "target_high", "bit_low", "bit_high",
+                 "n_bits", "n_gates")]
 
 
 def _load():
@@ -80,6 +82,7 @@ def _load():
         "ccut_plan_info": [vp, ctypes.POINTER(PlanInfo)],
         "ccut_plan_cut": [vp, i32, ctypes.POINTER(CutInfo)],
         "ccut_cut_weight": [i32, ctypes.POINTER(ctypes.c_double)],
+        "ccut_plan_cut_terms": [vp, i32, ctypes.POINTER(ctypes.c_double)],
         "ccut_plan_prepare": [vp],
         "ccut_simulate_subcircuits": [vp, vp, u64, vp],
         "ccut_merge_full_state": [vp, vp, u64, vp, u64, i32, vp],
@@ -227,6 +230,13 @@ class Plan:
             _check(_lib.ccut_plan_cut(self._h, j, ctypes.byref(c)))
             out.append({f: getattr(c, f) for f, _ in CutInfo._fields_})
         return out
+
+    def cut_terms(self, j: int) -> List[complex]:
+        """Weights of cut j's 2^{n_bits} terms (term t = its variant bits as an integer)."""
+        out = (ctypes.c_double * 8)()
+        _check(_lib.ccut_plan_cut_terms(self._h, j, out))
+        n = 1 << self.cuts()[j]["n_bits"]
+        return [complex(out[2 * t], out[2 * t + 1]) for t in range(n)]
 
     def free(self) -> None:
         if self._h and self._h.value:
@@ -487,6 +497,13 @@ class Graph:
 
     def launch(self, stream=None) -> None:
         _check(_lib.ccut_graph_launch(self._h, _stream(stream)))
+
+    def cut_terms(self, j: int) -> List[complex]:
+        """Weights of cut j's 2^{n_bits} terms (term t = its variant bits as an integer)."""
+        out = (ctypes.c_double * 8)()
+        _check(_lib.ccut_plan_cut_terms(self._h, j, out))
+        n = 1 << self.cuts()[j]["n_bits"]
+        return [complex(out[2 * t], out[2 * t + 1]) for t in range(n)]
 
     def free(self) -> None:
         if self._h and self._h.value:

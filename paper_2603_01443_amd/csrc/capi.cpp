@@ -213,17 +213,8 @@ int compile_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, UncutPro
   ProgramBuilder pb(q);
   for (int64_t k = 0; k < n_gates; ++k) {
     const ccut_gate_t& g = gates[k];
-    const bool two = g.kind == CCUT_GATE_CZ || g.kind == CCUT_GATE_CX;
-    const bool one = g.kind >= CCUT_GATE_H && g.kind <= CCUT_GATE_RYRZ;
-    if ((!one && !two) || g.q0 < 0 || g.q0 >= q || (two && (g.q1 < 0 || g.q1 >= q || g.q1 == g.q0)))
-      return fail(CCUT_EINVAL, "gate %lld is invalid for q=%d", (long long)k, q);
-    if (g.kind == CCUT_GATE_CZ) pb.cz(g.q0, g.q1);
-    else if (g.kind == CCUT_GATE_CX) pb.cx(g.q0, g.q1);
-    else {
-      cd m[4];
-      gate_matrix(g, m);
-      pb.one_qubit(g.q0, m, m, -1);
-    }
+    if (int rc = check_gate(g, q, k)) return rc;
+    pb.gate(g, 0);
   }
   std::vector<Pass> passes;
   if (int rc = schedule_passes(pb.prog, PASS_MAX_B, 4, passes)) return rc;

@@ -42,6 +42,18 @@ struct Program {
   std::vector<HOp> ops;
 };
 
+// ------------------------------------------------------- gate kinds
+bool is_two_qubit_kind(int kind);
+// SWAP, iSWAP, RXX, RYY, RZZ: each is phase * exp(-i/2 (tx XX + ty YY + tz ZZ))
+bool is_pauli_rotation_kind(int kind);
+void pauli_rotation_form(const ccut_gate_t& g, double t[3], cd* phase);
+// exp(-i/2 (t0 XX + t1 YY + t2 ZZ)) = sum_P c[P] P (x) P with P = I, X, Y, Z (the
+// three rotations commute; expanding cos(t/2) - i sin(t/2) PP and using
+// XX YY = -ZZ and its cyclic forms gives the four coefficients)
+void pauli_rotation_coeffs(const double t[3], cd c[4]);
+// Validates gate k of a circuit on q qubits (kind and qubit indices).
+int check_gate(const ccut_gate_t& g, int q, int64_t k);
+
 // Append a single-qubit matrix, fusing it into the previous single-qubit op on
 // that qubit when every op in between on the qubit commutes with it.
 struct ProgramBuilder {
@@ -52,6 +64,9 @@ struct ProgramBuilder {
   void one_qubit(int t, const cd m0[4], const cd m1[4], int slot);
   void cz(int a, int b);
   void cx(int c, int t);
+  // Any gate of the circuit whose qubits all lie in this register (qubit indices
+  // minus `off`); the Pauli-rotation kinds go through exact CX decompositions.
+  void gate(const ccut_gate_t& g, int off);
 };
 
 // --------------------------------------------------------- device op format

@@ -4,8 +4,9 @@
 //   E_0[u][u']  = W_0[u][u'] G_0[u][u']
 //   E_i[v][v']  = W_i[v][v'] sum_{u,u'} E_{i-1}[u][u'] G_i[u + 2^{c_{i-1}} v][u' + 2^{c_{i-1}} v']
 //   <O>         = sum_{u,u'} E_{n-2}[u][u'] G_{n-1}[u][u']
-// with W_b[u][u'] = prod over the cuts j of boundary b of conj(s_{u_j}) s_{u'_j}
-// (s_0 = 1/(1+i), s_1 = i/(1+i), Eq. CZ) and segment i's variant index
+// with W_b[u][u'] = conj(w_b(u)) w_b(u'), where w_b(u) is the product of the
+// term weights of boundary b's cuts (s_0 = 1/(1+i), s_1 = i/(1+i) for CZ / CX,
+// Eq. CZ; the Schmidt coefficients for the other kinds) and segment i's variant index
 // r = (lower-boundary bits) + 2^{c_{i-1}} (upper-boundary bits).
 #include <complex>
 #include <cstring>
@@ -46,18 +47,14 @@ WorkLayout work_layout(const ccut_plan* P) {
   return w;
 }
 
-// W_b for a boundary with c cuts: 2^c x 2^c
-std::vector<cd> boundary_weights(int c) {
-  const cd s[2] = {cd(0.5, -0.5), cd(0.5, 0.5)};
-  const int64_t V = (int64_t)1 << c;
-  std::vector<cd> w((size_t)(V * V));
-  for (int64_t u = 0; u < V; ++u)
-    for (int64_t v = 0; v < V; ++v) {
-      cd a = 1.0;
-      for (int j = 0; j < c; ++j) a *= std::conj(s[(u >> j) & 1]) * s[(v >> j) & 1];
-      w[(size_t)(u * V + v)] = a;
-    }
-  return w;
+// W_b[u][u'] = conj(w_b(u)) w_b(u'), w_b = the weights of boundary b's term combinations
+std::vector<cd> boundary_weights(const ccut_plan* P, int b) {
+  const auto& w = P->bw[b];
+  const size_t V = w.size();
+  std::vector<cd> out(V * V);
+  for (size_t u = 0; u < V; ++u)
+    for (size_t v = 0; v < V; ++v) out[u * V + v] = std::conj(w[u]) * w[v];
+  return out;
 }
 
 }  // namespace
@@ -134,12 +131,12 @@ extern "C" int ccut_expectation_pauli(ccut_plan_t* plan, const void* d_arena, ui
   } else {
     int cprev = plan->c_b[0];
     int64_t U = (int64_t)1 << cprev;
-    std::vector<cd> E = boundary_weights(cprev);
+    std::vector<cd> E = boundary_weights(plan, 0);
     for (int64_t e = 0; e < U * U; ++e) E[(size_t)e] *= G[0][(size_t)e];
     for (int i = 1; i + 1 < n; ++i) {
       const int cnext = plan->c_b[i];
       const int64_t Vn = (int64_t)1 << cnext, Vi = U * Vn;
-      std::vector<cd> W = boundary_weights(cnext), En((size_t)(Vn * Vn), cd(0));
+      std::vector<cd> W = boundary_weights(plan, i), En((size_t)(Vn * Vn), cd(0));
       for (int64_t v = 0; v < Vn; ++v)
         for (int64_t vp = 0; vp < Vn; ++vp) {
           cd acc = 0.0;

@@ -248,14 +248,55 @@ namespace {
 // Per-cut weight of Eq. (CZ): s_0 = 1/(1+i), s_1 = i/(1+i).
 cd cut_weight(int bit) { return bit ? cd(0.5, 0.5) : cd(0.5, -0.5); }
 
-int validate_gate(const ccut_gate_t& g, int q, int64_t k) {
-  const bool two = g.kind == CCUT_GATE_CZ || g.kind == CCUT_GATE_CX;
-  const bool one = g.kind >= CCUT_GATE_H && g.kind <= CCUT_GATE_RYRZ;
-  if (!one && !two) return fail(CCUT_EINVAL, "gate %lld: unknown kind %d", (long long)k, g.kind);
-  if (g.q0 < 0 || g.q0 >= q) return fail(CCUT_EINVAL, "gate %lld: qubit %d out of range", (long long)k, g.q0);
-  if (two && (g.q1 < 0 || g.q1 >= q || g.q1 == g.q0))
-    return fail(CCUT_EINVAL, "gate %lld: bad second qubit %d", (long long)k, g.q1);
-  return 0;
+void pauli_matrix(int p, cd m[4]) {
+  static const cd I(0, 1);
+  const cd tab[4][4] = {{1, 0, 0, 1}, {0, 1, 1, 0}, {0, -I, I, 0}, {1, 0, 0, -1}};
+  for (int z = 0; z < 4; ++z) m[z] = tab[p][z];
+}
+
+// A run of boundary gates cut as one: a CZ / CX, or consecutive Pauli-rotation
+// gates on the same pair (they commute, so their product is one Pauli rotation).
+struct Run {
+  int64_t first;
+  int boundary;
+  bool rotation;
+  double t[3];
+  cd phase;
+  int n_gates;
+};
+
+// Decomposition and term weights of a cut (Eq. CZ; Eq. schmidt in the Pauli form).
+ccut_plan::CutTerms cut_terms_of(const Run& r, int* n_bits) {
+  ccut_plan::CutTerms ct;
+  if (!r.rotation) {
+    ct.form = 0;
+    ct.w[0] = cut_weight(0);
+    ct.w[1] = cut_weight(1);
+    *n_bits = 1;
+    return ct;
+  }
+  cd c[4];
+  pauli_rotation_coeffs(r.t, c);
+  for (auto& x : c) x *= r.phase;
+  int nz[4], n = 0;
+  for (int p = 0; p < 4; ++p)
+    if (std::abs(c[p]) > 1e-12) nz[n++] = p;
+  if (n <= 2) {  // Schmidt rank 2 (or 1): one bit between two Paulis
+    ct.form = 1;
+    ct.pa = nz[0];
+    ct.pb = n == 2 ? nz[1] : (nz[0] + 1) % 4;
+    ct.w[0] = c[ct.pa];
+    ct.w[1] = c[ct.pb];
+    *n_bits = 1;
+  } else {  // rank 4: X^{b0} Z^{b1}, and Y (x) Y = -(X Z) (x) (X Z)
+    ct.form = 2;
+    ct.w[0] = c[0];
+    ct.w[1] = c[1];
+    ct.w[2] = c[3];
+    ct.w[3] = -c[2];
+    *n_bits = 2;
+  }
+  return ct;
 }
 
 }  // namespace
@@ -292,37 +333,76 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
   for (int i = 0; i < n_seg; ++i)
     for (int t = 0; t < P->segs[i].q; ++t) seg_of[P->segs[i].off + t] = i;
 
-  // Algorithm 1: scan for boundary gates.
-  std::vector<std::vector<int64_t>> on_boundary(std::max(0, n_seg - 1));
+  // Algorithm 1: scan for boundary gates.  Pauli-rotation gates that follow each
+  // other on the same cross-boundary pair, with no gate on either qubit in
+  // between, join one run (one cut).
+  std::vector<Run> runs;
+  std::vector<int> run_of_gate(n_gates, -1);
+  std::vector<uint8_t> absorbed(n_gates, 0);
+  std::vector<int64_t> last_gate(q, -1);
   for (int64_t k = 0; k < n_gates; ++k) {
     const ccut_gate_t& g = gates[k];
-    if (int rc = validate_gate(g, q, k)) return rc;
-    if (g.kind != CCUT_GATE_CZ && g.kind != CCUT_GATE_CX) continue;
-    int sa = seg_of[g.q0], sb = seg_of[g.q1];
-    if (sa == sb) continue;
-    if (std::abs(sa - sb) != 1)
-      return fail(CCUT_EUNCUTTABLE, "gate %lld joins non-adjacent segments %d and %d", (long long)k, sa, sb);
-    on_boundary[std::min(sa, sb)].push_back(k);
+    if (int rc = check_gate(g, q, k)) return rc;
+    const bool two = is_two_qubit_kind(g.kind);
+    if (two && seg_of[g.q0] != seg_of[g.q1]) {
+      const int sa = seg_of[g.q0], sb = seg_of[g.q1];
+      if (std::abs(sa - sb) != 1)
+        return fail(CCUT_EUNCUTTABLE, "gate %lld joins non-adjacent segments %d and %d", (long long)k, sa, sb);
+      const bool rot = is_pauli_rotation_kind(g.kind);
+      double t[3];
+      cd ph;
+      if (rot) pauli_rotation_form(g, t, &ph);
+      const int64_t pa = last_gate[g.q0], pb = last_gate[g.q1];
+      if (rot && pa >= 0 && pa == pb && run_of_gate[pa] >= 0 && runs[run_of_gate[pa]].rotation) {
+        Run& R = runs[run_of_gate[pa]];
+        for (int z = 0; z < 3; ++z) R.t[z] += t[z];
+        R.phase *= ph;
+        R.n_gates++;
+        run_of_gate[k] = run_of_gate[pa];
+        absorbed[k] = 1;
+      } else {
+        Run R{k, std::min(sa, sb), rot, {0, 0, 0}, cd(1.0), 1};
+        if (rot) {
+          for (int z = 0; z < 3; ++z) R.t[z] = t[z];
+          R.phase = ph;
+        }
+        run_of_gate[k] = (int)runs.size();
+        runs.push_back(R);
+      }
+    }
+    last_gate[g.q0] = k;
+    if (two) last_gate[g.q1] = k;
+  }
+  std::vector<std::vector<int>> on_boundary(std::max(0, n_seg - 1));
+  std::vector<ccut_plan::CutTerms> run_terms(runs.size());
+  std::vector<int> run_bits(runs.size());
+  for (size_t r = 0; r < runs.size(); ++r) {
+    on_boundary[runs[r].boundary].push_back((int)r);
+    run_terms[r] = cut_terms_of(runs[r], &run_bits[r]);
   }
   P->c_b.assign(std::max(0, n_seg - 1), 0);
-  for (int b = 0; b + 1 < n_seg; ++b) P->c_b[b] = (int32_t)on_boundary[b].size();
+  for (int b = 0; b + 1 < n_seg; ++b)
+    for (int r : on_boundary[b]) P->c_b[b] += run_bits[r];
   for (int i = 0; i < n_seg; ++i) {
     auto& S = P->segs[i];
     S.c_lo = i > 0 ? P->c_b[i - 1] : 0;
     S.c_hi = i + 1 < n_seg ? P->c_b[i] : 0;
     S.c = S.c_lo + S.c_hi;
     if (S.c > CCUT_MAX_CUTS_PER_SEG)
-      return fail(CCUT_EUNSUPPORTED, "segment %d has %d adjacent cuts (max %d)", i, S.c, CCUT_MAX_CUTS_PER_SEG);
+      return fail(CCUT_EUNSUPPORTED, "segment %d has %d adjacent cut bits (max %d)", i, S.c, CCUT_MAX_CUTS_PER_SEG);
   }
-  // Cut numbering: boundary-major, gate order within a boundary.
-  std::vector<int> cut_of_gate(n_gates, -1);
+  // Cut numbering: boundary-major, gate order within a boundary; each cut takes
+  // n_bits consecutive variant bits.
+  std::vector<int> cut_of_run(runs.size(), -1);
+  P->bw.assign(std::max(0, n_seg - 1), {});
   for (int b = 0; b + 1 < n_seg; ++b) {
-    for (size_t j = 0; j < on_boundary[b].size(); ++j) {
-      int64_t k = on_boundary[b][j];
-      const ccut_gate_t& g = gates[k];
+    int pos = 0;
+    std::vector<int> cut_pos;
+    for (int r : on_boundary[b]) {
+      const ccut_gate_t& g = gates[runs[r].first];
       ccut_cut_info_t c;
       std::memset(&c, 0, sizeof(c));
-      c.gate_index = (int32_t)k;
+      c.gate_index = (int32_t)runs[r].first;
       c.kind = g.kind;
       c.boundary = b;
       bool q0_low = seg_of[g.q0] == b;
@@ -330,28 +410,62 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
       c.q_high = q0_low ? g.q1 : g.q0;
       c.target_high = (g.kind == CCUT_GATE_CX && q0_low) ? 1 : 0;
       // segment b sees this boundary as its upper one; segment b+1 as its lower one
-      c.bit_low = P->segs[b].c_lo + (int32_t)j;
-      c.bit_high = (int32_t)j;
-      cut_of_gate[k] = (int)P->cuts.size();
+      c.bit_low = P->segs[b].c_lo + pos;
+      c.bit_high = pos;
+      c.n_bits = run_bits[r];
+      c.n_gates = runs[r].n_gates;
+      cut_pos.push_back(pos);
+      pos += run_bits[r];
+      cut_of_run[r] = (int)P->cuts.size();
       P->cuts.push_back(c);
+      P->cut_terms.push_back(run_terms[r]);
+    }
+    // weights of the boundary's term combinations: product over its cuts
+    const int64_t K = (int64_t)1 << P->c_b[b];
+    P->bw[b].resize((size_t)K);
+    for (int64_t m = 0; m < K; ++m) {
+      cd w = 1.0;
+      for (size_t j = 0; j < on_boundary[b].size(); ++j) {
+        const int r = on_boundary[b][j];
+        w *= run_terms[r].w[(m >> cut_pos[j]) & ((1 << run_bits[r]) - 1)];
+      }
+      P->bw[b][(size_t)m] = w;
     }
   }
 
-  // Per-segment programs: the segment's own gates, plus a slot per adjacent cut.
+  // Per-segment programs: the segment's own gates, plus the slot ops of each adjacent cut.
   for (int i = 0; i < n_seg; ++i) {
     auto& S = P->segs[i];
     ProgramBuilder pb(S.q);
     for (int64_t k = 0; k < n_gates; ++k) {
       const ccut_gate_t& g = gates[k];
-      int cj = cut_of_gate[k];
-      if (cj >= 0) {
+      if (run_of_gate[k] >= 0) {
+        if (absorbed[k]) continue;  // applied with the first gate of its run
+        const int cj = cut_of_run[run_of_gate[k]];
         const ccut_cut_info_t& c = P->cuts[cj];
+        const ccut_plan::CutTerms& ct = P->cut_terms[cj];
         int side;  // 0: this segment holds q_low, 1: q_high
         if (c.boundary == i) side = 0;
         else if (c.boundary + 1 == i) side = 1;
         else continue;
-        int local = (side == 0 ? c.q_low : c.q_high) - S.off;
-        int slot = side == 0 ? c.bit_low : c.bit_high;
+        const int local = (side == 0 ? c.q_low : c.q_high) - S.off;
+        const int slot = side == 0 ? c.bit_low : c.bit_high;
+        if (ct.form == 1) {
+          cd m0[4], m1[4];
+          pauli_matrix(ct.pa, m0);
+          pauli_matrix(ct.pb, m1);
+          pb.one_qubit(local, m0, m1, slot);
+          continue;
+        }
+        if (ct.form == 2) {  // Z^{b1}, then X^{b0}
+          cd id[4], x[4], z[4];
+          pauli_matrix(0, id);
+          pauli_matrix(1, x);
+          pauli_matrix(3, z);
+          pb.one_qubit(local, id, z, slot + 1);
+          pb.one_qubit(local, id, x, slot);
+          continue;
+        }
         cd s0[4] = {1, 0, 0, cd(0, 1)}, s1[4] = {1, 0, 0, cd(0, -1)};
         bool is_target = c.kind == CCUT_GATE_CX && ((side == 1) == (c.target_high == 1));
         if (is_target) {  // H S H and H S^dag H
@@ -369,13 +483,7 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
         continue;
       }
       if (seg_of[g.q0] != i) continue;
-      if (g.kind == CCUT_GATE_CZ) pb.cz(g.q0 - S.off, g.q1 - S.off);
-      else if (g.kind == CCUT_GATE_CX) pb.cx(g.q0 - S.off, g.q1 - S.off);
-      else {
-        cd m[4];
-        gate_matrix(g, m);
-        pb.one_qubit(g.q0 - S.off, m, m, -1);
-      }
+      pb.gate(g, S.off);
     }
     S.prog = std::move(pb.prog);
   }
@@ -421,8 +529,7 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
     st.out_bstride = (uint64_t)1 << (qacc + Sn.q);
     st.weight_off = (int32_t)(P->weights.size() / 2);
     for (int m = 0; m < st.K; ++m) {
-      cd w = 1.0;
-      for (int j = 0; j < P->c_b[k]; ++j) w *= cut_weight((m >> j) & 1);
+      const cd w = P->bw[k][(size_t)m];
       P->weights.push_back((float)w.real());
       P->weights.push_back((float)w.imag());
     }
@@ -483,7 +590,9 @@ extern "C" int ccut_plan_info(const ccut_plan_t* plan, ccut_plan_info_t* info) {
     info->n_sub += (int64_t)1 << S.c;
   }
   for (size_t b = 0; b < plan->c_b.size(); ++b) info->c_boundary[b] = plan->c_b[b];
-  info->n_terms = (int64_t)1 << info->c_total;
+  int bits = 0;
+  for (int c : plan->c_b) bits += c;
+  info->n_terms = (int64_t)1 << bits;
   info->state_bytes = plan->state_bytes;
   info->arena_bytes = plan->total_arena;
   info->sim_arena_bytes = plan->sim_bytes;
@@ -505,6 +614,19 @@ extern "C" int ccut_cut_weight(int32_t bit, double out[2]) {
   cd w = cut_weight(bit);
   out[0] = w.real();
   out[1] = w.imag();
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_cut_terms(const ccut_plan_t* plan, int32_t j, double w[8]) {
+  clear_error();
+  if (!plan || !w) return fail(CCUT_EINVAL, "NULL argument");
+  if (j < 0 || j >= (int32_t)plan->cuts.size()) return fail(CCUT_EINVAL, "cut %d out of range", j);
+  const auto& ct = plan->cut_terms[j];
+  for (int t = 0; t < 4; ++t) {
+    const bool used = t < (1 << plan->cuts[j].n_bits);
+    w[2 * t] = used ? ct.w[t].real() : 0.0;
+    w[2 * t + 1] = used ? ct.w[t].imag() : 0.0;
+  }
   return CCUT_OK;
 }
 

@@ -22,6 +22,15 @@ struct ccut_plan {
   int32_t q = 0, n_seg = 0, n_gates = 0;
   std::vector<Seg> segs;
   std::vector<ccut_cut_info_t> cuts;
+  // How each cut is decomposed (Eq. CZ for CZ / CX, the Pauli form of Eq. schmidt
+  // for the Pauli-rotation kinds) and the weights of its 2^{n_bits} terms.
+  struct CutTerms {
+    int form = 0;        // 0: S / S^dag (Eq. CZ), 1: one bit choosing Pauli pa or pb, 2: X^{b0} Z^{b1}
+    int pa = 0, pb = 0;  // form 1: the two Paulis (0 I, 1 X, 2 Y, 3 Z)
+    ccut::cd w[4];       // term weights, term t = the cut's variant bits as an integer
+  };
+  std::vector<CutTerms> cut_terms;
+  std::vector<std::vector<ccut::cd>> bw;  // per boundary: weight of each of its 2^{c_b} term combinations
   std::vector<int32_t> c_b;
   uint64_t state_bytes = 0, arena_bytes = 0, psi_bytes = 0;
   uint64_t temp_off[2] = {0, 0};  // ping / pong temp regions of the chain merge (bytes)

@@ -60,6 +60,46 @@ int gate_matrix(const ccut_gate_t& g, cd m[4]) {
   }
 }
 
+bool is_two_qubit_kind(int kind) {
+  return kind == CCUT_GATE_CZ || kind == CCUT_GATE_CX || is_pauli_rotation_kind(kind);
+}
+
+bool is_pauli_rotation_kind(int kind) { return kind >= CCUT_GATE_SWAP && kind <= CCUT_GATE_RZZ; }
+
+void pauli_rotation_form(const ccut_gate_t& g, double t[3], cd* phase) {
+  t[0] = t[1] = t[2] = 0.0;
+  *phase = 1.0;
+  switch (g.kind) {
+    case CCUT_GATE_SWAP: t[0] = t[1] = t[2] = M_PI / 2; *phase = std::polar(1.0, M_PI / 4); break;
+    case CCUT_GATE_ISWAP: t[0] = t[1] = -M_PI / 2; break;
+    case CCUT_GATE_RXX: t[0] = g.p0; break;
+    case CCUT_GATE_RYY: t[1] = g.p0; break;
+    case CCUT_GATE_RZZ: t[2] = g.p0; break;
+    default: break;
+  }
+}
+
+void pauli_rotation_coeffs(const double t[3], cd c[4]) {
+  const double cx = std::cos(t[0] / 2), sx = std::sin(t[0] / 2);
+  const double cy = std::cos(t[1] / 2), sy = std::sin(t[1] / 2);
+  const double cz = std::cos(t[2] / 2), sz = std::sin(t[2] / 2);
+  const cd I(0, 1);
+  c[0] = cx * cy * cz - I * (sx * sy * sz);
+  c[1] = -I * (sx * cy * cz) + cx * sy * sz;
+  c[2] = -I * (cx * sy * cz) + sx * cy * sz;
+  c[3] = -I * (cx * cy * sz) + sx * sy * cz;
+}
+
+int check_gate(const ccut_gate_t& g, int q, int64_t k) {
+  const bool two = is_two_qubit_kind(g.kind);
+  const bool one = g.kind >= CCUT_GATE_H && g.kind <= CCUT_GATE_RYRZ;
+  if (!one && !two) return fail(CCUT_EINVAL, "gate %lld: unknown kind %d", (long long)k, g.kind);
+  if (g.q0 < 0 || g.q0 >= q) return fail(CCUT_EINVAL, "gate %lld: qubit %d out of range", (long long)k, g.q0);
+  if (two && (g.q1 < 0 || g.q1 >= q || g.q1 == g.q0))
+    return fail(CCUT_EINVAL, "gate %lld: bad second qubit %d", (long long)k, g.q1);
+  return 0;
+}
+
 ProgramBuilder::ProgramBuilder(int nq)
     : last1q(nq, -1), any_since(nq, 0), nondiag_since(nq, 0) {
   prog.nq = nq;
@@ -117,6 +157,54 @@ void ProgramBuilder::cx(int c, int t) {
   any_since[c] = 1;
   any_since[t] = nondiag_since[t] = 1;
   last1q[t] = -1;  // nothing may fuse backwards past a CX target
+}
+
+void ProgramBuilder::gate(const ccut_gate_t& g, int off) {
+  const int a = g.q0 - off, b = g.q1 - off;
+  auto one = [&](int t, int kind, double p0) {
+    ccut_gate_t h{};
+    h.kind = kind;
+    h.p0 = p0;
+    cd m[4];
+    gate_matrix(h, m);
+    one_qubit(t, m, m, -1);
+  };
+  // exp(-i t ZZ / 2) = CX(a, b) . Rz(t) on b . CX(a, b)
+  auto rzz = [&](double t) {
+    cx(a, b);
+    one(b, CCUT_GATE_RZ, t);
+    cx(a, b);
+  };
+  switch (g.kind) {
+    case CCUT_GATE_CZ: cz(a, b); return;
+    case CCUT_GATE_CX: cx(a, b); return;
+    case CCUT_GATE_SWAP: cx(a, b); cx(b, a); cx(a, b); return;
+    case CCUT_GATE_RZZ: rzz(g.p0); return;
+    case CCUT_GATE_RXX:  // H Z H = X
+      one(a, CCUT_GATE_H, 0); one(b, CCUT_GATE_H, 0);
+      rzz(g.p0);
+      one(a, CCUT_GATE_H, 0); one(b, CCUT_GATE_H, 0);
+      return;
+    case CCUT_GATE_RYY:  // Rx(-pi/2) Z Rx(pi/2) = Y
+      one(a, CCUT_GATE_RX, M_PI / 2); one(b, CCUT_GATE_RX, M_PI / 2);
+      rzz(g.p0);
+      one(a, CCUT_GATE_RX, -M_PI / 2); one(b, CCUT_GATE_RX, -M_PI / 2);
+      return;
+    case CCUT_GATE_ISWAP: {  // exp(+i pi/4 (XX + YY)) = RXX(-pi/2) RYY(-pi/2)
+      ccut_gate_t h = g;
+      h.kind = CCUT_GATE_RXX;
+      h.p0 = -M_PI / 2;
+      gate(h, off);
+      h.kind = CCUT_GATE_RYY;
+      gate(h, off);
+      return;
+    }
+    default: {
+      cd m[4];
+      gate_matrix(g, m);
+      one_qubit(a, m, m, -1);
+    }
+  }
 }
 
 // ----------------------------------------------------------------- passes

@@ -7,6 +7,7 @@
     python -m paper_2603_01443_amd.experiments gemm       --out results/merge_gemm_variants.json
     python -m paper_2603_01443_amd.experiments paper      --out results/paper_family.json
     python -m paper_2603_01443_amd.experiments expectation --out results/expectation.json
+    python -m paper_2603_01443_amd.experiments rank4      --out results/rank4_cuts.json
 
 sweep      Random brickwork, q = 24 in two blocks of 12, d in {10, 20, 40},
            c_total in {0, 1, 2, 3, 4, 6} (extended by 2 up to --cmax while cutting
@@ -40,6 +41,10 @@ expectation Pauli-string expectation values from the subcircuit states (the
            c_total = 6) beside the merge and the uncut simulation, with the value
            from the uncut full state as the check; then q = 36 ... 60, past the
            2^35 amplitudes one GPU can hold as a full state.
+rank4      Schmidt-rank-4 cuts (Eq. schmidt): random brickwork, two segments,
+           d = 20, q = 24 and 28, with SWAP or a fused RXX RYY RZZ run on the
+           boundary (1..6 cuts, K = 4^c) beside CZ (2..12 cuts, K = 2^c): the
+           stage times, Delta against the uncut run and 1 - F.
 
 Timings: host wall clock for T_pre (cut_plan); HIP events on the stream for the
 device stages; warm-up runs first, then the mean of the timed repeats.
@@ -539,6 +544,34 @@ def run_paper(args):
     return out
 
 
+# ------------------------------------------------------------------ rank-4 cuts
+def run_rank4(args):
+    """Schmidt-rank-4 cuts (Eq. schmidt): SWAP and fused general interactions (an
+    RXX RYY RZZ run) on the boundary, against CZ (rank 2) at the same term counts."""
+    out = {"experiment": "rank-4 cuts", "d": 20, "rows": []}
+    bufs = Buffers()
+    s = torch.cuda.current_stream()
+    d = 20
+    for q in (24, 28):
+        for kind, cs in (("CZ", (2, 4, 6, 8, 10, 12)), ("SWAP", (1, 2, 3, 4, 5, 6)), ("CAN", (1, 2, 3, 4, 5, 6))):
+            for c in cs:
+                if q == 28 and c > (6 if kind == "CZ" else 3):
+                    continue
+                g = brickwork(q, d, 2, c, seed=q + c, boundary_gate=kind)
+                t_orig = time_uncut(q, g, bufs, reps=args.reps)
+                pre, sub, mer, plan = time_cut(q, g, 2, None, bufs, precision="auto", reps=args.reps)
+                info = plan.info()
+                st = ccut.norm_fidelity(c64(bufs.psi, q), c64(bufs.ref, q), q, stream=s)
+                t_cut = pre + sub + mer
+                row = {"q": q, "kind": kind, "cuts": c, "K": info["n_terms"], "n_sub": info["n_sub"],
+                       "T_pre": pre, "T_sub": sub, "T_merge": mer, "T_cut": t_cut, "T_orig": t_orig,
+                       "delta": (t_cut - t_orig) / t_orig, "one_minus_F_vs_uncut": 1.0 - st["fidelity"]}
+                out["rows"].append(row)
+                log(f"rank4 q{q} {kind} cuts={c} K={info['n_terms']}: sub {sub*1e3:.3f} merge {mer*1e3:.3f} "
+                    f"uncut {t_orig*1e3:.3f} ms delta {row['delta']:+.2f} 1-F {row['one_minus_F_vs_uncut']:.1e}")
+    return out
+
+
 # ------------------------------------------------------------------ expectation
 def pauli_expval_torch(psi, q, label):
     """<psi|P|psi> of a complex64 GPU state with plain torch ops (qubit by qubit on
@@ -659,7 +692,7 @@ def run_expectation(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["sweep", "precision", "batching", "costmodel", "gemm", "paper", "expectation"])
+    ap.add_argument("which", choices=["sweep", "precision", "batching", "costmodel", "gemm", "paper", "expectation", "rank4"])
     ap.add_argument("--out", required=True)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--epochs", type=int, default=3000)
@@ -672,7 +705,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("experiments need a GPU")
     fn = {"sweep": run_sweep, "precision": run_precision, "batching": run_batching, "costmodel": run_costmodel,
-          "gemm": run_gemm, "paper": run_paper, "expectation": run_expectation}
+          "gemm": run_gemm, "paper": run_paper, "expectation": run_expectation,
+          "rank4": run_rank4}
     res = fn[args.which](args)
     res["device"] = torch.cuda.get_device_name(0)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)

@@ -5,6 +5,8 @@ oracle's independent plan.  No GPU call is made here."""
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from inputs import Gate, brickwork, equal_blocks, staircase
@@ -186,3 +188,50 @@ def test_expectation_argument_checks():
     assert big.info()["c_total"] == 13
     with pytest.raises(ccut.CcutError, match="at most 12 cuts"):
         ccut.expectation_pauli(big, fake, "Z" * 16, fake, arena_bytes=1 << 40, work_bytes=1 << 40)
+
+
+@pytest.mark.parametrize("kind", ["SWAP", "ISWAP", "RXX", "RYY", "RZZ", "CZ", "CX"])
+def test_schmidt_cuts_match_oracle_ranks(kind):
+    """Each cut takes log2(k) variant bits, k its Schmidt rank from the oracle's SVD
+    (Eq. schmidt); N_sub = sum_i prod_j k_j and the term count follow; the term
+    weights carry the norm of the decomposition: with Pauli or S factors (Frobenius
+    norm sqrt 2) sum 4 |w|^2 equals sum |s|^2 |A|^2 |B|^2 of the oracle's terms
+    (4 = |U|_F^2 for the SVD's unit factors)."""
+    q, n = 12, 3
+    g = brickwork(q, 6, n, 4, seed=2, boundary_gate=kind) if kind != "CX" else staircase(q, 2)
+    sizes = equal_blocks(q, n)
+    plan = ccut.cut_plan(q, g, n)
+    info = plan.info()
+    cuts = plan.cuts()
+    ocuts = cutting.find_cuts(q, g, sizes)
+    by_gate = {oc.gate_index: oc for oc in ocuts}         # plan cuts are boundary-major
+    assert sorted(cu["gate_index"] for cu in cuts) == sorted(by_gate)
+    ranks = []
+    for j, cu in enumerate(cuts):
+        terms = cutting.cut_terms(by_gate[cu["gate_index"]])
+        ranks.append(len(terms))
+        assert 2 ** cu["n_bits"] == len(terms) and cu["n_gates"] == 1
+        w = plan.cut_terms(j)
+        onorm = sum(abs(s) ** 2 * np.linalg.norm(a) ** 2 * np.linalg.norm(b) ** 2 for s, a, b in terms)
+        assert abs(sum(abs(x) ** 2 for x in w) * 4 - onorm) < 1e-12
+    assert info["n_sub"] == cutting.n_subcircuits(ocuts, n)
+    assert info["n_terms"] == int(np.prod(ranks))
+    assert sum(info["c_boundary"][: n - 1]) == sum(cu["n_bits"] for cu in cuts)
+
+
+def test_pauli_rotation_runs_fuse_into_one_cut():
+    """RXX, RYY, RZZ on the same cross-boundary pair with nothing in between on
+    either qubit commute: one rank-4 cut (two bits), not three rank-2 cuts; a gate
+    on one of the qubits between them keeps the runs apart."""
+    q = 8
+    run = [Gate("RXX", 3, 4, 0.3), Gate("RYY", 4, 3, 1.2), Gate("RZZ", 3, 4, 2.1)]
+    plan = ccut.cut_plan(q, run, 2)
+    cuts = plan.cuts()
+    assert len(cuts) == 1 and cuts[0]["n_bits"] == 2 and cuts[0]["n_gates"] == 3
+    assert plan.info()["n_terms"] == 4
+    split = run[:1] + [Gate("H", 3)] + run[1:]
+    cuts = ccut.cut_plan(q, split, 2).cuts()
+    assert [cu["n_gates"] for cu in cuts] == [1, 2] and [cu["n_bits"] for cu in cuts] == [1, 2]
+    # a single rotation alone is rank 2 (one bit), SWAP rank 4 (two bits)
+    assert ccut.cut_plan(q, [Gate("RZZ", 3, 4, 0.5)], 2).cuts()[0]["n_bits"] == 1
+    assert ccut.cut_plan(q, [Gate("SWAP", 3, 4)], 2).cuts()[0]["n_bits"] == 2

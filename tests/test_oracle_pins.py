@@ -237,9 +237,10 @@ def test_sampled_amplitudes_match_full_merge():
 def test_uncuttable_gate_rejected():
     g = [Gate("H", 0), Gate("CZ", 1, 2)]
     with pytest.raises(ValueError):
-        # a gate the library has no rank-2 decomposition for, crossing the boundary
-        cutting.find_cuts(4, [Gate("SWAP", 1, 2)], [2, 2])
+        # a two-qubit gate joining segments 0 and 2 has no boundary to be cut at
+        cutting.find_cuts(6, [Gate("SWAP", 1, 4)], [2, 2, 2])
     assert len(cutting.find_cuts(4, g, [2, 2])) == 1
+    assert len(cutting.find_cuts(4, [Gate("SWAP", 1, 2)], [2, 2])) == 1
 
 
 def test_fidelity_metrics():
