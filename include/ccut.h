@@ -227,13 +227,17 @@ enum {
 
 /*
  * Merging, Algorithm 3 (Appendix B):
- *   Psi = sum over all 2^{c_total} cut-term combinations m of
+ *   Psi = sum over all info.n_terms cut-term combinations m of
  *         alpha_m  psi_{n-1}^{(r_{n-1}(m))} (x) ... (x) psi_0^{(r_0(m))},
- * alpha_m being the product of the per-cut weights of Eq. (CZ).  For n >= 3 the
- * sum is contracted boundary by boundary (same result up to rounding).
+ * alpha_m being the product of the per-cut term weights (Eq. CZ, or the
+ * Schmidt coefficients).  For n >= 3 the sum is contracted boundary by
+ * boundary (same result up to rounding).
  *
- *   d_arena    the arena filled by ccut_simulate_subcircuits; its workspace
- *              part (past info.state_bytes) is overwritten
+ *   d_arena    the arena filled by ccut_simulate_subcircuits for this plan; its
+ *              workspace part (past info.sim_arena_bytes) is overwritten.  The
+ *              merge weights are read from the table copy that call left in the
+ *              arena (they are copied again if this plan's last simulation used
+ *              another arena), so no other plan may use the arena in between
  *   d_psi      output, 2^q complex64 (psi_bytes >= info.psi_bytes); written once
  *   precision  one of CCUT_PREC_*
  * Errors: CCUT_ENOSPC, CCUT_EINVAL (unknown precision), CCUT_EHIP.

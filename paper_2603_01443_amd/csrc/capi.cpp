@@ -76,6 +76,7 @@ void pack_image(ccut_plan* P) {
   pack(P->image, P->weights, P->img_weights);
   pack(P->image, P->grefs, P->img_grefs);
   if (P->image.empty()) P->image.resize(256);
+  P->image_gen++;
 }
 
 int staged_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s) {
@@ -131,7 +132,12 @@ int upload_tables(DeviceTables& t, const std::vector<unsigned char>& img, uint64
 
 // Device addresses of a plan's tables for a call on `arena`: the plan-owned
 // copy when prepared on this device, otherwise a fresh copy into the arena.
-int plan_tables(ccut_plan* P, char* arena, hipStream_t s, DeviceTables& out) {
+// Device addresses of the plan's tables: its own copy after ccut_plan_prepare, else
+// the arena's table region, which receives the image (through the staging ring)
+// unless `reuse` is set and the last copy went to this arena from the current
+// image build.  The merge reuses: the arena it reads holds this plan's states,
+// so the simulation call that wrote them also left the tables there.
+int plan_tables(ccut_plan* P, char* arena, hipStream_t s, DeviceTables& out, bool reuse) {
   int dev = 0;
   CCUT_HIP(hipGetDevice(&dev));
   if (P->dev.device == dev) {
@@ -145,7 +151,11 @@ int plan_tables(ccut_plan* P, char* arena, hipStream_t s, DeviceTables& out) {
     return 0;
   }
   unsigned char* b = reinterpret_cast<unsigned char*>(arena + P->tables_off);
-  if (int rc = staged_copy(b, P->image.data(), P->image.size(), s)) return rc;
+  if (!(reuse && P->staged_arena == arena && P->staged_gen == P->image_gen)) {
+    if (int rc = staged_copy(b, P->image.data(), P->image.size(), s)) return rc;
+    P->staged_arena = arena;
+    P->staged_gen = P->image_gen;
+  }
   out = DeviceTables();
   out.ops = reinterpret_cast<KOp*>(b + P->img_ops);
   out.passes = reinterpret_cast<PassDesc*>(b + P->img_passes);
@@ -251,7 +261,7 @@ extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint6
                 (unsigned long long)plan->sim_bytes);
   hipStream_t s = static_cast<hipStream_t>(stream);
   DeviceTables T;
-  if (int rc = plan_tables(plan, static_cast<char*>(d_arena), s, T)) return rc;
+  if (int rc = plan_tables(plan, static_cast<char*>(d_arena), s, T, false)) return rc;
   const uint4* gtab = nullptr;
   if (plan->sim_precision == CCUT_SIM_FP16X3 && !plan->grefs.empty()) {
     uint4* g = reinterpret_cast<uint4*>(static_cast<char*>(d_arena) + plan->gtab_off);
@@ -292,7 +302,7 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* arena = static_cast<char*>(d_arena);
   DeviceTables T;
-  if (int rc = plan_tables(plan, arena, s, T)) return rc;
+  if (int rc = plan_tables(plan, arena, s, T, true)) return rc;
   if (plan->n_seg == 1) {
     CCUT_HIP(hipMemcpyAsync(d_psi, arena + plan->segs[0].arena_off, plan->psi_bytes, hipMemcpyDeviceToDevice, s));
     return CCUT_OK;

@@ -62,6 +62,10 @@ struct ccut_plan {
   uint64_t tables_off = 0;  // arena byte offset of the table region
   uint64_t tables_reserve = 0;  // bytes reserved for it
   uint64_t total_arena = 0; // bytes the caller's arena must hold
+  uint64_t image_gen = 0;   // bumped whenever the table image is rebuilt
+  // arena (and image build) whose table region last received this plan's image
+  const void* staged_arena = nullptr;
+  uint64_t staged_gen = 0;
 
   // expectation values: pinned host copy of the per-segment matrices (grow-only,
   // freed with the plan); the mutex serialises calls that share it
