@@ -376,9 +376,21 @@ int ccut_plan_get_block_bits(const ccut_plan_t* plan, int32_t* out);
 int ccut_plan_set_prefix_sharing(ccut_plan_t* plan, int32_t mode);
 /* 1 if the plan's tables use prefix sharing, else 0 (host-only). */
 int ccut_plan_get_prefix_sharing(const ccut_plan_t* plan, int32_t* out);
+/*
+ * First level of the prefix-sharing tree (default 0).  With level L, segment i's
+ * first min(L, c_i) slots are not shared: its 2^min(L, c_i) level-L states run
+ * the program up to slot L from |0...0> in one launch, and the tree branches
+ * from there.  The early levels hold few states and leave most of the device
+ * idle; starting later trades them for some repeated gates.  L >= c_i is the
+ * flat simulation.  Host-only; reschedules the plan.  Errors: CCUT_EINVAL
+ * (L outside [0, CCUT_MAX_CUTS_PER_SEG]).
+ */
+int ccut_plan_set_prefix_start(ccut_plan_t* plan, int32_t level);
+int ccut_plan_get_prefix_start(const ccut_plan_t* plan, int32_t* out);
 
 /*
- * Autotuner: times the simulation kernel over prefix sharing off / on x LDS
+ * Autotuner: times the simulation kernel over prefix sharing off / on (tree
+ * from level 0, 2, 3, 4) x LDS
  * block sizes (whole segment, 2 and 4 blocks per state; sizes whose tables do
  * not fit arena_bytes are skipped) x workgroup sizes x persistent grid sizes,
  * and the merge with the
@@ -389,7 +401,7 @@ int ccut_plan_get_prefix_sharing(const ccut_plan_t* plan, int32_t* out);
  * arena and d_psi.  *best_ms (nullable) receives the tuned simulation + merge
  * time.  ccut_autotune_save / _load write and read the cache as text (one
  * "key threads grid_cap mfma_min_terms epilogue merge_grid block_bits prefix"
- * line per entry).
+ * line per entry; prefix 0 = off, 1 + L = on with the tree from level L).
  * Errors: CCUT_EINVAL, CCUT_ENOSPC, CCUT_EHIP.
  */
 int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* d_psi, uint64_t psi_bytes,

@@ -118,6 +118,8 @@ def _load():
         "ccut_plan_set_block_bits": [vp, i32],
         "ccut_plan_set_sim_precision": [vp, i32],
         "ccut_plan_set_prefix_sharing": [vp, i32],
+        "ccut_plan_set_prefix_start": [vp, i32],
+        "ccut_plan_get_prefix_start": [vp, ctypes.POINTER(i32)],
         "ccut_plan_get_prefix_sharing": [vp, ctypes.POINTER(i32)],
         "ccut_plan_get_sim_precision": [vp, ctypes.POINTER(i32)],
         "ccut_plan_get_block_bits": [vp, ctypes.POINTER(i32)],
@@ -446,6 +448,17 @@ def plan_get_prefix_sharing(plan: Plan) -> bool:
     out = ctypes.c_int32(0)
     _check(_lib.ccut_plan_get_prefix_sharing(plan.handle, ctypes.byref(out)))
     return bool(out.value)
+
+
+def plan_set_prefix_start(plan: Plan, level: int) -> None:
+    """First level of the prefix-sharing tree (the slots below it run flat)."""
+    _check(_lib.ccut_plan_set_prefix_start(plan.handle, int(level)))
+
+
+def plan_get_prefix_start(plan: Plan) -> int:
+    out = ctypes.c_int32(0)
+    _check(_lib.ccut_plan_get_prefix_start(plan.handle, ctypes.byref(out)))
+    return int(out.value)
 
 
 def plan_get_block_bits(plan: Plan) -> int:

@@ -93,7 +93,10 @@ bool auto_prefix(const ccut_plan* P) {
 // Prefix sharing (a tree over the slots in program order): level l holds the 2^l
 // states of the first l slot choices; level l + 1 applies chunk l + 1 (which
 // starts at slot l + 1's op) to each of them, once per choice of that slot.
-// Levels below c live in a ping-pong scratch, level c is the arena layout.
+// The tree starts at level L = min(prefix_start, c): its 2^L states run the
+// program up to slot L from |0...0> (the early levels hold too few states to
+// fill the device, so they are traded for some repeated work).  Levels below c
+// live in a ping-pong scratch, level c is the arena layout.
 int build_tree_launches(ccut_plan* P) {
   const int n_seg = P->n_seg;
   int max_c = 0;
@@ -108,15 +111,15 @@ int build_tree_launches(ccut_plan* P) {
       }
     if ((int)pos.size() != S.c) return fail(CCUT_EINVAL, "segment program has %zu slotted ops for %d cuts",
                                             pos.size(), S.c);
-    for (int l = 0; l <= S.c; ++l) {
+    const int L0 = std::min(P->prefix_start, S.c);
+    S.chunk_passes.resize(S.c + 1);
+    for (int l = L0; l <= S.c; ++l) {
       Program chunk;
       chunk.nq = S.prog.nq;
-      const int begin = l == 0 ? 0 : pos[l - 1];
+      const int begin = l == L0 ? 0 : pos[l - 1];
       const int end = l < S.c ? pos[l] : (int)S.prog.ops.size();
       chunk.ops.assign(S.prog.ops.begin() + begin, S.prog.ops.begin() + end);
-      std::vector<Pass> passes;
-      if (int rc = schedule_passes(chunk, P->bmax, P->low_bits, passes, l == 0)) return rc;
-      S.chunk_passes.push_back(std::move(passes));
+      if (int rc = schedule_passes(chunk, P->bmax, P->low_bits, S.chunk_passes[l], l == L0)) return rc;
     }
     max_c = std::max(max_c, S.c);
   }
@@ -128,7 +131,9 @@ int build_tree_launches(ccut_plan* P) {
       ccut_plan::Launch L{(int)P->jobs.size(), 0, 0};
       std::vector<int> order;
       for (int i = 0; i < n_seg; ++i)
-        if (l <= P->segs[i].c && P->segs[i].chunk_passes[l].size() > p) order.push_back(i);
+        if (l <= P->segs[i].c && l >= std::min(P->prefix_start, P->segs[i].c) &&
+            P->segs[i].chunk_passes[l].size() > p)
+          order.push_back(i);
       std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P->segs[a].q > P->segs[b].q; });
       for (int i : order) {
         auto& S = P->segs[i];
@@ -142,7 +147,7 @@ int build_tree_launches(ccut_plan* P) {
           std::memset(&j, 0, sizeof(j));
           j.state_off = l == S.c ? S.arena_off / 8 + ((uint64_t)variant << S.q)
                                  : S.tree_off / 8 + (uint64_t)(l % 2) * half + ((uint64_t)u << S.q);
-          if (l > 0) {
+          if (l > std::min(P->prefix_start, S.c)) {
             const int64_t parent = u & ((int64_t(1) << (l - 1)) - 1);
             j.src_off = S.tree_off / 8 + (uint64_t)((l - 1) % 2) * half + ((uint64_t)parent << S.q);
           } else {

@@ -45,6 +45,7 @@ struct ccut_plan {
   int bmax = ccut::PASS_MAX_B, low_bits = 4;  // bmax: block bits in use
   int block_bits = 0;                         // requested block bits, 0: automatic
   int prefix_mode = -1;                       // prefix sharing: 0 off, 1 on, -1 automatic
+  int prefix_start = 0;                       // first tree level (the slots below it run flat)
   bool prefix_on = false;                     // in use by the current tables
   std::vector<ccut::PassDesc> pass_descs;
   std::vector<ccut::StageDesc> stage_descs;

@@ -92,7 +92,9 @@ void apply_tuned(ccut_plan* P) {
   P->merge_epilogue = it->second.epilogue;
   P->merge_grid_cap = it->second.merge_grid;
   P->block_bits = it->second.block_bits;
-  P->prefix_mode = it->second.prefix;
+  // prefix: -1 automatic, 0 off, 1 + L on with the tree starting at level L
+  P->prefix_mode = it->second.prefix <= 0 ? it->second.prefix : 1;
+  P->prefix_start = it->second.prefix > 0 ? it->second.prefix - 1 : 0;
 }
 
 }  // namespace ccut
@@ -194,6 +196,28 @@ extern "C" int ccut_plan_set_prefix_sharing(ccut_plan_t* plan, int32_t mode) {
   return CCUT_OK;
 }
 
+extern "C" int ccut_plan_set_prefix_start(ccut_plan_t* plan, int32_t level) {
+  clear_error();
+  if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
+  if (level < 0 || level > CCUT_MAX_CUTS_PER_SEG)
+    return fail(CCUT_EINVAL, "prefix start level %d outside [0, %d]", level, CCUT_MAX_CUTS_PER_SEG);
+  const int saved = plan->prefix_start;
+  plan->prefix_start = level;
+  if (int rc = build_sim_tables(plan, false)) {
+    plan->prefix_start = saved;
+    (void)build_sim_tables(plan, false);
+    return rc;
+  }
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_get_prefix_start(const ccut_plan_t* plan, int32_t* out) {
+  clear_error();
+  if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
+  *out = plan->prefix_start;
+  return CCUT_OK;
+}
+
 extern "C" int ccut_plan_get_prefix_sharing(const ccut_plan_t* plan, int32_t* out) {
   clear_error();
   if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
@@ -235,23 +259,32 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   plan->sim_per_variant = 0;
   float best = 1e30f;
   int bt = plan->sim_threads, bg = plan->sim_grid_cap, bb = plan->bmax, bpre = plan->prefix_on ? 1 : 0;
-  const int saved_bits = plan->block_bits, saved_prefix = plan->prefix_mode;
+  int bstart = plan->prefix_start;
+  const int saved_bits = plan->block_bits, saved_prefix = plan->prefix_mode, saved_start = plan->prefix_start;
   bool any_cut = false;
   for (const auto& S : plan->segs) any_cut = any_cut || S.c > 0;
   const int threads[3] = {256, 512, 1024};
   const int caps[5] = {0, 256, 512, 1024, 2048};
   int qmax = 0;
   for (const auto& S : plan->segs) qmax = std::max(qmax, S.q);
-  // prefix sharing off / on x block sizes: whole segment states in LDS, then 2 and 4 blocks
-  for (int pre = 0; pre <= (any_cut ? 1 : 0); ++pre)
+  // prefix sharing off / on (tree from level 0, 2, 3 or 4) x block sizes: whole segment
+  // states in LDS, then 2 and 4 blocks
+  int cmax = 0;
+  for (const auto& S : plan->segs) cmax = std::max(cmax, S.c);
+  const int pre_modes[5][2] = {{0, 0}, {1, 0}, {1, 2}, {1, 3}, {1, 4}};
+  for (int pm = 0; pm < (any_cut ? 5 : 1); ++pm)
   for (int bits = std::min(qmax, PASS_MAX_B); bits >= std::max(plan->low_bits + 1, std::min(qmax, PASS_MAX_B) - 2);
        --bits) {
+    const int pre = pre_modes[pm][0], start = pre_modes[pm][1];
+    if (pre && start > 0 && start >= cmax) continue;  // the same as flat
     plan->block_bits = bits;
     plan->prefix_mode = pre;
+    plan->prefix_start = start;
     if (int rc = build_sim_tables(plan, false)) {
       plan->sim_per_variant = saved_pv;
       plan->block_bits = saved_bits;
       plan->prefix_mode = saved_prefix;
+      plan->prefix_start = saved_start;
       (void)build_sim_tables(plan, false);
       return rc;
     }
@@ -269,10 +302,11 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
           plan->sim_per_variant = saved_pv;
           plan->block_bits = saved_bits;
           plan->prefix_mode = saved_prefix;
+          plan->prefix_start = saved_start;
           (void)build_sim_tables(plan, false);
           return rc;
         }
-        if (ms < best) { best = ms; bt = t; bg = c; bb = bits; bpre = pre; }
+        if (ms < best) { best = ms; bt = t; bg = c; bb = bits; bpre = pre; bstart = start; }
       }
     }
   }
@@ -280,6 +314,7 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   plan->sim_grid_cap = bg;
   plan->block_bits = bb;
   plan->prefix_mode = bpre;
+  plan->prefix_start = bpre ? bstart : 0;
   if (int rc = build_sim_tables(plan, false)) {
     plan->sim_per_variant = saved_pv;
     return rc;
@@ -313,7 +348,8 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   plan->auto_mfma_min_k = tmf < t32 ? 1 : kmax + 1;
   if (best_ms) *best_ms = best + std::min(t32, tmf);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[arch_name() + "|" + signature(plan)] = TuneEntry{bt, bg, plan->auto_mfma_min_k, best_epi, best_grid, bb, bpre};
+  g_tune[arch_name() + "|" + signature(plan)] =
+      TuneEntry{bt, bg, plan->auto_mfma_min_k, best_epi, best_grid, bb, bpre ? 1 + plan->prefix_start : 0};
   return CCUT_OK;
 }
 

@@ -165,6 +165,19 @@ def test_prefix_sharing_tree_shape():
     assert tree["fused_ops"] == flat["fused_ops"] and tree["dense_ops"] == flat["dense_ops"]
     ccut.plan_set_prefix_sharing(plan, 0)
     assert ccut.plan_stats(plan) == flat
+    # tree from level 2: the 4 level-2 states run the program up to slot 2 from |0>
+    ccut.plan_set_prefix_sharing(plan, 1)
+    ccut.plan_set_prefix_start(plan, 2)
+    st2 = ccut.plan_stats(plan)
+    assert st2["launches"] == 3 and st2["jobs"] == 2 * (4 + 8 + 16)
+    assert st2["fused_ops"] == flat["fused_ops"]
+    ccut.plan_set_prefix_start(plan, 4)                   # = c_i: the flat schedule
+    assert ccut.plan_stats(plan)["jobs"] == flat["jobs"] and ccut.plan_stats(plan)["launches"] == 1
+    ccut.plan_set_prefix_start(plan, 0)
+    assert ccut.plan_stats(plan) == tree
+    with pytest.raises(ccut.CcutError):
+        ccut.plan_set_prefix_start(plan, -1)
+    ccut.plan_set_prefix_sharing(plan, 0)
     big = ccut.cut_plan(24, brickwork(24, 20, 2, 12, seed=0), 2)   # 2 x 4096 x 2^12 = 2^25 amplitudes
     assert ccut.plan_get_prefix_sharing(big)
     for bad in (-2, 2):

@@ -202,17 +202,20 @@ def test_sim_precisions_match_oracle(lib, prec, bits):
     assert worst < fp32_tol(13)
 
 
-@pytest.mark.parametrize("prec,bits", [("fp16x3", 13), ("fp32", 13), ("fp16x3", 11), ("fp32", 9)])
-def test_prefix_sharing_matches_oracle(lib, prec, bits):
+@pytest.mark.parametrize("prec,bits,start", [("fp16x3", 13, 0), ("fp32", 13, 0), ("fp16x3", 11, 0), ("fp32", 9, 0),
+                                             ("fp16x3", 13, 2), ("fp32", 11, 3), ("fp16x3", 12, 4)])
+def test_prefix_sharing_matches_oracle(lib, prec, bits, start):
     """Prefix sharing (a tree over the slots: each chunk of the segment program run once
-    per prefix of slot choices) gives the oracle's subcircuit states, multi-pass too."""
+    per prefix of slot choices, from tree level `start` on) gives the oracle's subcircuit
+    states, multi-pass too."""
     ccut, pipeline = lib
     o = _q26_oracle()
     run = pipeline.CutRun(26, o["g"], 2)
     ccut.plan_set_sim_precision(run.plan, prec)
     ccut.plan_set_block_bits(run.plan, bits)
     ccut.plan_set_prefix_sharing(run.plan, 1)
-    assert ccut.plan_get_prefix_sharing(run.plan)
+    ccut.plan_set_prefix_start(run.plan, start)
+    assert ccut.plan_get_prefix_sharing(run.plan) and ccut.plan_get_prefix_start(run.plan) == start
     run.arena.zero_()
     run.simulate_subcircuits()
     torch.cuda.synchronize()
@@ -225,15 +228,19 @@ def test_prefix_sharing_matches_oracle(lib, prec, bits):
             assert metrics.one_minus_fidelity(ref, got) < 1e-9, (prec, bits, i, r)
 
 
-@pytest.mark.parametrize("q,n,c,kind", [(20, 2, 8, "brickwork"), (12, 3, 4, "staircase"), (15, 3, 6, "brickwork")])
-def test_prefix_sharing_full_pipeline(lib, q, n, c, kind):
+@pytest.mark.parametrize("q,n,c,kind,start", [(20, 2, 8, "brickwork", 0), (12, 3, 4, "staircase", 0),
+                                              (15, 3, 6, "brickwork", 0), (20, 2, 8, "brickwork", 3),
+                                              (15, 3, 6, "brickwork", 4)])
+def test_prefix_sharing_full_pipeline(lib, q, n, c, kind, start):
     """Tree simulation + merge against the oracle's plain sum, many cuts per segment,
-    three segments with interleaved boundary slots, and CX cuts (H S H on targets)."""
+    three segments with interleaved boundary slots (the middle one with more slots
+    than the tree start, the outer ones with fewer), and CX cuts (H S H on targets)."""
     ccut, pipeline = lib
     g = brickwork(q, 12, n, c, seed=q + c) if kind == "brickwork" else staircase(q, c // (n - 1))
     sizes = equal_blocks(q, n)
     run = pipeline.CutRun(q, g, n, sizes)
     ccut.plan_set_prefix_sharing(run.plan, 1)
+    ccut.plan_set_prefix_start(run.plan, start)
     psi = to_np(run.run("fp32"))
     ref = cutting.cut_simulate(q, g, sizes)
     check_state(ref, psi, q, f"tree q{q} n{n} c{c} {kind}")
