@@ -2,6 +2,7 @@
 // max |psi - ref|.  Cutting reproduces the uncut state exactly up to rounding
 // (Sec. III of the paper); these numbers measure how closely a computed state
 // does.  Two deterministic passes: fixed per-block partials, then one block.
+// The max keeps squared distances (the square root, monotone, is taken once).
 #include "ccut_internal.h"
 
 namespace ccut {
@@ -27,22 +28,54 @@ __device__ __forceinline__ void block_sum5(double v[5], double* red) {
   }
 }
 
+__device__ __forceinline__ void accumulate(double v[5], float px_, float py_, float rx_, float ry_) {
+  const double px = px_, py = py_, rx = rx_, ry = ry_;
+  v[0] += px * px + py * py;
+  v[1] += rx * rx + ry * ry;
+  v[2] += rx * px + ry * py;
+  v[3] += rx * py - ry * px;
+  const double dx = px - rx, dy = py - ry;
+  v[4] = fmax(v[4], dx * dx + dy * dy);  // squared: one square root at the end
+}
+
+// VEC: 16-byte loads (two amplitudes per lane), four of them in flight per array.
+template <bool VEC>
 __global__ __launch_bounds__(RT) void k_reduce_partial(const float2* __restrict__ psi,
                                                        const float2* __restrict__ ref, uint64_t n,
                                                        double* __restrict__ partials) {
   __shared__ double red[RT / 64 * 5];
   double v[5] = {0, 0, 0, 0, 0};
   const uint64_t stride = (uint64_t)gridDim.x * RT;
-  for (uint64_t i = (uint64_t)blockIdx.x * RT + threadIdx.x; i < n; i += stride) {
-    const float2 p = psi[i];
-    const float2 r = ref ? ref[i] : make_float2(0.f, 0.f);
-    const double px = p.x, py = p.y, rx = r.x, ry = r.y;
-    v[0] += px * px + py * py;
-    v[1] += rx * rx + ry * ry;
-    v[2] += rx * px + ry * py;
-    v[3] += rx * py - ry * px;
-    const double dx = px - rx, dy = py - ry;
-    v[4] = fmax(v[4], sqrt(dx * dx + dy * dy));
+  uint64_t i = (uint64_t)blockIdx.x * RT + threadIdx.x;
+  if (VEC) {
+    const float4* p4 = reinterpret_cast<const float4*>(psi);
+    const float4* r4 = reinterpret_cast<const float4*>(ref);
+    const uint64_t n4 = n / 2;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+      float4 p[4], r[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        p[u] = p4[i + u * stride];
+        r[u] = ref ? r4[i + u * stride] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        accumulate(v, p[u].x, p[u].y, r[u].x, r[u].y);
+        accumulate(v, p[u].z, p[u].w, r[u].z, r[u].w);
+      }
+    }
+    for (; i < n4; i += stride) {
+      const float4 p = p4[i];
+      const float4 r = ref ? r4[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+      accumulate(v, p.x, p.y, r.x, r.y);
+      accumulate(v, p.z, p.w, r.z, r.w);
+    }
+  } else {
+    for (; i < n; i += stride) {
+      const float2 p = psi[i];
+      const float2 r = ref ? ref[i] : make_float2(0.f, 0.f);
+      accumulate(v, p.x, p.y, r.x, r.y);
+    }
   }
   block_sum5(v, red);
   if (threadIdx.x == 0)
@@ -58,8 +91,10 @@ __global__ __launch_bounds__(RT) void k_reduce_final(const double* __restrict__ 
     v[4] = fmax(v[4], partials[(uint64_t)i * 5 + 4]);
   }
   block_sum5(v, red);
-  if (threadIdx.x == 0)
-    for (int i = 0; i < 5; ++i) out[i] = v[i];
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 4; ++i) out[i] = v[i];
+    out[4] = sqrt(v[4]);
+  }
 }
 
 }  // namespace
@@ -67,8 +102,13 @@ __global__ __launch_bounds__(RT) void k_reduce_final(const double* __restrict__ 
 int launch_reduce(const float* psi, const float* ref, uint64_t n, double* d_partials, int n_blocks,
                   double* d_out, hipStream_t s) {
   ProfScope prof(PROF_REDUCE, s);
-  hipLaunchKernelGGL(k_reduce_partial, dim3(n_blocks), dim3(RT), 0, s, reinterpret_cast<const float2*>(psi),
-                     reinterpret_cast<const float2*>(ref), n, d_partials);
+  const bool vec = (n % 2) == 0 && ((reinterpret_cast<uintptr_t>(psi) | reinterpret_cast<uintptr_t>(ref)) & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL(k_reduce_partial<true>, dim3(n_blocks), dim3(RT), 0, s, reinterpret_cast<const float2*>(psi),
+                       reinterpret_cast<const float2*>(ref), n, d_partials);
+  else
+    hipLaunchKernelGGL(k_reduce_partial<false>, dim3(n_blocks), dim3(RT), 0, s, reinterpret_cast<const float2*>(psi),
+                       reinterpret_cast<const float2*>(ref), n, d_partials);
   CCUT_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RT), 0, s, d_partials, n_blocks, d_out);
   CCUT_HIP(hipGetLastError());
