@@ -103,7 +103,8 @@ typedef struct ccut_plan_info {
                                           rank-2 cut, two per rank-4 cut) */
   int32_t c_boundary[CCUT_MAX_SEG];    /* c_b: variant bits of the cuts between segments b and b+1 */
   int64_t n_sub;                       /* N_sub = sum_i 2^{c_i} = sum_i k^{cuts_i}  (Sec. III.A) */
-  int64_t n_terms;                     /* 2^{sum_b c_b} global merge terms (Algorithm 3) */
+  int64_t n_terms;                     /* 2^{sum_b c_b} global merge terms (Algorithm 3);
+                                          INT64_MAX when that exceeds 2^62 */
   uint64_t seg_state_offset[CCUT_MAX_SEG]; /* byte offset of segment i's variant 0 in the arena */
   uint64_t state_bytes;                /* bytes of all subcircuit states */
   uint64_t arena_bytes;                /* the whole pipeline (simulation + merge workspace): size the arena to this */

@@ -597,7 +597,7 @@ extern "C" int ccut_plan_info(const ccut_plan_t* plan, ccut_plan_info_t* info) {
   for (size_t b = 0; b < plan->c_b.size(); ++b) info->c_boundary[b] = plan->c_b[b];
   int bits = 0;
   for (int c : plan->c_b) bits += c;
-  info->n_terms = (int64_t)1 << bits;
+  info->n_terms = bits < 63 ? (int64_t)1 << bits : INT64_MAX;  // eight segments can reach 2^64
   info->state_bytes = plan->state_bytes;
   info->arena_bytes = plan->total_arena;
   info->sim_arena_bytes = plan->sim_bytes;

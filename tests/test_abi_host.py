@@ -248,3 +248,16 @@ def test_pauli_rotation_runs_fuse_into_one_cut():
     # a single rotation alone is rank 2 (one bit), SWAP rank 4 (two bits)
     assert ccut.cut_plan(q, [Gate("RZZ", 3, 4, 0.5)], 2).cuts()[0]["n_bits"] == 1
     assert ccut.cut_plan(q, [Gate("SWAP", 3, 4)], 2).cuts()[0]["n_bits"] == 2
+
+
+def test_term_count_saturates():
+    """Eight segments with 16 cut bits on every other boundary (each segment within its
+    16-bit limit) have 2^64 global terms: reported as INT64_MAX, not an overflow."""
+    q, sizes = 16, [2] * 8
+    g = []
+    for b in (0, 2, 4, 6):                 # boundaries between segments b and b + 1
+        lo, hi = 2 * b + 1, 2 * b + 2
+        g += [Gate("CZ", lo, hi)] * 16
+    info = ccut.cut_plan(q, g, 8, sizes).info()
+    assert info["c_boundary"][:7] == [16, 0, 16, 0, 16, 0, 16]
+    assert info["n_terms"] == 2 ** 63 - 1
