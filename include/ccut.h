@@ -398,9 +398,11 @@ int ccut_plan_get_prefix_start(const ccut_plan_t* plan, int32_t* out);
  * float32 kernel against the split-precision MFMA GEMM over its variants and
  * grids (median of `reps` runs, HIP events on `stream`), applies the fastest
  * to the plan and records it in a process-wide cache keyed by (architecture,
- * plan shape); later plans of the same shape start from it.  Overwrites the
- * arena and d_psi.  *best_ms (nullable) receives the tuned simulation + merge
- * time.  ccut_autotune_save / _load write and read the cache as text (one
+ * plan shape); later plans of the same shape start from it.  The block size and
+ * prefix-sharing mode regroup the gates, so a tuned plan's states agree with the
+ * untuned ones to float32 rounding (not bit for bit).  Overwrites the arena and
+ * d_psi.  *best_ms (nullable) receives the tuned simulation + merge time.
+ * ccut_autotune_save / _load write and read the cache as text (one
  * "key threads grid_cap mfma_min_terms epilogue merge_grid block_bits prefix"
  * line per entry; prefix 0 = off, 1 + L = on with the tree from level L).
  * Errors: CCUT_EINVAL, CCUT_ENOSPC, CCUT_EHIP.

@@ -98,7 +98,15 @@ int staged_copy(void* dst, const void* src, uint64_t bytes, hipStream_t s) {
   if (R.used[slot]) CCUT_HIP(hipEventSynchronize(R.ev[slot]));
   unsigned char* h = R.host + (uint64_t)slot * SLOT_BYTES;
   std::memcpy(h, src, bytes);
-  CCUT_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s));
+  // a kernel reading the pinned slot starts sooner than a copy-engine transfer
+  void* hd = nullptr;
+  if ((bytes & 15) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0 &&
+      hipHostGetDevicePointer(&hd, h, 0) == hipSuccess && hd) {
+    if (int rc = launch_table_copy(dst, hd, bytes, s)) return rc;
+  } else {
+    (void)hipGetLastError();  // a failed device-pointer query leaves an error behind
+    CCUT_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s));
+  }
   CCUT_HIP(hipEventRecord(R.ev[slot], s));
   R.used[slot] = true;
   return 0;

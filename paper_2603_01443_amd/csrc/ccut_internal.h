@@ -222,6 +222,9 @@ int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, co
                const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax,
                int threads, int grid_cap, hipStream_t s);
 
+// Copies `bytes` (a multiple of 16, 16-byte aligned) from pinned host memory to dst.
+int launch_table_copy(void* dst, const void* host_src, uint64_t bytes, hipStream_t s);
+
 // Builds the n MFMA operand tables listed by refs into gtab (n * GROUP_TABLE_UINT4 uint4).
 int launch_group_tables(const KOp* d_ops, const GroupRef* d_refs, int n, uint4* gtab, hipStream_t s);
 

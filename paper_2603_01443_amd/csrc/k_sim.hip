@@ -36,6 +36,8 @@
 // the work.
 #include "ccut_internal.h"
 
+#include <algorithm>
+
 namespace ccut {
 
 namespace {
@@ -409,6 +411,15 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
   }
 }
 
+// Copies a table image from pinned host memory (the staging ring) into the arena.
+// A kernel reading host memory over the bus starts sooner than a copy-engine
+// transfer, and the images are small (tens to hundreds of KiB).
+__global__ __launch_bounds__(256) void k_table_copy(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                    uint64_t n16) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
 constexpr size_t shmem_bytes(int bmax) {
   return 2 * TAB * sizeof(uint64_t) + sizeof(float2) * (((size_t)1 << bmax) + ((size_t)1 << bmax) / 16);
 }
@@ -523,6 +534,18 @@ int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, co
                               threads, grid, s);
   return launch_sim_m<false>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, nullptr, base, bmax,
                              threads, grid, s);
+}
+
+int launch_table_copy(void* dst, const void* host_src, uint64_t bytes, hipStream_t s) {
+  if ((bytes & 15) || ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(host_src)) & 15))
+    return fail(CCUT_EINVAL, "table copy needs 16-byte alignment");
+  const uint64_t n16 = bytes / 16;
+  const uint64_t blocks = std::min<uint64_t>((n16 + 255) / 256, 1024);
+  if (blocks == 0) return 0;
+  hipLaunchKernelGGL(k_table_copy, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<uint4*>(dst),
+                     static_cast<const uint4*>(host_src), n16);
+  CCUT_HIP(hipGetLastError());
+  return 0;
 }
 
 int launch_group_tables(const KOp* d_ops, const GroupRef* d_refs, int n, uint4* gtab, hipStream_t s) {

@@ -76,7 +76,10 @@ def test_autotune_keeps_results_and_caches(lib, tmp_path):
     print("autotuned", cfg, f"{best:.3f} ms", flush=True)
     assert best > 0 and cfg["threads"] in (256, 512, 1024)
     after = run.run("bf16x3")
-    assert torch.equal(torch.view_as_real(after), torch.view_as_real(before))
+    # the tuned block size and prefix-sharing mode regroup the gates (rounding order),
+    # so the state agrees to float32 rounding rather than bit for bit
+    diff = (after - before).abs().max().item()
+    assert diff < 1e-4 * 2 ** (-q / 2), diff
     path = str(tmp_path / "tune.txt")
     ccut.autotune_save(path)
     assert os.path.getsize(path) > 0
