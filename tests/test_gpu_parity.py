@@ -100,6 +100,36 @@ def test_partitions(lib, q, n, cuts, sizes, d):
     check_state(ref, psi, q, f"q{q} n{n} cuts{cuts}")
 
 
+def _degenerate_cases():
+    H, T = "H", "T"
+    yield "empty circuit, two segments", 6, [], [3, 3]
+    yield "one qubit, one segment", 1, [Gate(H, 0), Gate(T, 0)], [1]
+    yield "gates on the first segment only", 9, [Gate(H, 0), Gate("CX", 0, 1), Gate("RY", 2, -1, 0.7)], [3, 3, 3]
+    g = [Gate("CZ", 3, 4)] + [Gate(H, j) for j in range(8)] + [Gate("RX", 4, -1, 1.1), Gate("CX", 4, 3)]
+    yield "cut gates first and last", 8, g, [4, 4]
+    g = [Gate(H, j) for j in range(16)]
+    g += [Gate("CZ", 2 * b + 1, 2 * b + 2) for b in range(7)]
+    g += [Gate("RYRZ", j, -1, 0.3 * j, 0.2 * j) for j in range(16)]
+    g += [Gate("CX", 2 * b + 2, 2 * b + 1) for b in range(7)]
+    yield "eight segments of two, two cuts per boundary", 16, g, [2] * 8
+
+
+@pytest.mark.parametrize("case", list(_degenerate_cases()), ids=lambda c: c[0])
+def test_degenerate_circuits(lib, case):
+    """Empty and one-qubit circuits, segments without gates, cuts at the ends of the gate
+    list and the largest segment count (a seven-stage chain)."""
+    ccut, pipeline = lib
+    _, q, g, sizes = case
+    n = len(sizes)
+    ref = statevector.simulate(q, g)
+    run = pipeline.CutRun(q, g, n, sizes)
+    for prec in ("fp32", "auto"):
+        psi = to_np(run.run(prec))
+        assert metrics.max_abs_error(ref, psi) < 1e-3 * 2 ** (-q / 2) + 1e-7, prec
+        assert metrics.one_minus_fidelity(ref, psi) < 1e-6, prec
+    assert metrics.max_abs_error(ref, to_np(pipeline.uncut(q, g))) < 1e-6
+
+
 @pytest.mark.parametrize("q,n,copies", [(6, 2, 1), (8, 2, 3), (9, 3, 2)])
 def test_cx_staircase(lib, q, n, copies):
     ccut, pipeline = lib
