@@ -175,21 +175,38 @@ __device__ __forceinline__ const float* kop_matrix(const KOp* k, int slot, int v
   return k->m + ((slot >= 0) ? 8 * ((variant >> slot) & 1) : 0);
 }
 
-// Applies the ops [o0, o1) of a register stage to one thread's amplitudes.
+// First 32 bytes of a KOp (type, a, b, slot, cond, nterms, pad[0..1]): for a group
+// they hold every member slot and the operand table index.
+struct OpHead {
+  int32_t type, a, b, slot, cond, nterms, pad0, pad1;
+};
+
+__device__ __forceinline__ OpHead load_head(const KOp* k) {
+  const int4* p = reinterpret_cast<const int4*>(k);
+  const int4 x = p[0], y = p[1];
+  return OpHead{x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+}
+
+// Applies the ops [o0, o1) of a register stage to one thread's amplitudes.  The
+// next op's header is loaded before the current op runs, so its load latency
+// (op tables are read by every workgroup) hides behind the arithmetic.
 // full_waves: every lane of the wavefront holds a thread slot (the MFMA path
 // exchanges data between lane halves, which needs both halves active).
 template <bool MFMA>
 __device__ __forceinline__ void run_stage_ops(float2 (&a)[R], const int (&idx)[R], const KOp* __restrict__ ops,
                                               int o0, int o1, uint64_t blockbase, int variant,
                                               const uint4* __restrict__ gtab, bool full_waves) {
+  if (o0 >= o1) return;
+  OpHead h = load_head(ops + o0);
   for (int o = o0; o < o1;) {
     const KOp* k = ops + o;
-    const int type = k->type;
+    const int type = h.type;
+    const int next = o + (type == KOP_GROUP ? 1 + REG_BITS : 1);
+    OpHead hn = h;
+    if (next < o1) hn = load_head(ops + next);
     if (MFMA && full_waves && type == KOP_GROUP) {
       // table of this choice of the members' slots: bit j = slot bit of the j-th slotted member
-      const int4 h = *reinterpret_cast<const int4*>(k);
-      const int s2 = k->cond, s3 = k->nterms;
-      const int slots[4] = {h.z, h.w, s2, s3};
+      const int slots[4] = {h.b, h.slot, h.cond, h.nterms};
       int sel = 0, j = 0;
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
@@ -198,71 +215,62 @@ __device__ __forceinline__ void run_stage_ops(float2 (&a)[R], const int (&idx)[R
           ++j;
         }
       }
-      const uint4* gt = gtab + (uint64_t)(k->pad[0] + sel) * GROUP_TABLE_UINT4 + (threadIdx.x & 63) * 4;
+      const uint4* gt = gtab + (uint64_t)(h.pad0 + sel) * GROUP_TABLE_UINT4 + (threadIdx.x & 63) * 4;
       group_mfma(a, gt);
-      o += 1 + REG_BITS;
-      continue;
-    }
-    if (type == KOP_GROUP) {
+    } else if (type == KOP_GROUP) {
       // one 2x2 gate per register position: every matrix address comes from the
       // header, the four matrices are fetched together, then straight-line arithmetic
-      const int4 h = *reinterpret_cast<const int4*>(k);
-      const int s3 = k->nterms;
-      const int s2 = k->cond;
-      const float* m0 = kop_matrix(k + 1, h.z, variant);
-      const float* m1 = kop_matrix(k + 2, h.w, variant);
-      const float* m2 = kop_matrix(k + 3, s2, variant);
-      const float* m3 = kop_matrix(k + 4, s3, variant);
+      const float* m0 = kop_matrix(k + 1, h.b, variant);
+      const float* m1 = kop_matrix(k + 2, h.slot, variant);
+      const float* m2 = kop_matrix(k + 3, h.cond, variant);
+      const float* m3 = kop_matrix(k + 4, h.nterms, variant);
       dense_reg<0>(a, m0);
       dense_reg<1>(a, m1);
       dense_reg<2>(a, m2);
       dense_reg<3>(a, m3);
-      o += 1 + REG_BITS;
-      continue;
-    }
-    ++o;
-    const int cond = k->cond;
-    if (cond >= 0 && !((blockbase >> cond) & 1)) continue;
-    const float* m = kop_matrix(k, k->slot, variant);
-    if (type == KOP_DENSE) {
-      switch (k->a) {
-        case 0: dense_reg<0>(a, m); break;
-        case 1: dense_reg<1>(a, m); break;
-        case 2: dense_reg<2>(a, m); break;
-        default: dense_reg<3>(a, m); break;
-      }
-    } else if (type == KOP_DIAG) {
-      const int j = k->a;
-      const float2 d0 = make_float2(m[0], m[1]), d1 = make_float2(m[6], m[7]);
+    } else if (!(h.cond >= 0 && !((blockbase >> h.cond) & 1))) {
+      const float* m = kop_matrix(k, h.slot, variant);
+      if (type == KOP_DENSE) {
+        switch (h.a) {
+          case 0: dense_reg<0>(a, m); break;
+          case 1: dense_reg<1>(a, m); break;
+          case 2: dense_reg<2>(a, m); break;
+          default: dense_reg<3>(a, m); break;
+        }
+      } else if (type == KOP_DIAG) {
+        const int jb = h.a;
+        const float2 d0 = make_float2(m[0], m[1]), d1 = make_float2(m[6], m[7]);
 #pragma unroll
-      for (int e = 0; e < R; ++e) a[e] = cmul(((idx[e] >> j) & 1) ? d1 : d0, a[e]);
-    } else if (type == KOP_CZL) {
-      const uint32_t* t = reinterpret_cast<const uint32_t*>(k->m);
-      const int nt = k->nterms;
+        for (int e = 0; e < R; ++e) a[e] = cmul(((idx[e] >> jb) & 1) ? d1 : d0, a[e]);
+      } else if (type == KOP_CZL) {
+        const uint32_t* t = reinterpret_cast<const uint32_t*>(k->m);
+        const int nt = h.nterms;
 #pragma unroll
-      for (int e = 0; e < R; ++e) {
-        const uint32_t i = (uint32_t)idx[e];
-        uint32_t par = 0;
-        for (int q = 0; q < nt; ++q) par ^= __popc(i & (i >> t[2 * q]) & t[2 * q + 1]);
-        if (par & 1) a[e] = make_float2(-a[e].x, -a[e].y);
-      }
-    } else if (type == KOP_SCALAR) {
-      const bool bit = (blockbase >> k->a) & 1;
-      const float2 ph = bit ? make_float2(m[6], m[7]) : make_float2(m[0], m[1]);
+        for (int e = 0; e < R; ++e) {
+          const uint32_t i = (uint32_t)idx[e];
+          uint32_t par = 0;
+          for (int q = 0; q < nt; ++q) par ^= __popc(i & (i >> t[2 * q]) & t[2 * q + 1]);
+          if (par & 1) a[e] = make_float2(-a[e].x, -a[e].y);
+        }
+      } else if (type == KOP_SCALAR) {
+        const bool bit = (blockbase >> h.a) & 1;
+        const float2 ph = bit ? make_float2(m[6], m[7]) : make_float2(m[0], m[1]);
 #pragma unroll
-      for (int e = 0; e < R; ++e) a[e] = cmul(ph, a[e]);
-    } else {  // KOP_CXL: control local bit a, target register position b
-      switch (k->b) {
-        case 0: cx_reg<0>(a, idx, k->a); break;
-        case 1: cx_reg<1>(a, idx, k->a); break;
-        case 2: cx_reg<2>(a, idx, k->a); break;
-        default: cx_reg<3>(a, idx, k->a); break;
+        for (int e = 0; e < R; ++e) a[e] = cmul(ph, a[e]);
+      } else {  // KOP_CXL: control local bit a, target register position b
+        switch (h.b) {
+          case 0: cx_reg<0>(a, idx, h.a); break;
+          case 1: cx_reg<1>(a, idx, h.a); break;
+          case 2: cx_reg<2>(a, idx, h.a); break;
+          default: cx_reg<3>(a, idx, h.a); break;
+        }
       }
     }
+    h = hn;
+    o = next;
   }
 }
 
-// Ops one at a time over the whole LDS block (small blocks).
 template <int NT>
 __device__ __forceinline__ void run_ops_direct(float2* sh, int nb, const KOp* __restrict__ ops, int o0, int o1,
                                                uint64_t blockbase, int variant) {
