@@ -122,6 +122,13 @@ def main():
     # one autotuning pass (outside the timed region); plans of this shape reuse its choice
     tuned_ms = ccut.autotune(plan0, arena, psi, reps=3, stream=stream)
     log(f"bench: autotuned launch {ccut.plan_get_launch(plan0)} ({tuned_ms:.3f} ms)")
+    # plans built from now on start from the tuned configuration, whose tables may
+    # need more arena than the untuned plan reserved: size the arena for them
+    need = ccut.cut_plan(Q, garr, NSEG, sizes).info()["arena_bytes"]
+    if need > arena.numel():
+        del arena
+        torch.cuda.empty_cache()
+        arena = torch.empty(need, dtype=torch.uint8, device=dev)
 
     t_pre = []
     keep = []
@@ -229,11 +236,15 @@ def main():
     sim_ms = kernels_ms.get("sim", 0.0) * kernel_launches.get("sim", 0)
     roof_sim = None
     if sim_ms > 0:
+        prefix = (f"prefix sharing from level {ccut.plan_get_prefix_start(plan0)}"
+                  if ccut.plan_get_prefix_sharing(plan0) else "flat")
         roof_sim = {"bound": "alu", "achieved": sim_flops / (sim_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "kernel": f"sim ({ccut.plan_get_sim_precision(plan0)} groups, "
-                    f"2^{ccut.plan_get_block_bits(plan0)} blocks)", "avg_ms_per_step": sim_ms,
+                    f"2^{ccut.plan_get_block_bits(plan0)} blocks, {prefix})", "avg_ms_per_step": sim_ms,
                     "algorithmic_flops": sim_flops,
-                    "note": "latency-bound (2 wavefronts per SIMD at this size); from the breakdown steps"}
+                    "note": "flops of the flat schedule (fused 2x2 gates on every variant); bound by the op "
+                            "interpreter, stage barriers and the group arithmetic, not by HBM; from the "
+                            "breakdown steps"}
         roof_sim["frac"] = roof_sim["achieved"] / roof_sim["peak"]
     log(f"bench: kernels (avg ms per launch) {kernels_ms}")
 

@@ -398,7 +398,9 @@ int ccut_plan_get_prefix_start(const ccut_plan_t* plan, int32_t* out);
  * float32 kernel against the split-precision MFMA GEMM over its variants and
  * grids (median of `reps` runs, HIP events on `stream`), applies the fastest
  * to the plan and records it in a process-wide cache keyed by (architecture,
- * plan shape); later plans of the same shape start from it.  The block size and
+ * plan shape); later plans of the same shape start from it (their tables, and so
+ * their info.arena_bytes, can be larger than the tuning plan's: size an arena
+ * from the plan that will use it).  The block size and
  * prefix-sharing mode regroup the gates, so a tuned plan's states agree with the
  * untuned ones to float32 rounding (not bit for bit).  Overwrites the arena and
  * d_psi.  *best_ms (nullable) receives the tuned simulation + merge time.
