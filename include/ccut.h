@@ -391,7 +391,7 @@ int ccut_plan_get_prefix_start(const ccut_plan_t* plan, int32_t* out);
 
 /*
  * Autotuner: times the simulation kernel over prefix sharing off / on (tree
- * from level 0, 2, 3, 4) x LDS
+ * from level 0, 2, 3, 4, c - 2 and c - 1, c the largest c_i) x LDS
  * block sizes (whole segment, 2 and 4 blocks per state; sizes whose tables do
  * not fit arena_bytes are skipped) x workgroup sizes x persistent grid sizes,
  * and the merge with the

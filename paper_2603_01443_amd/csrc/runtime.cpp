@@ -1,6 +1,7 @@
 // Runtime around the kernels: HIP-graph capture of a plan's whole pipeline,
 // launch configuration, and a measuring autotuner with a persistent cache.
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <functional>
@@ -271,12 +272,18 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   // states in LDS, then 2 and 4 blocks
   int cmax = 0;
   for (const auto& S : plan->segs) cmax = std::max(cmax, S.c);
-  const int pre_modes[5][2] = {{0, 0}, {1, 0}, {1, 2}, {1, 3}, {1, 4}};
-  for (int pm = 0; pm < (any_cut ? 5 : 1); ++pm)
+  // tree starts: the full tree, a few early levels, and the last two levels (only the
+  // final slots shared)
+  std::vector<std::array<int, 2>> pre_modes = {{0, 0}};
+  if (any_cut)
+    for (int st : {0, 2, 3, 4, cmax - 2, cmax - 1})
+      if (st >= 0 && (st == 0 || st < cmax) &&
+          std::find(pre_modes.begin(), pre_modes.end(), std::array<int, 2>{1, st}) == pre_modes.end())
+        pre_modes.push_back({1, st});
+  for (size_t pm = 0; pm < pre_modes.size(); ++pm)
   for (int bits = std::min(qmax, PASS_MAX_B); bits >= std::max(plan->low_bits + 1, std::min(qmax, PASS_MAX_B) - 2);
        --bits) {
     const int pre = pre_modes[pm][0], start = pre_modes[pm][1];
-    if (pre && start > 0 && start >= cmax) continue;  // the same as flat
     plan->block_bits = bits;
     plan->prefix_mode = pre;
     plan->prefix_start = start;
