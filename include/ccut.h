@@ -501,8 +501,11 @@ int ccut_decide(int32_t q, int32_t d, int32_t c_total, const float* d_params, do
  * recorded events, folds them into per-family totals and returns, for kernel
  * family `kernel` (0 <= kernel < CCUT_PROF_KERNELS), the number of launches
  * and their summed device milliseconds since the last reset, plus the family
- * name ("sim", "merge_f32", "split_R", "split_L", "merge_gemm", "reduce",
- * "mlp", "expect"; a static string, pass NULL to skip).  Errors: CCUT_EINVAL, CCUT_EHIP.
+ * name ("sim", "merge_f32", "split", "tables", "merge_gemm", "reduce",
+ * "mlp", "expect"; a static string, pass NULL to skip).  "split" is the
+ * packing of both merge GEMM operands (one launch per GEMM merge stage);
+ * "tables" the device copies of a plan's op and gate tables and the MFMA
+ * group tables built from them.  Errors: CCUT_EINVAL, CCUT_EHIP.
  */
 #define CCUT_PROF_KERNELS 8
 int ccut_profile_enable(int32_t on);

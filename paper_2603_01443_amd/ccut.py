@@ -379,7 +379,7 @@ def profile_enable(on: bool = True) -> None:
     _check(_lib.ccut_profile_enable(1 if on else 0))
 
 
-PROFILE_KERNELS = ("sim", "merge_f32", "split_R", "split_L", "merge_gemm", "reduce", "mlp", "expect")
+PROFILE_KERNELS = ("sim", "merge_f32", "split", "tables", "merge_gemm", "reduce", "mlp", "expect")
 
 
 def profile_mask(kernels=None) -> None:

@@ -202,7 +202,7 @@ struct DeviceTables {
 };
 
 // ---------------------------------------------------------------- timing
-enum ProfKernel : int { PROF_SIM = 0, PROF_MERGE_F32, PROF_SPLIT_R, PROF_SPLIT_L, PROF_MERGE_GEMM, PROF_REDUCE,
+enum ProfKernel : int { PROF_SIM = 0, PROF_MERGE_F32, PROF_SPLIT, PROF_TABLES, PROF_MERGE_GEMM, PROF_REDUCE,
                         PROF_MLP, PROF_EXPECT, PROF_N };
 int prof_begin(int kernel, hipStream_t s);   // -1 when timing is off
 void prof_end(int token, hipStream_t s);

@@ -63,17 +63,20 @@ __device__ __forceinline__ void split_value(float v, uint16_t& hi, uint16_t& lo)
   }
 }
 
-// ------------------------------------------------------------ split kernels
-// R fragments: one thread per (cb, s, lane) for one batch entry.
+// ------------------------------------------------------------ split kernel
+__device__ __forceinline__ uint4 pack8(const uint16_t (&v)[8]) {
+  uint4 r;
+  r.x = v[0] | ((uint32_t)v[1] << 16); r.y = v[2] | ((uint32_t)v[3] << 16);
+  r.z = v[4] | ((uint32_t)v[5] << 16); r.w = v[6] | ((uint32_t)v[7] << 16);
+  return r;
+}
+
+// R fragment of thread t (one (cb, s, lane)) for batch entry beta.  The fp16x2
+// mode never reads Rlo, so it is not written.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_split_R(const float2* __restrict__ A, uint64_t a_kstride,
-                                                 uint64_t a_bstride, const float2* __restrict__ w, int K, int qx,
-                                                 int S, uint4* __restrict__ hi, uint4* __restrict__ lo,
-                                                 uint64_t plane_stride) {
-  const int beta = blockIdx.y;
-  const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  const uint64_t ncb = (uint64_t)1 << (qx + 1 - 5);  // 2N / 32 column blocks
-  if (t >= ncb * S * 64) return;
+__device__ __forceinline__ void split_R_one(uint64_t t, int beta, const float2* __restrict__ A, uint64_t a_kstride,
+                                            uint64_t a_bstride, const float2* __restrict__ w, int K, int S,
+                                            uint4* __restrict__ hi, uint4* __restrict__ lo, uint64_t plane_stride) {
   const int lane = (int)(t & 63);
   const uint64_t cs = t >> 6;
   const int s = (int)(cs % S);
@@ -97,25 +100,15 @@ __global__ __launch_bounds__(256) void k_split_R(const float2* __restrict__ A, u
     split_value<MODE>(r0, h[2 * p], l[2 * p]);
     split_value<MODE>(r1, h[2 * p + 1], l[2 * p + 1]);
   }
-  uint4 H, Lo;
-  H.x = h[0] | ((uint32_t)h[1] << 16); H.y = h[2] | ((uint32_t)h[3] << 16);
-  H.z = h[4] | ((uint32_t)h[5] << 16); H.w = h[6] | ((uint32_t)h[7] << 16);
-  Lo.x = l[0] | ((uint32_t)l[1] << 16); Lo.y = l[2] | ((uint32_t)l[3] << 16);
-  Lo.z = l[4] | ((uint32_t)l[5] << 16); Lo.w = l[6] | ((uint32_t)l[7] << 16);
-  hi[beta * plane_stride + t] = H;
-  lo[beta * plane_stride + t] = Lo;
+  hi[beta * plane_stride + t] = pack8(h);
+  if (MODE != MERGE_FP16X2) lo[beta * plane_stride + t] = pack8(l);
 }
 
-// L fragments: one thread per (rb, s, lane) for one batch entry.
+// L fragment of thread t (one (rb, s, lane)) for batch entry beta.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_split_L(const float2* __restrict__ B, uint64_t b_kstride,
-                                                 uint64_t b_bstride, int K, int qy, int S,
-                                                 uint4* __restrict__ hi, uint4* __restrict__ lo,
-                                                 uint64_t plane_stride) {
-  const int beta = blockIdx.y;
-  const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  const uint64_t nrb = (uint64_t)1 << (qy - 5);
-  if (t >= nrb * S * 64) return;
+__device__ __forceinline__ void split_L_one(uint64_t t, int beta, const float2* __restrict__ B, uint64_t b_kstride,
+                                            uint64_t b_bstride, int K, int S, uint4* __restrict__ hi,
+                                            uint4* __restrict__ lo, uint64_t plane_stride) {
   const int lane = (int)(t & 63);
   const uint64_t rs = t >> 6;
   const int s = (int)(rs % S);
@@ -130,13 +123,26 @@ __global__ __launch_bounds__(256) void k_split_L(const float2* __restrict__ B, u
     split_value<MODE>(b.x, h[2 * p], l[2 * p]);
     split_value<MODE>(b.y, h[2 * p + 1], l[2 * p + 1]);
   }
-  uint4 H, Lo;
-  H.x = h[0] | ((uint32_t)h[1] << 16); H.y = h[2] | ((uint32_t)h[3] << 16);
-  H.z = h[4] | ((uint32_t)h[5] << 16); H.w = h[6] | ((uint32_t)h[7] << 16);
-  Lo.x = l[0] | ((uint32_t)l[1] << 16); Lo.y = l[2] | ((uint32_t)l[3] << 16);
-  Lo.z = l[4] | ((uint32_t)l[5] << 16); Lo.w = l[6] | ((uint32_t)l[7] << 16);
-  hi[beta * plane_stride + t] = H;
-  lo[beta * plane_stride + t] = Lo;
+  hi[beta * plane_stride + t] = pack8(h);
+  lo[beta * plane_stride + t] = pack8(l);
+}
+
+// Both operands in one launch: workgroups [0, r_blocks) write R fragments
+// (batch entries < r_batch), the rest L fragments (batch entries < batch).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_split(MergeMfmaArgs a, int r_blocks) {
+  const int beta = blockIdx.y;
+  if ((int)blockIdx.x < r_blocks) {
+    if (beta >= a.r_batch) return;
+    const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= ((uint64_t)1 << (a.qx + 1 - 5)) * a.S * 64) return;
+    split_R_one<MODE>(t, beta, a.A, a.a_kstride, a.a_bstride, a.w, a.K, a.S, a.Rhi, a.Rlo, a.r_plane_stride);
+  } else {
+    if (beta >= a.batch) return;
+    const uint64_t t = (uint64_t)(blockIdx.x - r_blocks) * 256 + threadIdx.x;
+    if (t >= ((uint64_t)1 << (a.qy - 5)) * a.S * 64) return;
+    split_L_one<MODE>(t, beta, a.B, a.b_kstride, a.b_bstride, a.K, a.S, a.Lhi, a.Llo, a.l_plane_stride);
+  }
 }
 
 // ------------------------------------------------------------- GEMM kernel
@@ -282,21 +288,15 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
 template <int MODE>
 int launch_mode(const MergeMfmaArgs& a, int variant, int grid_cap, hipStream_t s) {
   const int S = a.S;
-  // split R (the A side, weights folded in): per batch entry unless shared
+  // split R (the A side, weights folded in; per batch entry unless shared) and L
   {
-    const uint64_t n = ((uint64_t)1 << (a.qx + 1 - 5)) * S * 64;
-    dim3 grid((unsigned)((n + 255) / 256), a.r_batch);
-    ProfScope prof(PROF_SPLIT_R, s);
-    hipLaunchKernelGGL(k_split_R<MODE>, grid, dim3(256), 0, s, a.A, a.a_kstride, a.a_bstride, a.w, a.K, a.qx, S,
-                       a.Rhi, a.Rlo, a.r_plane_stride);
-    CCUT_HIP(hipGetLastError());
-  }
-  {
-    const uint64_t n = ((uint64_t)1 << (a.qy - 5)) * S * 64;
-    dim3 grid((unsigned)((n + 255) / 256), a.batch);
-    ProfScope prof(PROF_SPLIT_L, s);
-    hipLaunchKernelGGL(k_split_L<MODE>, grid, dim3(256), 0, s, a.B, a.b_kstride, a.b_bstride, a.K, a.qy, S, a.Lhi,
-                       a.Llo, a.l_plane_stride);
+    const uint64_t nr = ((uint64_t)1 << (a.qx + 1 - 5)) * S * 64;
+    const uint64_t nl = ((uint64_t)1 << (a.qy - 5)) * S * 64;
+    const uint64_t r_blocks = (nr + 255) / 256, l_blocks = (nl + 255) / 256;
+    if (r_blocks + l_blocks > 0x7FFFFFFFull) return fail(CCUT_EUNSUPPORTED, "merge operands too large to split");
+    dim3 grid((unsigned)(r_blocks + l_blocks), std::max(a.batch, a.r_batch));
+    ProfScope prof(PROF_SPLIT, s);
+    hipLaunchKernelGGL(k_split<MODE>, grid, dim3(256), 0, s, a, (int)r_blocks);
     CCUT_HIP(hipGetLastError());
   }
   const int col_tiles = 1 << (a.qx + 1 - 8);                      // 256 real columns per tile

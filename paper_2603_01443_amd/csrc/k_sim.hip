@@ -550,6 +550,7 @@ int launch_table_copy(void* dst, const void* host_src, uint64_t bytes, hipStream
   const uint64_t n16 = bytes / 16;
   const uint64_t blocks = std::min<uint64_t>((n16 + 255) / 256, 1024);
   if (blocks == 0) return 0;
+  ProfScope prof(PROF_TABLES, s);
   hipLaunchKernelGGL(k_table_copy, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<uint4*>(dst),
                      static_cast<const uint4*>(host_src), n16);
   CCUT_HIP(hipGetLastError());
@@ -558,6 +559,7 @@ int launch_table_copy(void* dst, const void* host_src, uint64_t bytes, hipStream
 
 int launch_group_tables(const KOp* d_ops, const GroupRef* d_refs, int n, uint4* gtab, hipStream_t s) {
   if (n <= 0) return 0;
+  ProfScope prof(PROF_TABLES, s);
   hipLaunchKernelGGL(k_group_tables, dim3(n), dim3(64), 0, s, d_ops, d_refs, gtab);
   CCUT_HIP(hipGetLastError());
   return 0;

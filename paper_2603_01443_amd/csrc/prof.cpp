@@ -27,7 +27,7 @@ std::vector<hipEvent_t> g_pool;
 int64_t g_count[PROF_N] = {};
 double g_ms[PROF_N] = {};
 
-const char* const kNames[PROF_N] = {"sim",    "merge_f32", "split_R", "split_L",
+const char* const kNames[PROF_N] = {"sim",    "merge_f32", "split",  "tables",
                                     "merge_gemm", "reduce", "mlp",     "expect"};
 
 hipEvent_t take() {
