@@ -114,6 +114,18 @@ def test_error_codes():
     assert "limit" in str(e.value) or "max" in str(e.value)
 
 
+def test_merge_variant_range():
+    """Merge GEMM variants 0..3 are accepted and read back; 4 and negative grids are not."""
+    plan = ccut.cut_plan(16, brickwork(16, 4, 2, 3, seed=1), 2)
+    for v in range(4):
+        ccut.plan_set_merge(plan, v, 256)
+        assert ccut.plan_get_merge(plan) == {"variant": v, "grid_cap": 256}
+    for v, cap in ((4, 0), (-1, 0), (3, -1)):
+        with pytest.raises(ccut.CcutError) as e:
+            ccut.plan_set_merge(plan, v, cap)
+        assert e.value.code == ccut.EINVAL
+
+
 def test_block_bits_reschedule():
     """The LDS block size reschedules the segment programs: smaller blocks mean
     more passes and launches but the same fused program; the automatic choice

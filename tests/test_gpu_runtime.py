@@ -88,13 +88,15 @@ def test_autotune_keeps_results_and_caches(lib, tmp_path):
     assert ccut.plan_get_launch(fresh) == {**cfg, "per_variant": 0}
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "bf16", "fp16x2"])
-def test_merge_gemm_variants_bit_identical(lib, prec):
-    """Store path (direct / LDS transpose) and persistent grids change only data movement:
-    every variant writes the same bits."""
+@pytest.mark.parametrize("prec,c", [("bf16x3", 6), ("fp16x3", 6), ("bf16", 6), ("fp16x2", 6),
+                                    ("fp16x2", 3), ("bf16", 5), ("fp16x2", 7)])
+def test_merge_gemm_variants_bit_identical(lib, prec, c):
+    """Store path (direct / LDS transpose), tile height and persistent grids change only
+    data movement: every variant writes the same bits, also at K = 8, 32 and 128
+    (c = 3, 5, 7: one, four and sixteen MFMA steps)."""
     ccut, pipeline = lib
     q, n = 22, 2
-    g = brickwork(q, 6, n, 6, seed=12)
+    g = brickwork(q, max(6, c), n, c, seed=12)
     run = pipeline.CutRun(q, g, n)
     run.simulate_subcircuits()
     ref = None
