@@ -333,19 +333,28 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
     return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_FP32, stream);
   });
   int best_epi = plan->merge_epilogue, best_grid = plan->merge_grid_cap;
-  const int grids[4] = {0, 512, 1024, 2048};
-  for (int epi = 0; epi < 4 && !rc; ++epi) {
-    for (int gc : grids) {
-      plan->merge_epilogue = epi;
-      plan->merge_grid_cap = gc;
+  // Merges are short and their clocks drift while the device heats up: every candidate
+  // is timed in a forward and a backward sweep (median of at least 7 runs each) and
+  // keeps the better of its two medians.
+  std::vector<std::array<int, 2>> cands;
+  for (int epi = 0; epi < 4; ++epi)
+    for (int gc : {0, 512, 1024, 2048}) cands.push_back({epi, gc});
+  std::vector<float> tbest(cands.size(), 1e30f);
+  const int mreps = std::max(reps, 7);
+  for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
+    for (size_t j = 0; j < cands.size() && !rc; ++j) {
+      const size_t i = sweep == 0 ? j : cands.size() - 1 - j;
+      plan->merge_epilogue = cands[i][0];
+      plan->merge_grid_cap = cands[i][1];
       float t = 0.f;
-      rc = time_call(s, reps, &t, [&]() {
+      rc = time_call(s, mreps, &t, [&]() {
         return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_FP16X2, stream);
       });
-      if (rc) break;
-      if (t < tmf) { tmf = t; best_epi = epi; best_grid = gc; }
+      if (!rc) tbest[i] = std::min(tbest[i], t);
     }
   }
+  for (size_t i = 0; i < cands.size() && !rc; ++i)
+    if (tbest[i] < tmf) { tmf = tbest[i]; best_epi = cands[i][0]; best_grid = cands[i][1]; }
   plan->merge_epilogue = best_epi;
   plan->merge_grid_cap = best_grid;
   plan->sim_per_variant = saved_pv;
@@ -388,7 +397,7 @@ extern "C" int ccut_autotune_load(const char* path) {
     if (line[0] == '#') continue;
     if (std::sscanf(line, "%1023s %d %d %d %d %d %d %d", key, &t, &c, &k, &ep, &mg, &bb, &pf) == 8 &&
         (t == 256 || t == 512 || t == 1024) && c >= 0 && k >= -1 && ep >= 0 && ep <= 3 && mg >= 0 &&
-        (bb == 0 || (bb > 4 && bb <= PASS_MAX_B)) && pf >= -1 && pf <= 1)
+        (bb == 0 || (bb > 4 && bb <= PASS_MAX_B)) && pf >= -1 && pf <= 1 + CCUT_MAX_CUTS_PER_SEG)
       g_tune[key] = TuneEntry{t, c, k, ep, mg, bb, pf};
   }
   std::fclose(f);

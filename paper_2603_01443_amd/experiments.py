@@ -8,6 +8,7 @@
     python -m paper_2603_01443_amd.experiments paper      --out results/paper_family.json
     python -m paper_2603_01443_amd.experiments expectation --out results/expectation.json
     python -m paper_2603_01443_amd.experiments rank4      --out results/rank4_cuts.json
+    python -m paper_2603_01443_amd.experiments headline   --out results/headline_q28.json
 
 sweep      Random brickwork, q = 24 in two blocks of 12, d in {10, 20, 40},
            c_total in {0, 1, 2, 3, 4, 6} (extended by 2 up to --cmax while cutting
@@ -45,6 +46,11 @@ rank4      Schmidt-rank-4 cuts (Eq. schmidt): random brickwork, two segments,
            d = 20, q = 24 and 28, with SWAP or a fused RXX RYY RZZ run on the
            boundary (1..6 cuts, K = 4^c) beside CZ (2..12 cuts, K = 2^c): the
            stage times, Delta against the uncut run and 1 - F.
+headline   The bench workload across depths and seeds: q = 28 (14 + 14), c_total = 6
+           (K = 64), d in {10, 20, 40}, seeds {0, 1, 2}; autotuned once per depth;
+           T_pre, T_sub, T_merge, T_orig, the speedup, amplitudes per second of the
+           device pipeline and of the merge alone, 1 - F and max-abs against the
+           uncut state.
 
 Timings: host wall clock for T_pre (cut_plan); HIP events on the stream for the
 device stages; warm-up runs first, then the mean of the timed repeats.
@@ -452,6 +458,41 @@ def run_gemm(args):
 
 
 
+# ------------------------------------------------------------------ headline workload
+def run_headline(args):
+    """q = 28 two-way cut with K = 64 at d = 10, 20, 40 and seeds 0, 1, 2."""
+    q, n, c = 28, 2, 6
+    sizes = equal_blocks(q, n)
+    bufs = Buffers()
+    s = torch.cuda.current_stream()
+    out = {"experiment": "headline workload across depths and seeds", "q": q, "n": n, "c_total": c,
+           "K": 2 ** c, "rows": []}
+    for d in (10, 20, 40):
+        for seed in (0, 1, 2):
+            g = brickwork(q, d, n, c, seed)
+            if seed == 0:   # later plans of this shape start from the tuned configuration
+                plan = ccut.cut_plan(q, ccut.gate_array(g), n, sizes)
+                arena = bufs.get("arena", plan.info()["arena_bytes"])
+                psi = bufs.get("psi", 8 << q)
+                ccut.autotune(plan, arena, psi, reps=3, arena_bytes=arena.numel(), psi_bytes=psi.numel(), stream=s)
+                tuned = {"launch": ccut.plan_get_launch(plan), "merge": ccut.plan_get_merge(plan),
+                         "prefix_sharing": ccut.plan_get_prefix_sharing(plan),
+                         "prefix_start": ccut.plan_get_prefix_start(plan),
+                         "block_bits": ccut.plan_get_block_bits(plan)}
+                del plan
+            pre, sub, mer, _ = time_cut(q, g, n, sizes, bufs, warm=2, reps=args.reps)
+            t_orig = time_uncut(q, g, bufs, reps=max(1, args.reps // 2))
+            st = ccut.norm_fidelity(c64(bufs.psi, q), c64(bufs.ref, q), q, stream=s)
+            row = {"d": d, "seed": seed, "T_pre": pre, "T_sub": sub, "T_merge": mer, "T_orig": t_orig,
+                   "speedup_device": t_orig / (sub + mer), "amps_per_s_device": (1 << q) / (sub + mer),
+                   "merge_amps_per_s": (1 << q) / mer, "one_minus_F": 1.0 - st["fidelity"],
+                   "max_abs": st["max_abs"], "norm_drift": abs(st["norm2"] - 1.0), "tuned": tuned}
+            out["rows"].append(row)
+            log(f"headline d={d} seed={seed}: pre {pre*1e3:.3f} sub {sub*1e3:.3f} merge {mer*1e3:.3f} ms, "
+                f"uncut {t_orig*1e3:.1f} ms ({row['speedup_device']:.0f}x), 1-F {row['one_minus_F']:.2e}")
+    return out
+
+
 # ------------------------------------------------------------------ paper family
 def svm_boundary(rows):
     """Weighted linear SVM on the sign of Delta over the (q, c_total) plane (the paper
@@ -692,7 +733,8 @@ def run_expectation(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["sweep", "precision", "batching", "costmodel", "gemm", "paper", "expectation", "rank4"])
+    ap.add_argument("which", choices=["sweep", "precision", "batching", "costmodel", "gemm", "paper", "expectation",
+                                      "rank4", "headline"])
     ap.add_argument("--out", required=True)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--epochs", type=int, default=3000)
@@ -706,7 +748,7 @@ def main():
         raise SystemExit("experiments need a GPU")
     fn = {"sweep": run_sweep, "precision": run_precision, "batching": run_batching, "costmodel": run_costmodel,
           "gemm": run_gemm, "paper": run_paper, "expectation": run_expectation,
-          "rank4": run_rank4}
+          "rank4": run_rank4, "headline": run_headline}
     res = fn[args.which](args)
     res["device"] = torch.cuda.get_device_name(0)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)

@@ -453,3 +453,53 @@ def test_bench_config_split_precision(lib):
               f"{1 - st['fidelity']:.3e}", flush=True)
         assert np.max(np.abs(got - want)) < split_tol(q, prec)
         assert 1 - st["fidelity"] <= 1e-6
+
+
+def absolute_term_sums(xs, sizes, cuts, states):
+    """T[x] = sum over the combinations m of |alpha_m| prod_i |psi_i^(m)[x_i]|: the bound on
+    every sum the merge forms for amplitude x, before cancellation."""
+    n = len(sizes)
+    off = cutting.segment_offsets(sizes)
+    adj = [cutting.adjacent_cuts(cuts, i) for i in range(n)]
+    combos = list(cutting.combinations(cuts))
+    weights = [abs(cutting.alpha(m, cuts)) for m in combos]
+    out = np.zeros(len(xs))
+    for t, x in enumerate(xs):
+        local = [(int(x) >> off[i]) & ((1 << sizes[i]) - 1) for i in range(n)]
+        for m, w in zip(combos, weights):
+            term = w
+            for i in range(n):
+                term *= abs(states[(i, tuple(m[j] for j in adj[i]))][local[i]])
+            out[t] += term
+    return out
+
+
+@pytest.mark.parametrize("d", [10, 40])
+def test_fp16x2_error_follows_the_term_sum(lib, d):
+    """fp16x2 rounds each weighted low-segment value once to float16 (relative error at
+    most 2^-11) and keeps the high-segment values to ~2^-22, so the error of amplitude x
+    is at most 2^-11 T[x] plus float32 accumulation; the bar 2^-10 T[x] + 1e-4 2^{-q/2}
+    also holds for shallow circuits, whose amplitudes are far from uniform in size (the
+    bound 1e-2 2^{-q/2} assumes scrambled states and is not used here)."""
+    ccut, pipeline = lib
+    q, n, c = 28, 2, 6
+    sizes = [14, 14]
+    g = brickwork(q, d, n, c, seed=1)
+    run = pipeline.CutRun(q, g, n)
+    psi = run.run("fp16x2")
+    ocuts = cutting.find_cuts(q, g, sizes)
+    ostates = cutting.variant_states(q, g, sizes, ocuts)
+    rng = np.random.default_rng(d)
+    xs = sorted(set(int(x) for x in rng.integers(0, 2 ** q, size=400)))
+    want = cutting.amplitudes(xs, sizes, ocuts, ostates)
+    tsum = absolute_term_sums(xs, sizes, ocuts, ostates)
+    got = to_np(psi[torch.tensor(xs, device=psi.device)])
+    err = np.abs(got - want)
+    ratio = np.max(err / (2.0 ** -10 * tsum + 1e-4 * 2 ** (-q / 2)))
+    ref = pipeline.uncut(q, g)
+    st = ccut.norm_fidelity(psi, ref, q)
+    print(f"q28 d{d} fp16x2: sampled max-abs {err.max():.3e}, max err / bar {ratio:.3f}, "
+          f"max |amp| / 2^(-q/2) {np.max(np.abs(want)) * 2 ** (q / 2):.1f}, "
+          f"1-F vs uncut {1 - st['fidelity']:.3e}", flush=True)
+    assert ratio <= 1.0
+    assert 1 - st["fidelity"] <= 1e-6

@@ -86,6 +86,22 @@ def test_autotune_keeps_results_and_caches(lib, tmp_path):
     ccut.autotune_load(path)
     fresh = ccut.cut_plan(q, g, n)                 # same shape: starts from the cached entry
     assert ccut.plan_get_launch(fresh) == {**cfg, "per_variant": 0}
+    assert ccut.plan_get_prefix_sharing(fresh) == ccut.plan_get_prefix_sharing(run.plan)
+    assert ccut.plan_get_prefix_start(fresh) == ccut.plan_get_prefix_start(run.plan)
+    # every saved line must load back: rewrite the entry with other threads and a tree
+    # from level 5 (prefix field 6) and check that a fresh plan takes both
+    lines = [ln.split() for ln in open(path) if not ln.startswith("#")]
+    assert len(lines) == 1 and len(lines[0]) == 8
+    key, fields = lines[0][0], lines[0][1:]
+    fields[0] = "256" if fields[0] != "256" else "1024"
+    fields[6] = "6"
+    edited = str(tmp_path / "edited.txt")
+    with open(edited, "w") as f:
+        f.write(key + " " + " ".join(fields) + "\n")
+    ccut.autotune_load(edited)
+    fresh = ccut.cut_plan(q, g, n)
+    assert ccut.plan_get_launch(fresh)["threads"] == int(fields[0])
+    assert ccut.plan_get_prefix_sharing(fresh) and ccut.plan_get_prefix_start(fresh) == 5
 
 
 @pytest.mark.parametrize("prec,c", [("bf16x3", 6), ("fp16x3", 6), ("bf16", 6), ("fp16x2", 6),
