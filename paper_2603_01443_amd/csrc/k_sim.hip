@@ -243,15 +243,24 @@ __device__ __forceinline__ void run_stage_ops(float2 (&a)[R], const int (&idx)[R
 #pragma unroll
         for (int e = 0; e < R; ++e) a[e] = cmul(((idx[e] >> jb) & 1) ? d1 : d0, a[e]);
       } else if (type == KOP_CZL) {
+        // terms outside, amplitudes inside: each (shift, mask) pair is read once, not
+        // once per amplitude (a scalar load and its wait each time); popcounts are
+        // summed (only the parity is used), which folds into the count instruction
         const uint32_t* t = reinterpret_cast<const uint32_t*>(k->m);
-        const int nt = h.nterms;
+        uint32_t par[R];
 #pragma unroll
-        for (int e = 0; e < R; ++e) {
-          const uint32_t i = (uint32_t)idx[e];
-          uint32_t par = 0;
-          for (int q = 0; q < nt; ++q) par ^= __popc(i & (i >> t[2 * q]) & t[2 * q + 1]);
-          if (par & 1) a[e] = make_float2(-a[e].x, -a[e].y);
+        for (int e = 0; e < R; ++e) par[e] = 0;
+        for (int q = 0; q < h.nterms; ++q) {
+          const uint32_t sh = t[2 * q], mk = t[2 * q + 1];
+#pragma unroll
+          for (int e = 0; e < R; ++e) {
+            const uint32_t i = (uint32_t)idx[e];
+            par[e] += __popc(i & (i >> sh) & mk);
+          }
         }
+#pragma unroll
+        for (int e = 0; e < R; ++e)
+          if (par[e] & 1) a[e] = make_float2(-a[e].x, -a[e].y);
       } else if (type == KOP_SCALAR) {
         const bool bit = (blockbase >> h.a) & 1;
         const float2 ph = bit ? make_float2(m[6], m[7]) : make_float2(m[0], m[1]);
