@@ -170,6 +170,36 @@ typedef struct ccut_cut_info {
 int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gates, int32_t n_seg,
                   const int32_t* seg_sizes, ccut_plan_t** plan_out);
 
+/*
+ * Seeded input circuits (host-only; input data, not part of the method).
+ *
+ * ccut_brickwork: the random brickwork of the problem statement (Sec. IV: q
+ * qubits, depth d, n contiguous segments, c_b cuts on boundary b).  Layer l
+ * (0-based) applies RYRZ(theta, phi) to every qubit, then CZ(i, i + 1) for
+ * i = l mod 2, l mod 2 + 2, ... except on the pairs that straddle a segment
+ * boundary; boundary b instead gets exactly c_b CZ gates, at the end of layers
+ * floor(j d / c_b), j = 0 .. c_b - 1, so c_total two-qubit gates cross the
+ * boundaries.  Angles are 2 pi u with u = (x >> 11) 2^-53 and x the SplitMix64
+ * (Steele, Lea and Flood 2014) stream of `seed`, drawn layer by layer, qubit
+ * by qubit, theta before phi.
+ *   seg_sizes: n sizes summing to q, or NULL for floor(q / n) with the
+ *     remainder on the last segments.
+ *   cuts_per_boundary: n - 1 counts summing to c_total, or NULL for an even
+ *     split with the extras on the lower boundaries.  Each c_b <= d.
+ *   out: caller-owned array of cap gates, or NULL to query the count.
+ *   *n_out: the number of gates (also when out is NULL or too small).
+ * ccut_staircase: the paper's own family (Fig. 1): H on every qubit, then
+ * `copies` CX staircases CX(i, i + 1), i = 0 .. q - 2, each CX preceded by T on
+ * its target (and, for i = 0, T on qubit 0) and followed by T on both qubits.
+ * tx_layers > 0 adds the depth padding of Sec. V.D: that many (T, X) pairs on
+ * qubit 0 before the first staircase and on qubit q - 1 after the last.
+ * Errors: CCUT_EINVAL (shape, sizes, counts, c_b > d), CCUT_ENOSPC (cap too small).
+ */
+int ccut_brickwork(int32_t q, int32_t d, int32_t n_seg, int32_t c_total, const int32_t* seg_sizes,
+                   const int32_t* cuts_per_boundary, uint64_t seed, ccut_gate_t* out, int64_t cap,
+                   int64_t* n_out);
+int ccut_staircase(int32_t q, int32_t copies, int32_t tx_layers, ccut_gate_t* out, int64_t cap, int64_t* n_out);
+
 /* Sizes and counts of a plan (host-only). */
 int ccut_plan_info(const ccut_plan_t* plan, ccut_plan_info_t* info);
 

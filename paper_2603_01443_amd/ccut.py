@@ -105,6 +105,8 @@ def _load():
         "ccut_mlp_grad": [vp, vp, vp, i64, vp, u64, vp, fp, vp],
         "ccut_mlp_train": [vp, vp, vp, i64, i32, ctypes.c_float, vp, u64, fp, vp],
         "ccut_decide": [i32, i32, i32, vp, ctypes.c_double, ctypes.c_double, ctypes.POINTER(i32), dp, vp],
+        "ccut_brickwork": [i32, i32, i32, i32, vp, vp, u64, vp, i64, ctypes.POINTER(i64)],
+        "ccut_staircase": [i32, i32, i32, vp, i64, ctypes.POINTER(i64)],
     }
     for name, args in more.items():
         fn = getattr(lib, name)
@@ -261,6 +263,30 @@ def cut_plan(q: int, gates, n_seg: int, seg_sizes: Optional[Sequence[int]] = Non
     h = ctypes.c_void_p(0)
     _check(_lib.ccut_cut_plan(q, arr.ctypes.data, len(arr), n_seg, sizes, ctypes.byref(h)))
     return Plan(h.value, q)
+
+
+def _gates_from(call) -> np.ndarray:
+    """Runs a generator entry point twice: a size query, then the fill."""
+    n = ctypes.c_int64(0)
+    _check(call(None, 0, ctypes.byref(n)))
+    arr = np.zeros(n.value, dtype=GATE_DTYPE)
+    _check(call(arr.ctypes.data if n.value else None, n.value, ctypes.byref(n)))
+    return arr
+
+
+def brickwork_gates(q: int, d: int, n_seg: int, c_total: int, seed: int,
+                    seg_sizes: Optional[Sequence[int]] = None,
+                    cuts_per_boundary: Optional[Sequence[int]] = None) -> np.ndarray:
+    """The library's seeded brickwork (ccut_brickwork) as a ccut_gate_t array."""
+    sizes = (ctypes.c_int32 * n_seg)(*seg_sizes) if seg_sizes is not None else None
+    cuts = (ctypes.c_int32 * max(1, n_seg - 1))(*cuts_per_boundary) if cuts_per_boundary is not None else None
+    return _gates_from(lambda out, cap, n: _lib.ccut_brickwork(q, d, n_seg, c_total, sizes, cuts,
+                                                               seed & 0xFFFFFFFFFFFFFFFF, out, cap, n))
+
+
+def staircase_gates(q: int, copies: int, tx_layers: int = 0) -> np.ndarray:
+    """The paper's Fig. 1 staircase family (ccut_staircase) as a ccut_gate_t array."""
+    return _gates_from(lambda out, cap, n: _lib.ccut_staircase(q, copies, tx_layers, out, cap, n))
 
 
 def plan_prepare(plan: Plan) -> None:
