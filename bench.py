@@ -49,12 +49,14 @@ def cpu_baseline(gates, sizes):
     Sample: the oracle's cut plan and all 2 * 2^6 subcircuit variants in full,
     then its merge (the plain sum over all 64 terms) restricted to the first
     R rows of the high segment, i.e. R * 2^14 of the 2^28 amplitudes; the merge
-    time is scaled by 2^14 / R to the full state.
+    time is scaled by 2^14 / R to the full state.  Beside it, the oracle's
+    uncut simulation: one single-qubit gate and one CZ applied to the 2^28
+    complex128 state, scaled by the circuit's gate counts.
     """
     import numpy as np
     from threadpoolctl import threadpool_limits
 
-    from oracle import cutting
+    from oracle import cutting, statevector
 
     rows = 128
     with threadpool_limits(limits=1):
@@ -66,7 +68,19 @@ def cpu_baseline(gates, sizes):
         trunc = {k: (v[:rows] if k[0] == 1 else v) for k, v in states.items()}
         part = cutting.merge(sizes, cuts, trunc)
         t3 = time.perf_counter()
-    assert part.shape[0] == rows << sizes[0]
+        assert part.shape[0] == rows << sizes[0]
+        del trunc, part
+        one_q = next(g for g in gates if g.q1 < 0)
+        two_q = next(g for g in gates if g.q1 >= 0)
+        psi = statevector.apply_gate(statevector.zero_state(Q), Q, one_q)   # first touch of the pages
+        t4 = time.perf_counter()
+        psi = statevector.apply_gate(psi, Q, one_q)
+        t5 = time.perf_counter()
+        psi = statevector.apply_gate(psi, Q, two_q)
+        t6 = time.perf_counter()
+        del psi
+    n_two = sum(1 for g in gates if g.q1 >= 0)
+    t_orig = (len(gates) - n_two) * (t5 - t4) + n_two * (t6 - t5)
     t_pre, t_sub, t_merge_s = t1 - t0, t2 - t1, t3 - t2
     t_merge = t_merge_s * ((1 << sizes[1]) / rows)
     t_cut = t_pre + t_sub + t_merge
@@ -77,7 +91,11 @@ def cpu_baseline(gates, sizes):
                    f"({rows << sizes[0]} amplitudes), scaled by {(1 << sizes[1]) // rows}; "
                    f"complex128 numpy, BLAS limited to 1 thread"),
         "seconds": {"pre": t_pre, "sub": t_sub, "merge_sample": t_merge_s, "merge_scaled": t_merge,
-                    "cut_total_est": t_cut},
+                    "cut_total_est": t_cut, "uncut_one_qubit_gate": t5 - t4, "uncut_cz_gate": t6 - t5,
+                    "uncut_est": t_orig},
+        "uncut_sample": (f"oracle uncut simulation (complex128, gate by gate): one single-qubit gate and "
+                         f"one CZ on the 2^{Q} state, scaled to the circuit's {len(gates) - n_two} "
+                         f"single-qubit and {n_two} two-qubit gates"),
     }, cuts, states
 
 
@@ -306,8 +324,8 @@ def main():
         got = psi[torch.tensor(xs, device=dev)].cpu().numpy().astype(np.complex128)
         result["oracle_sampled_max_abs"] = float(np.max(np.abs(got - want)))
         result["oracle_sampled_n"] = len(xs)
-        log(f"bench: cpu oracle {cb['value']:.3e} amps/s; sampled max-abs vs oracle "
-            f"{result['oracle_sampled_max_abs']:.3e}")
+        log(f"bench: cpu oracle {cb['value']:.3e} amps/s (uncut estimate {cb['seconds']['uncut_est']:.0f} s); "
+            f"sampled max-abs vs oracle {result['oracle_sampled_max_abs']:.3e}")
     print(json.dumps(result))
 
 
