@@ -111,7 +111,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of "
-              "the merge is a design, not part of this build", file=sys.stderr)
+              "the merge is described in the design notes but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -58,7 +58,7 @@ extern "C" {
 #define CCUT_ENOSPC (-3)        /* a caller buffer is smaller than required */
 #define CCUT_ENOMEM (-4)        /* host or device allocation failed */
 #define CCUT_EHIP (-5)          /* a HIP runtime call failed */
-#define CCUT_EUNSUPPORTED (-6)  /* valid request this build does not implement */
+#define CCUT_EUNSUPPORTED (-6)  /* valid request this library does not implement */
 
 /* ------------------------------------------------------------------ gates */
 enum {
