@@ -190,7 +190,10 @@ def _stream(s) -> int:
 
 
 def gate_array(gates: Iterable) -> np.ndarray:
-    """Packs (kind, q0, q1, p0, p1) tuples into the 32-byte ccut_gate_t layout."""
+    """Packs (kind, q0, q1, p0, p1) tuples into the 32-byte ccut_gate_t layout (an array
+    already in that layout is returned as a contiguous copy)."""
+    if isinstance(gates, np.ndarray) and gates.dtype == GATE_DTYPE:
+        return np.ascontiguousarray(gates).copy()
     gates = list(gates)
     arr = np.zeros(len(gates), dtype=GATE_DTYPE)
     for i, g in enumerate(gates):

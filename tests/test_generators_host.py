@@ -68,3 +68,10 @@ def test_generator_errors():
     assert rc == 0 and n.value == 3                       # 2 rotations and CZ(0, 1) on layer 0
     rc = ccut._lib.ccut_brickwork(4, 2, 1, 0, None, None, 0, buf.ctypes.data, len(buf), ctypes.byref(n))
     assert rc == ccut.ENOSPC and n.value == len(ccut.brickwork_gates(4, 2, 1, 0, 0))
+
+
+def test_gate_array_keeps_packed_input():
+    """A ccut_gate_t array passes through gate_array unchanged (no field shift)."""
+    g = ccut.brickwork_gates(10, 4, 2, 2, 3)
+    again = ccut.gate_array(g)
+    assert again.tobytes() == g.tobytes() and again is not g

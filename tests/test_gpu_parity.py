@@ -503,3 +503,14 @@ def test_fp16x2_error_follows_the_term_sum(lib, d):
           f"1-F vs uncut {1 - st['fidelity']:.3e}", flush=True)
     assert ratio <= 1.0
     assert 1 - st["fidelity"] <= 1e-6
+
+
+def test_library_generator_feeds_the_pipeline(lib):
+    """Gates from the library's own generator (ccut_brickwork) run through the cut
+    pipeline and give the oracle's state."""
+    ccut, pipeline = lib
+    q, d, n, c = 16, 8, 2, 4
+    g = ccut.brickwork_gates(q, d, n, c, 9)
+    psi = to_np(pipeline.CutRun(q, g, n).run("fp32"))
+    ref = statevector.simulate(q, brickwork(q, d, n, c, 9))
+    assert metrics.max_abs_error(ref, psi) <= 1e-4 * 2 ** (-q / 2)

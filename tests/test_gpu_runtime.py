@@ -124,3 +124,39 @@ def test_merge_gemm_variants_bit_identical(lib, prec, c):
             if ref is None:
                 ref = out
             assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref)), (variant, cap)
+
+
+def test_kernel_timing_families_and_mask(lib):
+    """Kernel timing: one cut pipeline records its kernel families (one split launch for
+    the one GEMM merge stage), the mask restricts timing to the named families, and a
+    reset clears the totals."""
+    ccut, pipeline = lib
+    q, n = 20, 2
+    run = pipeline.CutRun(q, brickwork(q, 8, n, 6, seed=4), n)
+    run.run("fp16x2")                         # tables staged, clocks up
+    torch.cuda.synchronize()
+    ccut.profile_reset()
+    ccut.profile_mask(None)
+    ccut.profile_enable(True)
+    try:
+        run.simulate_subcircuits()
+        run.merge("fp16x2")
+        torch.cuda.synchronize()
+        prof = ccut.profile_read()
+        assert set(prof) == set(ccut.PROFILE_KERNELS)
+        assert prof["sim"][0] >= 1 and prof["sim"][1] > 0
+        assert prof["split"][0] == 1 and prof["merge_gemm"][0] == 1
+        assert prof["merge_f32"][0] == 0 and prof["reduce"][0] == 0
+        ccut.profile_reset()
+        ccut.profile_mask(["merge_gemm"])
+        run.simulate_subcircuits()
+        run.merge("fp16x2")
+        torch.cuda.synchronize()
+        prof = ccut.profile_read()
+        assert prof["merge_gemm"][0] == 1 and prof["merge_gemm"][1] > 0
+        assert all(v[0] == 0 for k, v in prof.items() if k != "merge_gemm")
+        ccut.profile_reset()
+        assert all(v == (0, 0.0) for v in ccut.profile_read().values())
+    finally:
+        ccut.profile_enable(False)
+        ccut.profile_mask(None)
