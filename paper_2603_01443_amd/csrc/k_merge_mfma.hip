@@ -214,28 +214,74 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.f;
 
-    for (int s = 0; s < S; ++s) {
-      uint4 a_hi[RBW], a_lo[RBW], b_hi[4], b_lo[4];
+    if constexpr (RBW == 2) {
+      // 128-row tiles (128 accumulator registers: few wavefronts per SIMD, so each must
+      // hide its own load latency): two operand buffers filled alternately, so the
+      // loads of step s + 1 are in flight while the MFMAs of step s run; the scheduler
+      // barriers keep the compiler from sinking them below those MFMAs, and no register
+      // copies tie them to the current step.  Measured: q = 30, K = 256 merges
+      // 6.4 -> 4.6 ms.  The 64-row tiles rely on four wavefronts per SIMD instead; the
+      // second buffer would cost them that occupancy.
+      struct Frag {
+        uint4 a_hi[RBW], a_lo[RBW], b_hi[4], b_lo[4];
+      };
+      auto load = [&](Frag& f, int st) {
 #pragma unroll
-      for (int r = 0; r < RBW; ++r) {
-        a_hi[r] = lh[r * lstep + s * 64];
-        if (L_SPLIT) a_lo[r] = ll[r * lstep + s * 64];
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        b_hi[c] = rh[c * lstep + s * 64];
-        if (R_SPLIT) b_lo[c] = rl[c * lstep + s * 64];
-      }
-#pragma unroll
-      for (int r = 0; r < RBW; ++r)
+        for (int r = 0; r < RBW; ++r) {
+          f.a_hi[r] = lh[r * lstep + st * 64];
+          if (L_SPLIT) f.a_lo[r] = ll[r * lstep + st * 64];
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          if (L_SPLIT) acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
-          if (R_SPLIT) acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
-          acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
+          f.b_hi[c] = rh[c * lstep + st * 64];
+          if (R_SPLIT) f.b_lo[c] = rl[c * lstep + st * 64];
         }
+      };
+      auto mma = [&](const Frag& f) {
+#pragma unroll
+        for (int r = 0; r < RBW; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (L_SPLIT) acc[r][c] = mfma<MODE>(f.a_lo[r], f.b_hi[c], acc[r][c]);
+            if (R_SPLIT) acc[r][c] = mfma<MODE>(f.a_hi[r], f.b_lo[c], acc[r][c]);
+            acc[r][c] = mfma<MODE>(f.a_hi[r], f.b_hi[c], acc[r][c]);
+          }
+      };
+      Frag fa, fb;
+      load(fa, 0);
+      int s = 0;
+      for (; s + 1 < S; s += 2) {
+        load(fb, s + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(fa);
+        load(fa, s + 2 < S ? s + 2 : s + 1);  // past the end: reload step s + 1 (unused)
+        __builtin_amdgcn_sched_barrier(0);
+        mma(fb);
+      }
+      if (s < S) mma(fa);  // odd S: the last step
+    } else {
+      for (int s = 0; s < S; ++s) {
+        uint4 a_hi[RBW], a_lo[RBW], b_hi[4], b_lo[4];
+#pragma unroll
+        for (int r = 0; r < RBW; ++r) {
+          a_hi[r] = lh[r * lstep + s * 64];
+          if (L_SPLIT) a_lo[r] = ll[r * lstep + s * 64];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          b_hi[c] = rh[c * lstep + s * 64];
+          if (R_SPLIT) b_lo[c] = rl[c * lstep + s * 64];
+        }
+#pragma unroll
+        for (int r = 0; r < RBW; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (L_SPLIT) acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
+            if (R_SPLIT) acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
+            acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
+          }
+      }
     }
-
     if (EPI == 0) {
 #pragma unroll
       for (int r = 0; r < RBW; ++r)
