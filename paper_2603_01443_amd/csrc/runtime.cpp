@@ -56,13 +56,19 @@ std::string signature(const ccut_plan* P) {
   return s;
 }
 
-int time_call(hipStream_t s, int reps, float* ms_out, const std::function<int()>& fn) {
+// Median device time of `reps` calls of fn (after one warm-up call).  `pre`, when
+// given, runs untimed before every call of fn, so that fn is timed in the state the
+// pipeline leaves it in (a merge right after the simulation that feeds it).
+int time_call(hipStream_t s, int reps, float* ms_out, const std::function<int()>& fn,
+              const std::function<int()>& pre = nullptr) {
   hipEvent_t a, b;
   CCUT_HIP(hipEventCreate(&a));
   CCUT_HIP(hipEventCreate(&b));
-  int rc = fn();  // warm-up
+  int rc = pre ? pre() : 0;
+  if (rc == 0) rc = fn();  // warm-up
   std::vector<float> t;
   for (int r = 0; r < reps && rc == 0; ++r) {
+    if (pre && (rc = pre()) != 0) break;
     (void)hipEventRecord(a, s);
     rc = fn();
     (void)hipEventRecord(b, s);
@@ -329,9 +335,13 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   // merge: float32 vector kernel against the split MFMA kernel (the CCUT_PREC_AUTO mode) at this
   // plan's term counts, over the GEMM variants and grids
   float t32 = 0.f, tmf = 1e30f;
-  int rc = time_call(s, reps, &t32, [&]() {
-    return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_FP32, stream);
-  });
+  // every merge is timed right after a simulation, as the pipeline runs it: back to back
+  // merges see the previous merge's writes still draining and rank the variants differently
+  auto sim = [&]() { return ccut_simulate_subcircuits(plan, d_arena, arena_bytes, stream); };
+  int rc = time_call(
+      s, reps, &t32,
+      [&]() { return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_FP32, stream); },
+      sim);
   int best_epi = plan->merge_epilogue, best_grid = plan->merge_grid_cap;
   // Merges are short and their clocks drift while the device heats up: every candidate
   // is timed in a forward and a backward sweep (median of at least 7 runs each) and
@@ -347,9 +357,12 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
       plan->merge_epilogue = cands[i][0];
       plan->merge_grid_cap = cands[i][1];
       float t = 0.f;
-      rc = time_call(s, mreps, &t, [&]() {
-        return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_FP16X2, stream);
-      });
+      rc = time_call(
+          s, mreps, &t,
+          [&]() {
+            return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_FP16X2, stream);
+          },
+          sim);
       if (!rc) tbest[i] = std::min(tbest[i], t);
     }
   }
