@@ -43,6 +43,7 @@ namespace ccut {
 namespace {
 
 constexpr int TAB = 128;  // offset-table entries per half (local bits 0..6 / 7..13)
+constexpr int IO_BATCH = 2;  // amplitudes per thread in flight when a block is loaded (4 costs occupancy)
 constexpr int R = 1 << REG_BITS;
 
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
@@ -382,9 +383,26 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
       __syncthreads();
       if (tid == 0 && blockbase == 0) sh[0] = make_float2(scale_in, 0.f);
     } else {
-      for (int i = tid; i < nb; i += NT) {
-        const float2 v = src[blockbase + lo_tab[i & (TAB - 1)] + hi_tab[i >> 7]];
-        sh[pad(i)] = make_float2(v.x * scale_in, v.y * scale_in);
+      // IO_BATCH amplitudes per thread at a time: their offsets are read from the
+      // tables first, then all their loads are issued, then they are written to LDS
+      // (one at a time, every table read waits behind the previous LDS write and every
+      // load for its table reads: one L2 or HBM latency per amplitude)
+      for (int i0 = tid; i0 < nb; i0 += IO_BATCH * NT) {
+        uint64_t off[IO_BATCH];
+        float2 v[IO_BATCH];
+#pragma unroll
+        for (int u = 0; u < IO_BATCH; ++u) {
+          const int i = i0 + u * NT;
+          off[u] = i < nb ? lo_tab[i & (TAB - 1)] + hi_tab[i >> 7] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < IO_BATCH; ++u)
+          if (i0 + u * NT < nb) v[u] = src[blockbase + off[u]];
+#pragma unroll
+        for (int u = 0; u < IO_BATCH; ++u) {
+          const int i = i0 + u * NT;
+          if (i < nb) sh[pad(i)] = make_float2(v[u].x * scale_in, v[u].y * scale_in);
+        }
       }
     }
     __syncthreads();
