@@ -77,10 +77,24 @@ typedef __attribute__((ext_vector_type(2))) _Float16 f16x2;
 
 // hi = float16(x), lo = float16(x - hi) for a pair, both rounded to nearest
 // (v_cvt_pk_f16_f32: unbiased, so rounding errors do not drift the norm).
+// x - f32(half h) as one mixed-precision fma (h the low or high float16 of hp); exact,
+// since x - round16(x) is representable in float32.  The compiler does not form
+// v_fma_mix itself while float32 denormals are kept, so it is written out here.
+__device__ __forceinline__ float sub_half_lo(uint32_t hp, float x) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(hp), "v"(-1.0f), "v"(x));
+  return r;
+}
+__device__ __forceinline__ float sub_half_hi(uint32_t hp, float x) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(hp), "v"(-1.0f), "v"(x));
+  return r;
+}
+
 __device__ __forceinline__ void split_pair(float x0, float x1, uint32_t& hi, uint32_t& lo) {
   const f16x2 h = {(_Float16)x0, (_Float16)x1};
-  const f16x2 l = {(_Float16)(x0 - (float)h[0]), (_Float16)(x1 - (float)h[1])};
   hi = __builtin_bit_cast(uint32_t, h);
+  const f16x2 l = {(_Float16)sub_half_lo(hi, x0), (_Float16)sub_half_hi(hi, x1)};
   lo = __builtin_bit_cast(uint32_t, l);
 }
 
