@@ -273,9 +273,13 @@ __device__ __forceinline__ void run_stage_ops(float2 (&a)[R], const int (&idx)[R
             par[e] += __popc(i & (i >> sh) & mk);
           }
         }
+        // negate on odd parity: bit 0 of the count shifted into both sign bits
 #pragma unroll
-        for (int e = 0; e < R; ++e)
-          if (par[e] & 1) a[e] = make_float2(-a[e].x, -a[e].y);
+        for (int e = 0; e < R; ++e) {
+          const uint32_t sgn = par[e] << 31;
+          a[e].x = __uint_as_float(__float_as_uint(a[e].x) ^ sgn);
+          a[e].y = __uint_as_float(__float_as_uint(a[e].y) ^ sgn);
+        }
       } else if (type == KOP_SCALAR) {
         const bool bit = (blockbase >> h.a) & 1;
         const float2 ph = bit ? make_float2(m[6], m[7]) : make_float2(m[0], m[1]);
