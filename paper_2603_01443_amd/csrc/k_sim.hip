@@ -152,10 +152,10 @@ __device__ __forceinline__ void group_mfma(float2 (&a)[R], const uint4* __restri
   }
 #pragma unroll
   for (int e = 0; e < R; ++e) {
-    const int vr = (e & 3) | ((e >> 3) << 2);              // row e      (real part)
-    const int vi = (e & 3) | ((2 + (e >> 3)) << 2);        // row 16 + e (imaginary part)
-    a[e].x = (e & 4) ? c1[vr] : c0[vr];
-    a[e].y = (e & 4) ? c1[vi] : c0[vi];
+    // rows 2 e (real part) and 2 e + 1 (imaginary part): registers v, v + 1 of c0 or c1
+    const int v = 2 * (e & 1) + 4 * (e >> 2);
+    a[e].x = ((e >> 1) & 1) ? c1[v] : c0[v];
+    a[e].y = ((e >> 1) & 1) ? c1[v + 1] : c0[v + 1];
   }
 }
 
@@ -500,8 +500,10 @@ __global__ __launch_bounds__(64) void k_group_tables(const KOp* __restrict__ ops
     for (int t = 0; t < 4; ++t) u[p][t] = make_float2(m[2 * t], m[2 * t + 1]);
   }
   const int m = lane & 31, h = lane >> 5;
-  const int row = m & 15;
-  const bool imag_row = m >= 16;
+  // output rows interleaved: row 2 e = Re y_e, row 2 e + 1 = Im y_e, so that each
+  // amplitude's two parts land in adjacent accumulator registers
+  const int row = m >> 1;
+  const bool imag_row = m & 1;
   uint32_t hi[2][4], lo[2][4];
 #pragma unroll
   for (int e = 0; e < 8; e += 2) {
@@ -516,7 +518,7 @@ __global__ __launch_bounds__(64) void k_group_tables(const KOp* __restrict__ ops
         const float2 f = rb ? (cb ? u[p][3] : u[p][2]) : (cb ? u[p][1] : u[p][0]);
         gv = cmul(gv, f);
       }
-      // rows 0..15: Re y = Re G Re x - Im G Im x;  rows 16..31: Im y = Im G Re x + Re G Im x
+      // row 2 e: Re y = Re G Re x - Im G Im x;  row 2 e + 1: Im y = Im G Re x + Re G Im x
       const float s0 = imag_row ? gv.y : gv.x;
       const float s1 = imag_row ? gv.x : -gv.y;
       if (d == 0) { v0[0] = s0; v0[1] = s1; } else { v1[0] = s0; v1[1] = s1; }
