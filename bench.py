@@ -32,9 +32,15 @@ sys.path.insert(0, ROOT)
 Q, D, NSEG, CTOTAL, SEED = 28, 20, 2, 6, 0
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the merge GEMM from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by
-# a 1 GiB copy (2.0 x FETCH + 1.0 x WRITE); see profiles/.  Only valid for the kernel revision
-# it was measured on: set to None whenever that kernel changes.
-MEASURED_TRAFFIC = {"merge_gemm (fp16x2, v3)": 2.224e9}
+# a 1 GiB copy (2.0 x FETCH + 1.0 x WRITE); see profiles/.  One entry per variant the autotuner
+# may pick (mean over its grid sizes).  Only valid for the kernel revision it was measured on:
+# remove an entry whenever that kernel changes.
+MEASURED_TRAFFIC = {
+    "merge_gemm (fp16x2, v0)": 2.226e9,
+    "merge_gemm (fp16x2, v1)": 2.227e9,
+    "merge_gemm (fp16x2, v2)": 2.224e9,
+    "merge_gemm (fp16x2, v3)": 2.224e9,
+}
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 FP32_PEAK_TFLOPS = 157.3
 

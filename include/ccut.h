@@ -429,7 +429,8 @@ int ccut_plan_get_prefix_start(const ccut_plan_t* plan, int32_t* out);
  * grids (median of `reps` runs, HIP events on `stream`; every merge run follows
  * an untimed simulation, as in the pipeline, and each GEMM candidate is timed in
  * a forward and a backward sweep, median of max(reps, 7) runs each, keeping the
- * better median, since short merges see clock drift), applies the fastest
+ * better median, since short merges see clock drift; the plan's current GEMM
+ * variant and grid are kept unless another is more than 2 % faster), applies the fastest
  * to the plan and records it in a process-wide cache keyed by (architecture,
  * plan shape); later plans of the same shape start from it (their tables, and so
  * their info.arena_bytes, can be larger than the tuning plan's: size an arena

@@ -343,6 +343,7 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
       [&]() { return ccut_merge_full_state(plan, d_arena, arena_bytes, d_psi, psi_bytes, CCUT_PREC_FP32, stream); },
       sim);
   int best_epi = plan->merge_epilogue, best_grid = plan->merge_grid_cap;
+  const int saved_epi = best_epi, saved_grid = best_grid;
   // Merges are short and their clocks drift while the device heats up: every candidate
   // is timed in a forward and a backward sweep (median of at least 7 runs each) and
   // keeps the better of its two medians.
@@ -368,6 +369,14 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   }
   for (size_t i = 0; i < cands.size() && !rc; ++i)
     if (tbest[i] < tmf) { tmf = tbest[i]; best_epi = cands[i][0]; best_grid = cands[i][1]; }
+  // the plan's own choice stays unless another is clearly faster: near ties would
+  // otherwise flip with run-to-run noise
+  for (size_t i = 0; i < cands.size() && !rc; ++i)
+    if (cands[i][0] == saved_epi && cands[i][1] == saved_grid && tbest[i] <= 1.02f * tmf) {
+      tmf = tbest[i];
+      best_epi = saved_epi;
+      best_grid = saved_grid;
+    }
   plan->merge_epilogue = best_epi;
   plan->merge_grid_cap = best_grid;
   plan->sim_per_variant = saved_pv;
