@@ -124,6 +124,7 @@ static_assert(sizeof(StageDesc) == 160, "StageDesc layout");
 // the row and column index) acting on a thread's 16 amplitudes.  As a real
 // 32x32 matrix on (Re x[0..15], Im x[0..15]) it is the A operand of two
 // v_mfma_f32_32x32x16_f16 steps (k = 0..15: real parts, 16..31: imaginary).
+// Its output rows interleave the parts: row 2 e = Re y_e, row 2 e + 1 = Im y_e.
 // A table holds, per lane l (row m = l % 32, k half h = l / 32), four uint4:
 // hi and lo float16 parts of A[m][16 s + 8 h + e], e = 0..7, for s = 0, 1.
 struct GroupRef {
