@@ -514,3 +514,35 @@ def test_library_generator_feeds_the_pipeline(lib):
     psi = to_np(pipeline.CutRun(q, g, n).run("fp32"))
     ref = statevector.simulate(q, brickwork(q, d, n, c, 9))
     assert metrics.max_abs_error(ref, psi) <= 1e-4 * 2 ** (-q / 2)
+
+
+def test_q34_indices_beyond_32_bits(lib):
+    """q = 34 (17 + 17, 128 GiB output): amplitude indices above 2^32 in the merge's
+    tiles, the split operands and the reductions.  Sampled amplitudes (the highest
+    indices included) against the oracle's plain sum, and the FP64 norm of the whole
+    state."""
+    ccut, pipeline = lib
+    if torch.cuda.get_device_properties(0).total_memory < (200 << 30):
+        pytest.skip("needs a device with more than 200 GiB")
+    torch.cuda.empty_cache()                  # blocks cached by earlier tests
+    q, d, n, c = 34, 6, 2, 4
+    sizes = [17, 17]
+    g = brickwork(q, d, n, c, seed=5)
+    run = pipeline.CutRun(q, g, n)
+    psi = run.run("auto")                     # K = 16: the fp16x2 GEMM
+    stats = ccut.norm_fidelity(psi, None, q, stream=torch.cuda.current_stream())
+    ocuts = cutting.find_cuts(q, g, sizes)
+    ostates = cutting.variant_states(q, g, sizes, ocuts)
+    rng = np.random.default_rng(34)
+    top = 2 ** q - 1
+    xs = sorted(set(int(x) for x in rng.integers(0, 2 ** q, size=200))
+                | {0, 2 ** 32 - 1, 2 ** 32, 2 ** 33 + 12345, top - 1, top})
+    want = cutting.amplitudes(xs, sizes, ocuts, ostates)
+    tsum = absolute_term_sums(xs, sizes, ocuts, ostates)
+    got = to_np(psi[torch.tensor(xs, device=psi.device)])
+    ratio = np.max(np.abs(got - want) / (2.0 ** -10 * tsum + 1e-4 * 2 ** (-q / 2)))
+    print(f"q34: sampled err / bar {ratio:.3f}, norm drift {abs(stats['norm2'] - 1):.2e}", flush=True)
+    del psi, run
+    torch.cuda.empty_cache()
+    assert ratio <= 1.0
+    assert abs(stats["norm2"] - 1) < 1e-5
