@@ -75,8 +75,6 @@ __device__ __forceinline__ void swap_halves(float& x, float& y) {
 
 typedef __attribute__((ext_vector_type(2))) _Float16 f16x2;
 
-// hi = float16(x), lo = float16(x - hi) for a pair, both rounded to nearest
-// (v_cvt_pk_f16_f32: unbiased, so rounding errors do not drift the norm).
 // x - f32(half h) as one mixed-precision fma (h the low or high float16 of hp); exact,
 // since x - round16(x) is representable in float32.  The compiler does not form
 // v_fma_mix itself while float32 denormals are kept, so it is written out here.
@@ -91,6 +89,8 @@ __device__ __forceinline__ float sub_half_hi(uint32_t hp, float x) {
   return r;
 }
 
+// hi = float16(x), lo = float16(x - hi) for a pair, both rounded to nearest
+// (v_cvt_pk_f16_f32: unbiased, so rounding errors do not drift the norm).
 __device__ __forceinline__ void split_pair(float x0, float x1, uint32_t& hi, uint32_t& lo) {
   const f16x2 h = {(_Float16)x0, (_Float16)x1};
   hi = __builtin_bit_cast(uint32_t, h);
