@@ -540,13 +540,6 @@ class Graph:
     def launch(self, stream=None) -> None:
         _check(_lib.ccut_graph_launch(self._h, _stream(stream)))
 
-    def cut_terms(self, j: int) -> List[complex]:
-        """Weights of cut j's 2^{n_bits} terms (term t = its variant bits as an integer)."""
-        out = (ctypes.c_double * 8)()
-        _check(_lib.ccut_plan_cut_terms(self._h, j, out))
-        n = 1 << self.cuts()[j]["n_bits"]
-        return [complex(out[2 * t], out[2 * t + 1]) for t in range(n)]
-
     def free(self) -> None:
         if self._h and self._h.value:
             _lib.ccut_graph_free(self._h)

@@ -145,6 +145,52 @@ def test_textbook_states():
     assert np.max(np.abs(psi - 2 ** (-q / 2) * np.exp(1j * phase))) < 1e-14
 
 
+def test_ryrz_order_rz_acts_first():
+    """The workload's single-qubit gate is Ry(theta) Rz(phi): Rz acts first.
+
+    On |0>, Rz(phi) contributes only the global phase e^{-i phi/2}, so
+    Ry(theta) Rz(phi)|0> = e^{-i phi/2} (cos theta/2, sin theta/2): both amplitudes
+    share one phase.  The reversed order Rz(phi) Ry(theta)|0> would give them the
+    phases e^{-i phi/2} and e^{+i phi/2}.  The matrix is checked entry by entry
+    against its hand expansion with Qiskit's Ry(t) = [[c, -s], [s, c]] and
+    Rz(t) = diag(e^{-it/2}, e^{it/2}).
+    """
+    th, ph = 1.1, 2.3
+    c, s = math.cos(th / 2), math.sin(th / 2)
+    em, ep = complex(math.cos(ph / 2), -math.sin(ph / 2)), complex(math.cos(ph / 2), math.sin(ph / 2))
+    want = np.array([[c * em, -s * ep], [s * em, c * ep]])
+    assert np.max(np.abs(og.one_qubit_matrix("RYRZ", th, ph) - want)) < 1e-15
+    # through the simulator: single gates on |0> and on |1> (X first) of a 3-qubit register
+    q = 3
+    for pre, col in ((False, (c * em, s * em)), (True, (-s * ep, c * ep))):
+        circ = ([Gate("X", 1)] if pre else []) + [Gate("RYRZ", 1, -1, th, ph)]
+        psi = statevector.simulate(q, circ)
+        assert abs(psi[0] - col[0]) < 1e-15 and abs(psi[2] - col[1]) < 1e-15
+        assert np.max(np.abs(np.delete(psi, [0, 2]))) == 0.0
+
+
+def test_brickwork_layer_product_state_closed_form():
+    """One brickwork layer from |0^q>: RYRZ on every qubit, then CZ on the even pairs.
+
+    The RYRZ layer gives the product state prod_j e^{-i phi_j/2} (cos theta_j/2,
+    sin theta_j/2); the CZs multiply amplitude x by (-1)^{sum x_i x_{i+1}} over the
+    even pairs (i, i+1).  Angles are read from the generated gate list itself.
+    """
+    q = 6
+    g = brickwork(q, 1, 1, 0, seed=3)
+    ang = {x.q0: (x.p0, x.p1) for x in g if x.kind == "RYRZ"}
+    pairs = [(x.q0, x.q1) for x in g if x.kind == "CZ"]
+    assert sorted(pairs) == [(0, 1), (2, 3), (4, 5)]
+    x = np.arange(1 << q)
+    want = np.ones(1 << q, dtype=np.complex128)
+    for j, (th, ph) in ang.items():
+        b = (x >> j) & 1
+        want *= np.exp(-0.5j * ph) * np.where(b == 1, math.sin(th / 2), math.cos(th / 2))
+    for a, b in pairs:
+        want *= (-1.0) ** (((x >> a) & 1) * ((x >> b) & 1))
+    assert np.max(np.abs(statevector.simulate(q, g) - want)) < 1e-14
+
+
 def test_graph_state_closed_form():
     q = 8
     edges = [(0, 1), (1, 2), (2, 5), (3, 7), (4, 6), (0, 7), (5, 6)]

@@ -104,3 +104,38 @@ def test_mlp_training_reduces_loss():
     t = np.stack([x[:, 0] + 0.5 * x[:, 1], np.sin(x[:, 2]), x[:, 3] ** 2], axis=1)
     _, hist = mlp.train(glorot_params(3), x, t, epochs=300, lr=1e-2)
     assert hist[-1] < 0.2 * hist[0]
+
+
+def test_closed_form_choice_takes_the_largest_margin():
+    """Fallback rule: among admissible n, the largest Eq. (speedup_depth_free) margin.
+
+    Worked by hand at q = 24, c_total = 4 (cuts split evenly, extras low):
+      n = 2: cuts [4], N_sub = 2^4 + 2^4 = 32, margin 24/2 - log2(32/2) = 8;
+      n = 3: cuts [2, 2], N_sub = 4 + 16 + 4 = 24, margin 16 - log2(24/3) = 13;
+      n = 4: cuts [2, 1, 1], N_sub = 4 + 8 + 4 + 2 = 18, margin 18 - log2(18/4) = 15.83.
+    All three are admissible and distinct, so the order in which candidates are
+    listed must not matter: the answer is the n with margin 15.83, or 13 when n = 4
+    is not offered.
+    """
+    assert threshold.speedup_margin(24, 2, 32) == 8.0
+    assert threshold.speedup_margin(24, 3, 24) == 13.0
+    assert abs(threshold.speedup_margin(24, 4, 18) - (18 - math.log2(4.5))) < 1e-12
+    assert threshold.n_sub_from_cuts([2, 1, 1]) == 18
+    assert threshold.closed_form_choice(24, 4, (2, 3, 4)) == 4
+    assert threshold.closed_form_choice(24, 4, (4, 3, 2)) == 4
+    assert threshold.closed_form_choice(24, 4, (2, 3)) == 3
+    assert threshold.closed_form_choice(24, 4, (3, 2)) == 3
+    assert threshold.closed_form_choice(24, 4, (2,)) == 2
+
+
+def test_closed_form_choice_strict_condition():
+    """Eq. (speedup_depth_free) is strict: a zero margin is not a speedup.
+
+    q = 8, n = 2, c_total = 4: N_sub/2 = 16 = 2^{8/2}, margin exactly 0, so no cut;
+    c_total = 3 gives margin 1 and cuts.  A c_total far above every threshold
+    (q = 10, c_total = 40) leaves no admissible n at all.
+    """
+    assert threshold.speedup_margin(8, 2, threshold.n_sub_equal(4, 2)) == 0.0
+    assert threshold.closed_form_choice(8, 4, (2,)) == 0
+    assert threshold.closed_form_choice(8, 3, (2,)) == 2
+    assert threshold.closed_form_choice(10, 40) == 0
