@@ -299,6 +299,25 @@ int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, vo
 int ccut_norm_fidelity(const void* d_psi, const void* d_ref, int32_t q, double out[5], void* stream);
 
 /*
+ * Allocation-free variant of ccut_norm_fidelity, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same kernels and the same five results
+ * in the same order as ccut_norm_fidelity, written to DEVICE memory d_out
+ * (5 doubles, caller-owned, 8-byte aligned) instead of host memory.  The call
+ * enqueues on `stream` and returns without synchronising or copying
+ * to the host.  It calls no hipMalloc/hipFree: the per-block partials live in
+ * a fixed device array of 1024 x 5 doubles (40 KiB) inside the library, one
+ * copy per device, held until the process ends and looked up on the first call
+ * on each device.  That covers every q <= CCUT_MAX_Q; larger q is rejected
+ * with CCUT_EINVAL.  The array keeps the last call's partials; every partial a
+ * call reads is written by that same call.  Calls that overlap on one device
+ * (two streams, or two host threads without ordering between their streams)
+ * share that array and race: order them on one stream.
+ * Errors: CCUT_EINVAL (NULL pointer, q out of range), CCUT_EHIP.
+ */
+int ccut_norm_fidelity_noalloc(const void* d_psi, const void* d_ref, int32_t q, double* d_out, void* stream);
+
+/*
  * Expectation value of a Pauli string on the cut state, from the subcircuit
  * states alone (the setting the paper's closing section names, Sec. VI: no
  * O(2^q) merge and no 2^q buffer).  With O = P_{n-1} x ... x P_0 split by the

@@ -88,6 +88,7 @@ def _load():
         "ccut_merge_full_state": [vp, vp, u64, vp, u64, i32, vp],
         "ccut_simulate_uncut": [i32, vp, i64, vp, u64, vp],
         "ccut_norm_fidelity": [vp, vp, i32, ctypes.POINTER(ctypes.c_double), vp],
+        "ccut_norm_fidelity_noalloc": [vp, vp, i32, vp, vp],
         "ccut_expectation_work_bytes": [vp, ctypes.POINTER(u64)],
         "ccut_expectation_pauli": [vp, vp, u64, ctypes.c_char_p, vp, u64, ctypes.POINTER(ctypes.c_double), vp],
     }
@@ -328,6 +329,11 @@ def norm_fidelity(psi, ref, q: int, stream=None) -> dict:
     if ref is not None and n2p > 0 and n2r > 0:
         res["fidelity"] = (ore * ore + oim * oim) / (n2p * n2r)
     return res
+
+
+def norm_fidelity_noalloc(psi, ref, q: int, out, stream=None) -> None:
+    """Allocation-free form: the five float64 results go to the device buffer `out`."""
+    _check(_lib.ccut_norm_fidelity_noalloc(_ptr(psi), _ptr(ref), q, _ptr(out), _stream(stream)))
 
 
 PROF_KERNELS = 8

@@ -175,7 +175,6 @@ int plan_tables(ccut_plan* P, char* arena, hipStream_t s, DeviceTables& out, boo
 }
 
 // Per-device buffer for reduction partials (allocated once, kept for the process).
-constexpr int RED_BLOCKS = 1024;
 static std::mutex g_red_mu;
 static double* g_red_buf[64] = {nullptr};
 
@@ -450,4 +449,24 @@ extern "C" int ccut_norm_fidelity(const void* d_psi, const void* d_ref, int32_t 
   CCUT_HIP(hipMemcpyAsync(out, buf + RED_BLOCKS * 5, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
   CCUT_HIP(hipStreamSynchronize(s));
   return CCUT_OK;
+}
+
+extern "C" int ccut_norm_fidelity_noalloc(const void* d_psi, const void* d_ref, int32_t q, double* d_out,
+                                          void* stream) {
+  clear_error();
+  if (!d_psi || !d_out) return fail(CCUT_EINVAL, "NULL argument");
+  if (q < 0 || q > CCUT_MAX_Q)
+    return fail(CCUT_EINVAL, "q=%d outside [0, %d]: the fixed scratch array covers states up to 2^%d amplitudes", q,
+                CCUT_MAX_Q, CCUT_MAX_Q);
+  double* scratch = nullptr;
+  uint64_t cap = 0;
+  if (int rc = reduce_scratch(&scratch, &cap)) return rc;
+  const uint64_t n = (uint64_t)1 << q;
+  const int blocks = (int)std::min<uint64_t>(RED_BLOCKS, (n + 255) / 256);
+  if ((uint64_t)blocks * 5 > cap)
+    return fail(CCUT_ENOSPC, "%d reduction blocks need %d doubles of scratch, the array holds %llu", blocks,
+                blocks * 5, (unsigned long long)cap);
+  // every partial the final pass reads is written by this call's first pass: nothing to clear
+  return launch_reduce(static_cast<const float*>(d_psi), static_cast<const float*>(d_ref), n, scratch, blocks,
+                       d_out, static_cast<hipStream_t>(stream));
 }

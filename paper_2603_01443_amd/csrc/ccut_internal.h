@@ -242,7 +242,12 @@ GramShape gram_shape(int V, uint64_t N);
 int launch_gram(const float2* states, int V, uint64_t N, uint32_t flip, uint32_t zy, GramShape g, double2* part,
                 double2* out, hipStream_t s);
 
+// Partial blocks of the float64 reductions (5 doubles each); every state size uses at most this many.
+constexpr int RED_BLOCKS = 1024;
 int launch_reduce(const float* psi, const float* ref, uint64_t n, double* d_partials, int n_blocks,
                   double* d_out, hipStream_t s);
+// Device address of the fixed reduction scratch array on the current device (looked
+// up once per device) and its capacity in doubles.
+int reduce_scratch(double** out, uint64_t* n_doubles);
 
 }  // namespace ccut

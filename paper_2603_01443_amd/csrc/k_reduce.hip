@@ -3,6 +3,8 @@
 // (Sec. III of the paper); these numbers measure how closely a computed state
 // does.  Two deterministic passes: fixed per-block partials, then one block.
 // The max keeps squared distances (the square root, monotone, is taken once).
+#include <mutex>
+
 #include "ccut_internal.h"
 
 namespace ccut {
@@ -98,6 +100,38 @@ __global__ __launch_bounds__(RT) void k_reduce_final(const double* __restrict__ 
 }
 
 }  // namespace
+
+// ------------------------------------------------ allocation-free variant
+// The partials of ccut_norm_fidelity_noalloc live in this fixed array instead of a
+// buffer the library allocates: RED_BLOCKS blocks x 5 partials (40 KiB), enough for
+// every state size since the partial pass never uses more blocks.  Each device holds
+// its own copy at its own address until the process ends.  In host code `scratch`
+// names a host-side stand-in, never the device memory: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[RED_BLOCKS * 5];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[MAX_DEVICES] = {};
+}  // namespace
+
+int reduce_scratch(double** out, uint64_t* n_doubles) {
+  int dev = 0;
+  CCUT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(CCUT_EUNSUPPORTED, "device id %d", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(CCUT_EHIP, "hipGetSymbolAddress(scratch) returned NULL on device %d", dev);
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  *n_doubles = (uint64_t)RED_BLOCKS * 5;
+  return 0;
+}
 
 int launch_reduce(const float* psi, const float* ref, uint64_t n, double* d_partials, int n_blocks,
                   double* d_out, hipStream_t s) {
