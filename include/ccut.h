@@ -367,12 +367,17 @@ int ccut_plan_get_launch(const ccut_plan_t* plan, int32_t out[4]);
 int ccut_plan_stats(const ccut_plan_t* plan, int64_t out[8]);
 
 /*
- * Variant and grid of the MFMA merge GEMM.  epilogue (0..3): bit 0 set
- * transposes 16-row slabs through LDS into 16-byte row stores (clear: each
- * lane stores its accumulators directly); bit 1 set uses 64 x 256 tiles with
- * 32 rows per wavefront (clear: 128 x 256 tiles, 64 rows per wavefront).
+ * Variant and grid of the MFMA merge GEMM.  epilogue 0..3 are tiled kernels:
+ * bit 0 set transposes 16-row slabs through LDS into 16-byte row stores
+ * (clear: each lane stores its accumulators directly); bit 1 set uses 64 x 256
+ * tiles with 32 rows per wavefront (clear: 128 x 256 tiles, 64 rows per
+ * wavefront).  epilogue 4 is the R-stationary kernel: one 16-wavefront
+ * workgroup per CU keeps a 128-column strip of the low-qubit factor (all
+ * terms, hi and lo) in LDS and sweeps all rows of its strip; it covers up to
+ * K = 64 terms per stage and runs larger stages as epilogue 1.
  * grid_cap 0 launches one workgroup per tile, > 0 a persistent grid of at most
- * grid_cap workgroups looping over tiles.  Results do not depend on either.
+ * grid_cap workgroups looping over tiles (ignored by epilogue 4, whose grid is
+ * one workgroup per CU).  Results do not depend on either.
  * Host-only.  Errors: CCUT_EINVAL.
  */
 int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap);

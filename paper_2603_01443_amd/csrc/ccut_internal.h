@@ -12,6 +12,9 @@
 
 namespace ccut {
 
+// MFMA merge GEMM variants (0..3 tiled, 4 R-stationary; see merge_mfma.h)
+constexpr int MERGE_VARIANTS = 5;
+
 // ----------------------------------------------------------------- errors
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();

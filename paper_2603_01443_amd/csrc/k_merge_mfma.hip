@@ -331,6 +331,160 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
   (void)qy;
 }
 
+// ------------------------------------------- R-stationary GEMM (K <= 64)
+// One workgroup of 16 wavefronts per CU owns a strip of 256 real columns (8
+// column blocks) and keeps the strip's R fragments for every step (hi and lo;
+// at most 8 steps: 128 KiB) in LDS for its whole life.  Each wavefront sweeps
+// its own 32-row blocks (w, w + 16, ...) independently: it holds the block's L
+// fragments for all steps in registers and runs the strip in four passes of two
+// column blocks, reading R from LDS.  L2 serves half the output size in operand
+// bytes (the tiled kernel above: 3x to 5x).
+// Stores and loads share one in-order counter, so a wavefront that loads after
+// storing waits for its stores to drain.  The next block's L fragments are
+// therefore fetched during the last pass (into the registers of the steps that
+// pass has already used) before that pass's stores, and the first block is peeled
+// so that every path into the loop has the same load/store order (the compiler
+// then waits only for the loads, not for the stores issued after them).
+// Stores are buffer stores: a wave-uniform base, one lane offset and the row
+// offset in a scalar, each access range-checked by the hardware.
+constexpr int RS_WAVES = 16;
+constexpr int RS_NC = 8;  // column blocks per strip
+
+template <int MODE, int S>
+__global__ __launch_bounds__(RS_WAVES * 64) void k_merge_gemm_rs(
+    const uint4* __restrict__ Lhi, const uint4* __restrict__ Llo, const uint4* __restrict__ Rhi,
+    const uint4* __restrict__ Rlo, uint64_t l_bstride, uint64_t r_bstride, float* __restrict__ out,
+    uint64_t out_bstride, int qx, int qy, int strips, int row_split) {
+  constexpr bool L_SPLIT = MODE != MERGE_BF16;
+  constexpr bool R_SPLIT = MODE == MERGE_BF16X3 || MODE == MERGE_FP16X3;
+  constexpr int CB = 2;  // column blocks per pass
+  // R fragments in LDS: index ((cb * S + s) * NP + plane) * 64 + lane, hi and lo of one
+  // (column block, step) side by side so that a pass's reads sit within the 64 KiB
+  // reach of one base address plus immediate offsets
+  constexpr int NP = R_SPLIT ? 2 : 1;
+  __shared__ uint4 sR[RS_NC * S * NP * 64];
+  const int beta = blockIdx.y;
+  const int strip = (int)blockIdx.x % strips;
+  const int part = (int)blockIdx.x / strips;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const float scale = is_f16(MODE) ? (1.0f / 268435456.0f) : 1.0f;  // 2^-28
+  const uint32_t ncols = 2u << qx;
+  float* ob = out + beta * out_bstride;
+  const char* out_end = reinterpret_cast<const char*>(ob + ((uint64_t)1 << qy) * ncols);
+
+  {  // the strip's R fragments: 8 column blocks x S steps, contiguous in both planes
+    constexpr int n = RS_NC * S * 64;
+    const uint4* gh = Rhi + beta * r_bstride + (uint64_t)strip * n;
+    const uint4* gl = Rlo + beta * r_bstride + (uint64_t)strip * n;
+    for (int i = threadIdx.x; i < n; i += RS_WAVES * 64) {
+      const int d = (i >> 6) * NP * 64 + (i & 63);
+      sR[d] = gh[i];
+      if (R_SPLIT) sR[d + 64] = gl[i];
+    }
+  }
+  __syncthreads();
+
+  const int nrb = 1 << (qy - 5);
+  const int per = (nrb + row_split - 1) / row_split;
+  const int rb_begin = part * per;
+  const int rb_end = min(nrb, rb_begin + per);
+  const uint4* lbh = Lhi + beta * l_bstride;
+  const uint4* lbl = Llo + beta * l_bstride;
+  // byte offset of this lane's first accumulator within a 32-row block
+  const uint32_t o_st = ((uint32_t)(4 * (lane >> 5)) * ncols + (uint32_t)(lane & 31)) * 4u;
+  uint4 Lh[S], Ll[S];
+  // L fragments of steps [s0, s0 + n) of row block r (always in bounds: r < nrb)
+  auto loadL = [&](int r, int s0, int n) {
+    const char* bh = reinterpret_cast<const char*>(lbh + (uint64_t)r * S * 64);
+    const char* bl = reinterpret_cast<const char*>(lbl + (uint64_t)r * S * 64);
+    const uint32_t lo16 = (uint32_t)lane * 16u;
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+      if (t >= s0 && t < s0 + n) {
+        Lh[t] = *reinterpret_cast<const uint4*>(bh + (lo16 + t * 1024u));
+        if (L_SPLIT) Ll[t] = *reinterpret_cast<const uint4*>(bl + (lo16 + t * 1024u));
+      }
+  };
+  auto block = [&](int rb) {
+    const int nx = min(rb + RS_WAVES, nrb - 1);  // past the last block: a valid block, never used
+    float* orow = ob + (uint64_t)rb * 32 * ncols + (uint64_t)strip * (RS_NC * 32);
+#pragma unroll
+    for (int p = 0; p < RS_NC / CB; ++p) {
+      constexpr int kLast = RS_NC / CB - 1;
+      f32x16 acc[CB];
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[c][v] = 0.f;
+      const uint4* rp = sR + (CB * p) * S * NP * 64 + lane;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        uint4 bh[CB], bl[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          bh[c] = rp[(c * S + s) * NP * 64];
+          if (R_SPLIT) bl[c] = rp[(c * S + s) * NP * 64 + 64];
+        }
+        if (L_SPLIT) {
+#pragma unroll
+          for (int c = 0; c < CB; ++c) acc[c] = mfma<MODE>(Ll[s], bh[c], acc[c]);
+        }
+        if (R_SPLIT) {
+#pragma unroll
+          for (int c = 0; c < CB; ++c) acc[c] = mfma<MODE>(Lh[s], bl[c], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[c] = mfma<MODE>(Lh[s], bh[c], acc[c]);
+        if (p == kLast) {
+          // registers of steps this pass is done with take the next block's fragments
+          if (S == 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            loadL(nx, 0, 1);
+            __builtin_amdgcn_sched_barrier(0);
+          } else if (s == S / 2 - 1 || s == S - 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            loadL(nx, s == S - 1 ? S / 2 : 0, S / 2);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        if (is_f16(MODE)) acc[c] *= scale;
+        float* oc = orow + (CB * p + c) * 32;
+        const uint64_t left = (uint64_t)(out_end - reinterpret_cast<const char*>(oc));
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            oc, 0, (int)(left > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)left), 0x00020000);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const uint32_t soff = (uint32_t)((v & 3) + 8 * (v >> 2)) * ncols * 4u;
+          // non-temporal (cache policy bit 1)
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[c][v]), rs, (int)o_st, (int)soff, 2);
+        }
+      }
+    }
+  };
+  int rb = rb_begin + wave;
+  loadL(min(rb, nrb - 1), 0, S);
+  if (rb < rb_end) {
+    block(rb);
+    for (rb += RS_WAVES; rb < rb_end; rb += RS_WAVES) block(rb);
+  }
+}
+
+// S in {1, 2, 4, 8} (K <= 64; K is a power of two) and row offsets of a 32-row block
+// within 32 bits (the buffer stores' scalar offset): 2^(qx + 1) floats per row, qx <= 23
+bool merge_rs_supported(int qx, int S) { return qx >= 7 && qx <= 23 && (S == 1 || S == 2 || S == 4 || S == 8); }
+
+int cu_count() {
+  int dev = 0, c = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0)
+    return c;
+  return 256;
+}
+
 template <int MODE>
 int launch_mode(const MergeMfmaArgs& a, int variant, int grid_cap, hipStream_t s) {
   const int S = a.S;
@@ -345,6 +499,31 @@ int launch_mode(const MergeMfmaArgs& a, int variant, int grid_cap, hipStream_t s
     hipLaunchKernelGGL(k_split<MODE>, grid, dim3(256), 0, s, a, (int)r_blocks);
     CCUT_HIP(hipGetLastError());
   }
+  if (variant == 4 && merge_rs_supported(a.qx, S)) {
+    // R-stationary kernel: one workgroup per (strip, row part, batch entry); row parts
+    // only as many as it takes to give every CU one workgroup
+    const int strips = 1 << (a.qx + 1 - 8);
+    const int nrb = 1 << (a.qy - 5);
+    const int want = (cu_count() + strips * a.batch - 1) / (strips * a.batch);
+    const int row_split = std::max(1, std::min(want, nrb / RS_WAVES));
+    if ((uint64_t)strips * row_split > 0x7FFFFFFFull) return fail(CCUT_EUNSUPPORTED, "merge too large");
+    dim3 grid((unsigned)(strips * row_split), a.batch);
+    const uint64_t r_bstride = a.r_batch > 1 ? a.r_plane_stride : 0;
+    ProfScope prof(PROF_MERGE_GEMM, s);
+#define CCUT_RS(SS)                                                                                              \
+  hipLaunchKernelGGL((k_merge_gemm_rs<MODE, SS>), grid, dim3(RS_WAVES * 64), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo,    \
+                     a.l_plane_stride, r_bstride, a.out, a.out_bstride * 2, a.qx, a.qy, strips, row_split)
+    switch (S) {
+      case 1: CCUT_RS(1); break;
+      case 2: CCUT_RS(2); break;
+      case 4: CCUT_RS(4); break;
+      default: CCUT_RS(8); break;
+    }
+#undef CCUT_RS
+    CCUT_HIP(hipGetLastError());
+    return 0;
+  }
+  if (variant == 4) variant = 1;  // shapes the R-stationary kernel does not take
   const int col_tiles = 1 << (a.qx + 1 - 8);                      // 256 real columns per tile
   const int row_tiles = 1 << (a.qy - ((variant & 2) ? 6 : 7));    // 64 or 128 rows per tile
   const int ntiles = col_tiles * row_tiles;

@@ -22,8 +22,11 @@ struct MergeMfmaArgs {
 };
 
 bool merge_mfma_supported(int qx, int qy);
-// variant bit 0: stores through an LDS transpose (else direct accumulator stores);
-// variant bit 1: 64-row tiles, 32 rows per wavefront (else 128-row tiles).
+// variant 0..3, bit 0: stores through an LDS transpose (else direct accumulator stores);
+//               bit 1: 64-row tiles, 32 rows per wavefront (else 128-row tiles);
+// variant 4: R-stationary kernel (a 128-column strip of R held in LDS by one
+//            16-wavefront workgroup per CU), up to 8 MFMA steps (K <= 64); above
+//            that it runs as variant 1.
 // grid_cap > 0: persistent grid of at most grid_cap workgroups per batch entry.
 int launch_merge_mfma(const MergeMfmaArgs& a, int mode, int variant, int grid_cap, hipStream_t s);
 

@@ -124,7 +124,7 @@ extern "C" int ccut_plan_set_launch(ccut_plan_t* plan, int32_t threads, int32_t 
 extern "C" int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap) {
   clear_error();
   if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
-  if (epilogue < 0 || epilogue > 3 || grid_cap < 0) return fail(CCUT_EINVAL, "bad merge configuration");
+  if (epilogue < 0 || epilogue > MERGE_VARIANTS - 1 || grid_cap < 0) return fail(CCUT_EINVAL, "bad merge configuration");
   plan->merge_epilogue = epilogue;
   plan->merge_grid_cap = grid_cap;
   return CCUT_OK;
@@ -418,7 +418,7 @@ extern "C" int ccut_autotune_load(const char* path) {
   while (std::fgets(line, sizeof(line), f)) {
     if (line[0] == '#') continue;
     if (std::sscanf(line, "%1023s %d %d %d %d %d %d %d", key, &t, &c, &k, &ep, &mg, &bb, &pf) == 8 &&
-        (t == 256 || t == 512 || t == 1024) && c >= 0 && k >= -1 && ep >= 0 && ep <= 3 && mg >= 0 &&
+        (t == 256 || t == 512 || t == 1024) && c >= 0 && k >= -1 && ep >= 0 && ep < MERGE_VARIANTS && mg >= 0 &&
         (bb == 0 || (bb > 4 && bb <= PASS_MAX_B)) && pf >= -1 && pf <= 1 + CCUT_MAX_CUTS_PER_SEG)
       g_tune[key] = TuneEntry{t, c, k, ep, mg, bb, pf};
   }
