@@ -4,15 +4,21 @@
 Workload (the metric's configuration): random Ry.Rz + CZ brickwork, q = 28
 qubits, two equal segments of 14, depth d = 20, c_total = 6 cut CZs
 (K = 64 merge terms), seed 0.  One step is the whole cut pipeline of
-Eq. (runtime_decomp): cut_plan on the host (T_pre; its tables are copied
-into the arena by the first device call), every
-subcircuit variant (T_sub) and the merge into the 2^28 complex64 state
-(T_merge).  value = 2^q amplitudes per step / seconds per step.
+Eq. (runtime_decomp): cut_plan on the host (T_pre), every subcircuit variant
+(T_sub) and the merge into the 2^28 complex64 state (T_merge), with the merge
+in the library's default arithmetic (AUTO: the fully split fp16 hi + lo
+product on MFMA at this term count).  The device part of a step is one HIP
+graph replay: the graph is captured once, and every step's freshly built plan
+is rebound into it (its tables copied into the graph's table buffer) before
+the replay.  value = 2^q amplitudes per step / seconds per step.
 
-Beside the steps it times the uncut simulation of the same circuit on the
-same GPU (T_orig), checks the cut state against the uncut state (1 - F,
-float64 reductions) and against oracle amplitudes at sampled indices, and
-times the complex128 CPU oracle on a bounded sample (cpu_baseline).
+Beside the steps it times the merge GEMM with HIP events in a second run of
+direct-launch steps (the roofline kernel), the same steps with the fp16x2
+opt-in merge, the uncut simulation of the same circuit (T_orig), checks the
+cut state against the uncut state (1 - F, float64 reductions) and against
+oracle amplitudes at sampled indices, and times the complex128 CPU oracle on
+a bounded sample of the same workload (cpu_baseline), at one thread and on
+a process pool over the host's cores, before the GPU is touched.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -21,7 +27,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -32,39 +37,92 @@ sys.path.insert(0, ROOT)
 Q, D, NSEG, CTOTAL, SEED = 28, 20, 2, 6, 0
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the merge GEMM from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by
-# a 1 GiB copy (2.0 x FETCH + 1.0 x WRITE); see profiles/.  One entry per variant the autotuner
-# may pick (mean over its grid sizes).  Only valid for the kernel revision it was measured on:
-# remove an entry whenever that kernel changes.
-MEASURED_TRAFFIC = {
-    "merge_gemm (fp16x2, v0)": 2.226e9,
-    "merge_gemm (fp16x2, v1)": 2.227e9,
-    "merge_gemm (fp16x2, v2)": 2.224e9,
-    "merge_gemm (fp16x2, v3)": 2.224e9,
-}
-MFMA_BF16_PEAK_TFLOPS = 2500.0
+# a 1 GiB copy (2.0 x FETCH + 1.0 x WRITE), keyed by the kernel the bench line names.  Only valid
+# for the kernel revision the counters were taken on: remove an entry whenever that kernel changes.
+MEASURED_TRAFFIC: dict = {}
 FP32_PEAK_TFLOPS = 157.3
+# float32 flops per amplitude of a fused dense 2x2 gate (two complex multiply-adds, FMA = 2 flops)
+# and of a diagonal phase (one complex multiply)
+DENSE_FLOPS, DIAG_FLOPS = 16, 6
+CPU_WORKERS_MAX = 16
+MERGE_ROWS = 128  # high-segment rows of the oracle's merge sample per worker
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_info():
+    model, mem_gib = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem_gib = int(line.split()[1]) / 2 ** 20
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable, "mem_gib": mem_gib}
+
+
+# Process-pool tasks: each runs the unmodified oracle on its own share of the sample.
+_POOL_CTX = {}
+
+
+def _pool_init(gates, sizes):
+    from threadpoolctl import threadpool_limits
+    from oracle import cutting
+    threadpool_limits(limits=1)
+    cuts = cutting.find_cuts(Q, gates, sizes)
+    _POOL_CTX.update(gates=gates, sizes=sizes, cuts=cuts)
+
+
+def _pool_variants(keys):
+    from oracle import cutting
+    g, sizes, cuts = _POOL_CTX["gates"], _POOL_CTX["sizes"], _POOL_CTX["cuts"]
+    out = {}
+    for seg, bits in keys:
+        adj = cutting.adjacent_cuts(cuts, seg)
+        out[(seg, bits)] = cutting.simulate_local(
+            sizes[seg], cutting.subcircuit(g, sizes, seg, cuts, dict(zip(adj, bits))))
+    return out
+
+
+def _pool_merge(args):
+    from oracle import cutting
+    states, r0 = args
+    sizes, cuts = _POOL_CTX["sizes"], _POOL_CTX["cuts"]
+    part = {k: (v[r0:r0 + MERGE_ROWS] if k[0] == 1 else v) for k, v in states.items()}
+    return cutting.merge(sizes, cuts, part).shape[0]
+
+
 def cpu_baseline(gates, sizes):
     """Times the complex128 oracle on a bounded sample of the same workload.
 
     Sample: the oracle's cut plan and all 2 * 2^6 subcircuit variants in full,
-    then its merge (the plain sum over all 64 terms) restricted to the first
-    R rows of the high segment, i.e. R * 2^14 of the 2^28 amplitudes; the merge
-    time is scaled by 2^14 / R to the full state.  Beside it, the oracle's
-    uncut simulation: one single-qubit gate and one CZ applied to the 2^28
-    complex128 state, scaled by the circuit's gate counts.
+    then its merge (the plain sum over all 64 terms) restricted to MERGE_ROWS
+    rows of the high segment; the merge time is scaled to the full state.
+    Timed once at one thread, and once on a pool of W worker processes (W =
+    the host's usable CPUs, at most 16): the variants are divided among the
+    workers and each merges its own MERGE_ROWS rows (W times the one-thread
+    sample).  Beside it, the oracle's uncut simulation at one thread: one
+    single-qubit gate and one CZ applied to the 2^28 complex128 state, scaled
+    by the circuit's gate counts (numpy's elementwise kernels use one thread).
     """
+    import multiprocessing as mp
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import cutting, statevector
 
-    rows = 128
+    rows = MERGE_ROWS
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         cuts = cutting.find_cuts(Q, gates, sizes)
@@ -87,22 +145,50 @@ def cpu_baseline(gates, sizes):
         del psi
     n_two = sum(1 for g in gates if g.q1 >= 0)
     t_orig = (len(gates) - n_two) * (t5 - t4) + n_two * (t6 - t5)
+    scale = (1 << sizes[1]) / rows
     t_pre, t_sub, t_merge_s = t1 - t0, t2 - t1, t3 - t2
-    t_merge = t_merge_s * ((1 << sizes[1]) / rows)
-    t_cut = t_pre + t_sub + t_merge
-    return {
-        "value": (1 << Q) / t_cut, "unit": "amps/s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle cut plan + all {len(states)} variant states in full; merge over all "
-                   f"{2 ** len(cuts)} terms on the first {rows} of {1 << sizes[1]} high-segment rows "
-                   f"({rows << sizes[0]} amplitudes), scaled by {(1 << sizes[1]) // rows}; "
-                   f"complex128 numpy, BLAS limited to 1 thread"),
-        "seconds": {"pre": t_pre, "sub": t_sub, "merge_sample": t_merge_s, "merge_scaled": t_merge,
-                    "cut_total_est": t_cut, "uncut_one_qubit_gate": t5 - t4, "uncut_cz_gate": t6 - t5,
-                    "uncut_est": t_orig},
-        "uncut_sample": (f"oracle uncut simulation (complex128, gate by gate): one single-qubit gate and "
-                         f"one CZ on the 2^{Q} state, scaled to the circuit's {len(gates) - n_two} "
+    t_cut1 = t_pre + t_sub + t_merge_s * scale
+    single = {"value": (1 << Q) / t_cut1, "unit": "amps/s", "cores": 1,
+              "seconds": {"pre": t_pre, "sub": t_sub, "merge_sample": t_merge_s,
+                          "merge_scaled": t_merge_s * scale, "cut_total_est": t_cut1,
+                          "uncut_one_qubit_gate": t5 - t4, "uncut_cz_gate": t6 - t5, "uncut_est": t_orig}}
+
+    info = host_info()
+    workers = max(1, min(CPU_WORKERS_MAX, info["usable_cpus"] or 1))
+    keys = list(states.keys())
+    chunks = [keys[i::workers] for i in range(workers)]
+    ctx = mp.get_context("fork")   # the GPU is not initialised yet in this process
+    with ctx.Pool(workers, initializer=_pool_init, initargs=(gates, sizes)) as pool:
+        # warm-up: every worker imports the oracle and runs one tiny merge before the clock starts
+        pool.map(_pool_merge, [({k: v[:1] for k, v in states.items()}, 0)] * workers)
+        p0 = time.perf_counter()
+        got = {}
+        for d in pool.map(_pool_variants, chunks):
+            got.update(d)
+        p1 = time.perf_counter()
+        starts = [(w * rows) % (1 << sizes[1]) for w in range(workers)]
+        done = pool.map(_pool_merge, [(states, r0) for r0 in starts])
+        p2 = time.perf_counter()
+    assert len(got) == len(states) and all(n == rows << sizes[0] for n in done)
+    t_sub_p, t_merge_p = p1 - p0, p2 - p1
+    merged = workers * rows << sizes[0]
+    t_cutp = t_pre + t_sub_p + t_merge_p * ((1 << Q) / merged)
+    out = {
+        "value": (1 << Q) / t_cutp, "unit": "amps/s", "cores": workers, "kind": "oracle",
+        "sample": (f"oracle cut plan + all {len(states)} variant states in full, divided over {workers} worker "
+                   f"processes; merge over all {2 ** len(cuts)} terms on {workers} x {rows} of the "
+                   f"{1 << sizes[1]} high-segment rows ({merged} amplitudes, one slice per worker), scaled to the "
+                   f"full state; complex128 numpy, one BLAS thread per worker"),
+        "seconds": {"pre": t_pre, "sub": t_sub_p, "merge_sample": t_merge_p, "cut_total_est": t_cutp},
+        "single_thread": single,
+        "single_thread_sample": (f"the same oracle calls in one process and thread; merge on the first {rows} "
+                                 f"rows ({rows << sizes[0]} amplitudes), scaled by {int(scale)}"),
+        "uncut_sample": (f"oracle uncut simulation at one thread (complex128, gate by gate): one single-qubit "
+                         f"gate and one CZ on the 2^{Q} state, scaled to the circuit's {len(gates) - n_two} "
                          f"single-qubit and {n_two} two-qubit gates"),
-    }, cuts, states
+        "host": info,
+    }
+    return out, cuts, states
 
 
 def main():
@@ -121,18 +207,30 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     from inputs import brickwork, equal_blocks
+
+    sizes = equal_blocks(Q, NSEG)
+    gates = brickwork(Q, D, NSEG, CTOTAL, SEED)
+
+    cb = cuts = states = None
+    if not args.no_cpu:
+        log("bench: timing the CPU oracle on a bounded sample (before the GPU is used)")
+        cb, cuts, states = cpu_baseline(gates, sizes)
+        log(f"bench: cpu oracle {cb['value']:.3e} amps/s on {cb['cores']} processes, "
+            f"{cb['single_thread']['value']:.3e} at one thread (uncut estimate "
+            f"{cb['single_thread']['seconds']['uncut_est']:.0f} s)")
+
+    import torch
+
     from paper_2603_01443_amd import ccut
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
-    sizes = equal_blocks(Q, NSEG)
-    gates = brickwork(Q, D, NSEG, CTOTAL, SEED)
+    stream = torch.cuda.Stream()   # graph capture needs a non-default stream (default priority)
+    torch.cuda.set_stream(stream)
     garr = ccut.gate_array(gates)
     plan0 = ccut.cut_plan(Q, garr, NSEG, sizes)
     info = plan0.info()
@@ -145,7 +243,8 @@ def main():
 
     # one autotuning pass (outside the timed region); plans of this shape reuse its choice
     tuned_ms = ccut.autotune(plan0, arena, psi, reps=3, stream=stream)
-    log(f"bench: autotuned launch {ccut.plan_get_launch(plan0)} ({tuned_ms:.3f} ms)")
+    log(f"bench: autotuned launch {ccut.plan_get_launch(plan0)}, merge {ccut.plan_get_merge(plan0)} in "
+        f"{ccut.plan_get_auto_precision(plan0)} ({tuned_ms:.3f} ms)")
     # plans built from now on start from the tuned configuration, whose tables may
     # need more arena than the untuned plan reserved: size the arena for them
     need = ccut.cut_plan(Q, garr, NSEG, sizes).info()["arena_bytes"]
@@ -153,48 +252,76 @@ def main():
         del arena
         torch.cuda.empty_cache()
         arena = torch.empty(need, dtype=torch.uint8, device=dev)
+    used = ccut.resolved_precision(plan0, prec, K)
 
     t_pre = []
     keep = []
 
-    def step(marks=None):
-        t0 = time.perf_counter()
-        plan = ccut.cut_plan(Q, garr, NSEG, sizes)   # tables reach the device with the first call
-        t_pre.append(time.perf_counter() - t0)
+    # ---- direct-launch steps: the roofline kernel bracketed by HIP events on its stream
+    kname = "merge_f32" if used == "fp32" else "merge_gemm"
+
+    def direct_step(precision, marks=None):
+        plan = ccut.cut_plan(Q, garr, NSEG, sizes)
         if marks:
             marks[0].record(stream)
         ccut.simulate_subcircuits(plan, arena, stream=stream)
         if marks:
             marks[1].record(stream)
-        ccut.merge_full_state(plan, arena, psi, prec, stream=stream)
+        ccut.merge_full_state(plan, arena, psi, precision, stream=stream)
         if marks:
             marks[2].record(stream)
-        keep.append(plan)   # freed after the timed region (freeing syncs the device)
+        keep.append(plan)
+
+    def timed_direct(precision, kernel):
+        for _ in range(2):
+            direct_step(precision)
+        torch.cuda.synchronize()
+        keep.clear()
+        ccut.profile_reset()
+        ccut.profile_mask([kernel])
+        ccut.profile_enable(True)
+        w0 = time.perf_counter()
+        for _ in range(args.steps):
+            direct_step(precision)
+        torch.cuda.synchronize()
+        w = time.perf_counter() - w0
+        ccut.profile_enable(False)
+        n, tot = ccut.profile_read()[kernel]
+        keep.clear()
+        return 1e3 * w / args.steps, tot / n, n
+
+    # first: these steps also bring clocks and memory to their steady state before the graph steps
+    direct_ms, k_ms, k_launches = timed_direct(prec, kname)
+    log(f"bench: {direct_ms:.3f} ms/step direct; {kname} ({used}) {k_ms:.4f} ms per launch")
+
+    # ---- the timed steps: host plan, rebind into the captured graph, one replay
+    graph = ccut.Graph(ccut.cut_plan(Q, garr, NSEG, sizes), arena, psi, prec, stream=stream)
+
+    def graph_step():
+        t0 = time.perf_counter()
+        plan = ccut.cut_plan(Q, garr, NSEG, sizes)
+        t_pre.append(time.perf_counter() - t0)
+        graph.rebind(plan, stream)
+        graph.launch(stream)
+        keep.append(plan)   # freed after the timed region
 
     for _ in range(args.warmup):
-        step()
+        graph_step()
     torch.cuda.synchronize()
     keep.clear()
     t_pre.clear()
-    used = prec if prec != "auto" else ("fp16x2" if K >= 8 else "fp32")
-    kname = "merge_f32" if used == "fp32" else "merge_gemm"
-    log(f"bench: warmup done, timing {args.steps} steps")
-    # Timed region: only the roofline kernel is bracketed by HIP events (on the stream it
-    # is launched on), so the other launches run unperturbed.
-    ccut.profile_reset()
-    ccut.profile_mask([kname])
-    ccut.profile_enable(True)
+    log(f"bench: warmup done, timing {args.steps} graph-replayed steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        graph_step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ccut.profile_enable(False)
-    kprof_timed = ccut.profile_read()
     keep.clear()
     ms_step = 1e3 * wall / args.steps
     t_pre_ms = 1e3 * float(np.mean(t_pre))
+    cut_state_check = psi.clone()
+    log(f"bench: {ms_step:.3f} ms/step graph-replayed")
 
     # Stage breakdown on further (untimed) steps: events between stages, every kernel timed.
     nb = min(10, max(1, args.steps))
@@ -203,15 +330,19 @@ def main():
     ccut.profile_mask(None)
     ccut.profile_enable(True)
     for i in range(nb):
-        step(marks[i])
+        direct_step(prec, marks[i])
     torch.cuda.synchronize()
     ccut.profile_enable(False)
     kprof = ccut.profile_read()
     keep.clear()
     t_sub = [m[0].elapsed_time(m[1]) for m in marks]
     t_merge = [m[1].elapsed_time(m[2]) for m in marks]
-    log(f"bench: {ms_step:.3f} ms/step; breakdown (separate steps, all kernels timed): sub "
-        f"{np.mean(t_sub):.3f} ms, merge {np.mean(t_merge):.3f} ms, pre {t_pre_ms:.3f} ms")
+    log(f"bench: breakdown (separate steps, all kernels timed): sub {np.mean(t_sub):.3f} ms, merge "
+        f"{np.mean(t_merge):.3f} ms, pre {t_pre_ms:.3f} ms")
+
+    # fp16x2 (opt-in: only the high-qubit factor split) on the same direct-launch steps
+    x2_ms, x2_k_ms, _ = timed_direct("fp16x2", "merge_gemm")
+    log(f"bench: fp16x2 opt-in {x2_ms:.3f} ms/step direct, merge_gemm {x2_k_ms:.4f} ms")
 
     # uncut baseline on the same GPU
     ref = torch.empty_like(psi)
@@ -228,18 +359,17 @@ def main():
     torch.cuda.synchronize()
     t_orig_wall = 1e3 * (time.perf_counter() - w0) / reps
     t_orig = e0.elapsed_time(e1) / reps
-    stats = ccut.norm_fidelity(psi, ref, Q, stream=stream)
+    stats = ccut.norm_fidelity(cut_state_check, ref, Q, stream=stream)
     one_minus_f = 1.0 - stats["fidelity"]
-    log(f"bench: uncut {t_orig:.3f} ms; cut vs uncut 1-F {one_minus_f:.3e}, norm drift "
-        f"{abs(stats['norm2'] - 1):.3e}")
+    log(f"bench: uncut {t_orig:.3f} ms; graph-replayed cut state vs uncut 1-F {one_minus_f:.3e}, norm drift "
+        f"{abs(stats['norm2'] - 1):.3e}, max-abs {stats['max_abs']:.3e}")
 
     merge_ms = float(np.mean(t_merge))
     merge_bytes = 8 * (1 << Q) + 8 * K * ((1 << sizes[0]) + (1 << sizes[1]))
     merge_flops = 8 * K * (1 << Q)
     kernels_ms = {k: v[1] / v[0] for k, v in kprof.items() if v[0] > 0}
     kernel_launches = {k: v[0] // nb for k, v in kprof.items() if v[0] > 0}
-    k_launches, k_total = kprof_timed[kname]
-    k_ms = k_total / k_launches
+    variant = ccut.plan_get_merge(plan0)["variant"]
     if used == "fp32" and K * 8 > FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9) * 8:
         roof = {"bound": "alu", "achieved": merge_flops / (k_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s"}
@@ -247,16 +377,19 @@ def main():
         roof = {"bound": "hbm", "achieved": merge_bytes / (k_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = f"{kname} ({used}, v{ccut.plan_get_merge(plan0)['variant']})"
+    roof["kernel"] = f"{kname} ({used}, v{variant})"
     roof["traffic"] = MEASURED_TRAFFIC.get(roof["kernel"])
     roof["avg_ms"] = k_ms
     roof["launches_timed"] = k_launches
+    roof["timing"] = (f"HIP events around each {kname} launch on its stream, over {args.steps} direct-launch "
+                      f"steps of the same pipeline (graph replays carry no event nodes)")
     roof["algorithmic_bytes"] = merge_bytes
     roof["algorithmic_flops"] = merge_flops
-    # Second kernel: the subcircuit simulation, work counted as fused float32 2x2 gates
-    # (16 flop per amplitude per gate) on every variant of both (equal) segments.
-    pstats = ccut.plan_stats(plan0)
-    sim_flops = 16.0 * pstats["dense_ops"] * (1 << (CTOTAL if NSEG == 2 else 0)) * (1 << sizes[0])
+    # Second kernel: the subcircuit simulation, work counted as the float32 flops of the fused
+    # gates the tuned schedule executes (prefix tree levels x chunk ops, every job's amplitudes)
+    work = ccut.plan_work(plan0)
+    sim_flops = DENSE_FLOPS * work["dense_amp_ops"] + DIAG_FLOPS * work["diag_amp_ops"]
+    flat_flops = DENSE_FLOPS * work["flat_dense_amp_ops"]
     sim_ms = kernels_ms.get("sim", 0.0) * kernel_launches.get("sim", 0)
     roof_sim = None
     if sim_ms > 0:
@@ -265,14 +398,15 @@ def main():
         roof_sim = {"bound": "alu", "achieved": sim_flops / (sim_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "kernel": f"sim ({ccut.plan_get_sim_precision(plan0)} groups, "
                     f"2^{ccut.plan_get_block_bits(plan0)} blocks, {prefix})", "avg_ms_per_step": sim_ms,
-                    "algorithmic_flops": sim_flops,
-                    "note": "flops of the flat schedule (fused 2x2 gates on every variant); bound by the op "
-                            "interpreter, stage barriers and the group arithmetic, not by HBM; from the "
-                            "breakdown steps"}
+                    "algorithmic_flops": sim_flops, "flat_schedule_flops": flat_flops,
+                    "note": (f"flops the schedule executes: {DENSE_FLOPS} per amplitude per fused dense 2x2 gate, "
+                             f"{DIAG_FLOPS} per diagonal phase, over every job of the tuned schedule "
+                             f"(ccut_plan_work); the flat schedule would execute flat_schedule_flops; from the "
+                             f"breakdown steps")}
         roof_sim["frac"] = roof_sim["achieved"] / roof_sim["peak"]
     log(f"bench: kernels (avg ms per launch) {kernels_ms}")
 
-    # achievable HBM bandwidth on this machine: a torch fill (write only) and copy of 2 GiB
+    # achievable HBM bandwidth on this machine: a fill (write only) and a copy of 2 GiB
     probe = {}
     big = torch.empty(1 << 28, dtype=torch.complex64, device=dev)
     big2 = torch.empty_like(big)
@@ -297,41 +431,47 @@ def main():
         torch.cuda.synchronize()
         log("bench: calibration copy of 1073741824 bytes done")
 
+    merge_desc = {"fp32": "complex64 float32 FMA", "fp16x3": "fp16 hi+lo split, 3 MFMA products",
+                  "bf16x3": "bf16 hi+lo split, 3 MFMA products",
+                  "fp16x2": "fp16, high-qubit factor split, 2 MFMA products"}[used]
     result = {
         "metric": "full-state amps/s merged; cut vs uncut wall-clock at q=28, 1-F<=1e-6",
         "value": (1 << Q) / (ms_step * 1e-3),
         "unit": "amps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64", "data": "synthetic",
+        "dtype": f"c64 state; merge {used} ({merge_desc}, fp32 accumulate)", "data": "synthetic",
         "config": {"workload": f"brickwork q={Q} n={NSEG} ({sizes[0]}+{sizes[1]}) d={D} c_total={CTOTAL} K={K}",
-                   "q": Q, "d": D, "n_seg": NSEG, "c_total": CTOTAL, "seed": SEED, "merge_precision": prec},
+                   "q": Q, "d": D, "n_seg": NSEG, "c_total": CTOTAL, "seed": SEED,
+                   "merge_precision": f"{prec} -> {used}", "merge_gemm_variant": variant,
+                   "step": "host cut_plan + graph rebind + one HIP graph replay (simulation and merge)"},
         "stages_ms": {"pre": t_pre_ms, "sub": float(np.mean(t_sub)), "merge": merge_ms,
-                      "uncut": t_orig, "uncut_wall": t_orig_wall,
-                      "note": "sub/merge from separate steps with every kernel timed"},
+                      "uncut": t_orig, "uncut_wall": t_orig_wall, "direct_launch_step": direct_ms,
+                      "note": "sub/merge from separate direct-launch steps with every kernel timed"},
         "merge_amps_per_s": (1 << Q) / (merge_ms * 1e-3),
         "cut_vs_uncut": {"speedup": t_orig / ms_step, "one_minus_F": one_minus_f,
                          "norm_drift": abs(stats["norm2"] - 1.0), "max_abs": stats["max_abs"]},
         "roofline": roof,
         "roofline_sim": roof_sim,
+        "fp16x2_opt_in": {"ms_per_step_direct": x2_ms, "merge_gemm_ms": x2_k_ms,
+                          "gemm_frac": merge_bytes / (x2_k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "note": "opt-in arithmetic (low-qubit factor rounded once to fp16), not the default"},
         "kernels_ms": kernels_ms,
         "hbm_probe": probe,
         "kernel_launches_per_step": kernel_launches,
     }
 
-    if not args.no_cpu:
-        log("bench: timing the CPU oracle on a bounded sample")
-        cb, cuts, states = cpu_baseline(gates, sizes)
+    if cb is not None:
         result["cpu_baseline"] = cb
         from oracle import cutting
         rng = np.random.default_rng(0)
         xs = sorted(set(int(x) for x in rng.integers(0, 1 << Q, size=256)))
         want = cutting.amplitudes(xs, sizes, cuts, states)
-        got = psi[torch.tensor(xs, device=dev)].cpu().numpy().astype(np.complex128)
+        got = cut_state_check[torch.tensor(xs, device=dev)].cpu().numpy().astype(np.complex128)
         result["oracle_sampled_max_abs"] = float(np.max(np.abs(got - want)))
         result["oracle_sampled_n"] = len(xs)
-        log(f"bench: cpu oracle {cb['value']:.3e} amps/s (uncut estimate {cb['seconds']['uncut_est']:.0f} s); "
-            f"sampled max-abs vs oracle {result['oracle_sampled_max_abs']:.3e}")
+        log(f"bench: graph-replayed state, sampled max-abs vs oracle {result['oracle_sampled_max_abs']:.3e}")
+    graph.free()
     print(json.dumps(result))
 
 

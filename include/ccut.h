@@ -247,13 +247,15 @@ int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint64_t arena_b
 
 /* Merge precisions (Algorithm 3 arithmetic). */
 enum {
-  CCUT_PREC_AUTO = -1,   /* by term count: FP32 below K = 8 (or the autotuned threshold), else FP16X2 */
+  CCUT_PREC_AUTO = -1,   /* by term count: FP32 below K = 8 (or the autotuned threshold), else the
+                            plan's split MFMA arithmetic: FP16X3 unless the autotuner found BF16X3
+                            faster, or FP16X2 where ccut_plan_set_auto_precision asks for it */
   CCUT_PREC_FP32 = 0,    /* complex64 factors, float32 FMA accumulation (vector ALUs) */
   CCUT_PREC_BF16X3 = 1,  /* factors split hi + lo in bfloat16, hi.hi + hi.lo + lo.hi on MFMA, float32 accumulate */
   CCUT_PREC_FP16X3 = 2,  /* as BF16X3 with float16 halves and power-of-two pre-scaling */
   CCUT_PREC_BF16 = 3,    /* unsplit bfloat16 on MFMA: a low-accuracy control */
   CCUT_PREC_FP16X2 = 4   /* float16, only the high-qubit factor split: Lhi.R + Llo.R (R rounded once);
-                            relative error of R <= 2^-11, 1 - F ~ 1e-7 */
+                            relative error of R <= 2^-11, 1 - F ~ 1e-7; explicit opt-in only */
 };
 
 /*
@@ -347,7 +349,7 @@ int ccut_expectation_pauli(ccut_plan_t* plan, const void* d_arena, uint64_t aren
  *                at most grid_cap workgroups looping over all blocks of all variants
  *   per_variant  0: one launch covers every variant of every segment (per pass);
  *                1: one launch per (segment, variant), the unbatched reference
- *   mfma_min_terms  CCUT_PREC_AUTO merges on MFMA (FP16X2) from this term
+ *   mfma_min_terms  CCUT_PREC_AUTO merges on MFMA (ccut_plan_get_auto_precision) from this term
  *                count K (-1: library default 8)
  * Results do not depend on the configuration.  ccut_plan_get_launch returns
  * (threads, grid_cap, per_variant, mfma_min_terms).  Host-only.
@@ -367,6 +369,17 @@ int ccut_plan_get_launch(const ccut_plan_t* plan, int32_t out[4]);
 int ccut_plan_stats(const ccut_plan_t* plan, int64_t out[8]);
 
 /*
+ * Work the plan's simulation launches execute (host-only), summed over every
+ * job of the current schedule (flat or prefix tree, at the current block size):
+ * out[0] dense 2x2 gate applications x amplitudes, out[1] diagonal ones (phases,
+ * scalars), out[2] permutation and sign ops (CX, CZ), out[3] amplitudes moved
+ * between HBM (or L2) and LDS (a pass that starts from |0...0> only writes),
+ * out[4] the dense gate applications x amplitudes of the flat schedule (every
+ * fused gate of a segment on every variant), for comparison.
+ */
+int ccut_plan_work(const ccut_plan_t* plan, double out[5]);
+
+/*
  * Variant and grid of the MFMA merge GEMM.  epilogue 0..3 are tiled kernels:
  * bit 0 set transposes 16-row slabs through LDS into 16-byte row stores
  * (clear: each lane stores its accumulators directly); bit 1 set uses 64 x 256
@@ -383,6 +396,16 @@ int ccut_plan_stats(const ccut_plan_t* plan, int64_t out[8]);
 int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap);
 /* The current (epilogue, grid_cap) of a plan (host-only). */
 int ccut_plan_get_merge(const ccut_plan_t* plan, int32_t out[2]);
+
+/*
+ * The MFMA arithmetic CCUT_PREC_AUTO uses for merge stages at or above the
+ * plan's term threshold: CCUT_PREC_FP16X3 (default), CCUT_PREC_BF16X3, or
+ * CCUT_PREC_FP16X2 as an explicit opt-in (its max-abs error is larger: the
+ * low-qubit factor is rounded once to float16).  ccut_autotune sets it to the
+ * faster of the two fully split arithmetics.  Host-only.  Errors: CCUT_EINVAL.
+ */
+int ccut_plan_set_auto_precision(ccut_plan_t* plan, int32_t precision);
+int ccut_plan_get_auto_precision(const ccut_plan_t* plan, int32_t* out);
 
 /* Gate arithmetic of the state-vector simulation (Algorithm 2 and the uncut baseline). */
 enum {
@@ -449,12 +472,13 @@ int ccut_plan_get_prefix_start(const ccut_plan_t* plan, int32_t* out);
  * block sizes (whole segment, 2 and 4 blocks per state; sizes whose tables do
  * not fit arena_bytes are skipped) x workgroup sizes x persistent grid sizes,
  * and the merge with the
- * float32 kernel against the split-precision MFMA GEMM over its variants and
- * grids (median of `reps` runs, HIP events on `stream`; every merge run follows
+ * float32 kernel against the fully split MFMA GEMM (FP16X3 and BF16X3) over its
+ * variants and grids (median of `reps` runs, HIP events on `stream`; every merge run follows
  * an untimed simulation, as in the pipeline, and each GEMM candidate is timed in
  * a forward and a backward sweep, median of max(reps, 7) runs each, keeping the
- * better median, since short merges see clock drift; the plan's current GEMM
- * variant and grid are kept unless another is more than 2 % faster), applies the fastest
+ * better median, since short merges see clock drift; the plan's current split
+ * arithmetic, GEMM variant and grid are kept unless another is more than 2 % faster),
+ * applies the fastest (AUTO then merges in the chosen split arithmetic)
  * to the plan and records it in a process-wide cache keyed by (architecture,
  * plan shape); later plans of the same shape start from it (their tables, and so
  * their info.arena_bytes, can be larger than the tuning plan's: size an arena
@@ -463,8 +487,9 @@ int ccut_plan_get_prefix_start(const ccut_plan_t* plan, int32_t* out);
  * untuned ones to float32 rounding (not bit for bit).  Overwrites the arena and
  * d_psi.  *best_ms (nullable) receives the tuned simulation + merge time.
  * ccut_autotune_save / _load write and read the cache as text (one
- * "key threads grid_cap mfma_min_terms epilogue merge_grid block_bits prefix"
- * line per entry; prefix 0 = off, 1 + L = on with the tree from level L).
+ * "key threads grid_cap mfma_min_terms epilogue merge_grid block_bits prefix
+ * mfma_mode" line per entry; prefix 0 = off, 1 + L = on with the tree from level
+ * L; mfma_mode is AUTO's split arithmetic and may be absent, meaning FP16X3).
  * Errors: CCUT_EINVAL, CCUT_ENOSPC, CCUT_EHIP.
  */
 int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* d_psi, uint64_t psi_bytes,
@@ -474,18 +499,32 @@ int ccut_autotune_load(const char* path);
 
 /*
  * HIP graph of a plan's whole device pipeline (subcircuit simulation, then
- * merge at `precision`) captured on `stream` (must not be the default
- * stream).  The plan is prepared first, so replays copy nothing from the
- * host; the arena and d_psi addresses are baked into the graph and must stay
- * valid.  ccut_graph_launch replays it on any stream.  The graph does not own
- * the plan: keep the plan alive while the graph is used.
- * Errors: CCUT_EINVAL, CCUT_ENOSPC, CCUT_EHIP.
+ * merge at `precision`; Algorithms 2 and 3 as one replayable unit) captured on
+ * `stream` (must not be the default stream).  The graph owns a device copy of
+ * the plan's tables, made at capture, so replays copy nothing from the host;
+ * the plan can be freed once the graph exists.  The arena and d_psi addresses
+ * are baked into the graph and must stay valid.  ccut_graph_launch replays it
+ * on any stream.  Do not use the plan from another thread while it is captured.
+ * Errors: CCUT_EINVAL, CCUT_ENOSPC, CCUT_ENOMEM, CCUT_EHIP.
  */
 typedef struct ccut_graph ccut_graph_t;
 int ccut_graph_create(ccut_plan_t* plan, void* d_arena, uint64_t arena_bytes, void* d_psi, uint64_t psi_bytes,
                       int32_t precision, void* stream, ccut_graph_t** out);
 int ccut_graph_launch(ccut_graph_t* graph, void* stream);
 void ccut_graph_free(ccut_graph_t* graph);
+
+/*
+ * Points a graph at another plan of the same launch layout (same circuit shape,
+ * segment sizes, cut positions and fused program lengths, launch configuration
+ * and table layout; typically the same circuit family with other angles):
+ * enqueues on `stream` a copy of that plan's tables into the graph's table copy.
+ * Replays on `stream` after this call compute the new plan's pipeline; a replay
+ * enqueued earlier on `stream` still reads the old tables (stream order), so
+ * rebind and launch on one stream.  The plan may be freed after the call.
+ * Errors: CCUT_EINVAL (NULL, other device, or a different launch layout),
+ * CCUT_EHIP.
+ */
+int ccut_graph_rebind(ccut_graph_t* graph, const ccut_plan_t* plan, void* stream);
 
 /* ------------------------------------------------------------ cost model */
 /*

@@ -118,6 +118,8 @@ def _load():
         "ccut_plan_get_launch": [vp, ctypes.POINTER(i32)],
         "ccut_plan_set_merge": [vp, i32, i32],
         "ccut_plan_get_merge": [vp, ctypes.POINTER(i32)],
+        "ccut_plan_set_auto_precision": [vp, i32],
+        "ccut_plan_get_auto_precision": [vp, ctypes.POINTER(i32)],
         "ccut_plan_set_block_bits": [vp, i32],
         "ccut_plan_set_sim_precision": [vp, i32],
         "ccut_plan_set_prefix_sharing": [vp, i32],
@@ -127,11 +129,13 @@ def _load():
         "ccut_plan_get_sim_precision": [vp, ctypes.POINTER(i32)],
         "ccut_plan_get_block_bits": [vp, ctypes.POINTER(i32)],
         "ccut_plan_stats": [vp, ctypes.POINTER(i64)],
+        "ccut_plan_work": [vp, ctypes.POINTER(ctypes.c_double)],
         "ccut_autotune": [vp, vp, u64, vp, u64, i32, vp, dp],
         "ccut_autotune_save": [ctypes.c_char_p],
         "ccut_autotune_load": [ctypes.c_char_p],
         "ccut_graph_create": [vp, vp, u64, vp, u64, i32, vp, ctypes.POINTER(vp)],
         "ccut_graph_launch": [vp, vp],
+        "ccut_graph_rebind": [vp, vp, vp],
     }.items():
         fn = getattr(lib, name)
         fn.argtypes = args
@@ -454,6 +458,26 @@ def plan_get_merge(plan: Plan) -> dict:
     return {"variant": out[0], "grid_cap": out[1]}
 
 
+def plan_set_auto_precision(plan: Plan, precision) -> None:
+    """Split arithmetic CCUT_PREC_AUTO uses on MFMA: "fp16x3", "bf16x3" or (opt-in) "fp16x2"."""
+    p = PRECISIONS[precision] if isinstance(precision, str) else precision
+    _check(_lib.ccut_plan_set_auto_precision(plan.handle, p))
+
+
+def plan_get_auto_precision(plan: Plan) -> str:
+    out = ctypes.c_int32()
+    _check(_lib.ccut_plan_get_auto_precision(plan.handle, ctypes.byref(out)))
+    return {v: k for k, v in PRECISIONS.items()}[out.value]
+
+
+def resolved_precision(plan: Plan, precision, k: int) -> str:
+    """The arithmetic merge_full_state runs for a stage of k terms under `precision`."""
+    if precision not in ("auto", PREC_AUTO):
+        return precision if isinstance(precision, str) else {v: n for n, v in PRECISIONS.items()}[precision]
+    kmin = plan_get_launch(plan)["mfma_min_terms"]
+    return plan_get_auto_precision(plan) if k >= (kmin if kmin >= 0 else 8) else "fp32"
+
+
 def plan_set_block_bits(plan: Plan, bits: int) -> None:
     """LDS block size of the simulation (2^bits amplitudes; 0 = automatic)."""
     _check(_lib.ccut_plan_set_block_bits(plan.handle, int(bits)))
@@ -509,6 +533,14 @@ def plan_stats(plan: Plan) -> dict:
     return dict(zip(keys, out[:]))
 
 
+def plan_work(plan: Plan) -> dict:
+    """Work the simulation launches execute under the plan's current schedule."""
+    out = (ctypes.c_double * 5)()
+    _check(_lib.ccut_plan_work(plan.handle, out))
+    return {"dense_amp_ops": out[0], "diag_amp_ops": out[1], "perm_amp_ops": out[2],
+            "amps_moved": out[3], "flat_dense_amp_ops": out[4]}
+
+
 def plan_get_launch(plan: Plan) -> dict:
     out = (ctypes.c_int32 * 4)()
     _check(_lib.ccut_plan_get_launch(plan.handle, out))
@@ -541,7 +573,10 @@ class Graph:
         _check(_lib.ccut_graph_create(plan.handle, _ptr(arena), _nbytes(arena, arena_bytes), _ptr(psi),
                                       _nbytes(psi, psi_bytes), prec, _stream(stream), ctypes.byref(h)))
         self._h = h
-        self.plan = plan   # the graph reads the plan's device tables
+
+    def rebind(self, plan: Plan, stream=None) -> None:
+        """Next replays on `stream` run `plan` (same launch layout as the captured plan)."""
+        _check(_lib.ccut_graph_rebind(self._h, plan.handle, _stream(stream)))
 
     def launch(self, stream=None) -> None:
         _check(_lib.ccut_graph_launch(self._h, _stream(stream)))

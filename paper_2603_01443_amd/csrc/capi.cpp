@@ -331,7 +331,7 @@ extern "C" int ccut_merge_full_state(ccut_plan_t* plan, void* d_arena, uint64_t 
     int mode = precision;
     if (mode == CCUT_PREC_AUTO) {
       const int kmin = plan->auto_mfma_min_k >= 0 ? plan->auto_mfma_min_k : MFMA_MIN_TERMS;
-      mode = st.K >= kmin ? CCUT_PREC_FP16X2 : CCUT_PREC_FP32;
+      mode = st.K >= kmin ? plan->auto_mfma_mode : CCUT_PREC_FP32;
     }
     if (mode == CCUT_PREC_FP32 || !merge_mfma_supported(st.qx, st.qy)) {
       // shapes below one MFMA tile take the float32 kernel, which is at least as accurate

@@ -82,7 +82,8 @@ struct ccut_plan {
   int sim_grid_cap = 0;      // 0: one workgroup per block; > 0: persistent grid of this size
   int sim_per_variant = 0;   // 1: one launch per (segment, variant) instead of one per pass index
   int auto_mfma_min_k = -1;  // CCUT_PREC_AUTO threshold on K (-1: library default)
-  int merge_epilogue = 1;    // MFMA merge store path: 0 direct, 1 through LDS
+  int auto_mfma_mode = CCUT_PREC_FP16X3;  // CCUT_PREC_AUTO arithmetic at and above that K
+  int merge_epilogue = 1;    // MFMA merge GEMM variant (see merge_mfma.h)
   int merge_grid_cap = 0;    // MFMA merge: 0 one workgroup per tile, > 0 persistent grid
   int sim_precision = CCUT_SIM_FP16X3;  // register-stage gate groups: split-float16 MFMA or float32 VALU
 };
@@ -101,6 +102,9 @@ int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector
                 std::vector<KOp>& kops, std::vector<GroupRef>& grefs);
 int gate_matrix(const ccut_gate_t& g, cd m[4]);
 void release_device(DeviceTables& t);
+// Copies a table image to a new device allocation (synchronous).
+int upload_tables(DeviceTables& t, const std::vector<unsigned char>& img, uint64_t o_ops, uint64_t o_pass,
+                  uint64_t o_stage, uint64_t o_jobs, uint64_t o_w, uint64_t o_grefs);
 // Packs the tables into one image with 256-byte aligned sections.
 void pack_image(ccut_plan* P);
 // Applies a cached autotuned launch configuration to a new plan, if any.

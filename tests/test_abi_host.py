@@ -117,14 +117,30 @@ def test_error_codes():
 
 
 def test_merge_variant_range():
-    """Merge GEMM variants 0..3 are accepted and read back; 4 and negative grids are not."""
+    """Merge GEMM variants 0..4 are accepted and read back; 5 and negative grids are not."""
     plan = ccut.cut_plan(16, brickwork(16, 4, 2, 3, seed=1), 2)
-    for v in range(4):
+    for v in range(5):
         ccut.plan_set_merge(plan, v, 256)
         assert ccut.plan_get_merge(plan) == {"variant": v, "grid_cap": 256}
-    for v, cap in ((4, 0), (-1, 0), (3, -1)):
+    for v, cap in ((5, 0), (-1, 0), (3, -1)):
         with pytest.raises(ccut.CcutError) as e:
             ccut.plan_set_merge(plan, v, cap)
+        assert e.value.code == ccut.EINVAL
+
+
+def test_auto_precision_is_fully_split_by_default():
+    """AUTO merges in a fully split arithmetic (fp16x3) unless told otherwise; fp16x2 is
+    an explicit opt-in, and only MFMA split arithmetics are accepted."""
+    plan = ccut.cut_plan(16, brickwork(16, 4, 2, 3, seed=1), 2)
+    assert ccut.plan_get_auto_precision(plan) == "fp16x3"
+    assert ccut.resolved_precision(plan, "auto", 8) == "fp16x3"
+    assert ccut.resolved_precision(plan, "auto", 4) == "fp32"
+    for p in ("bf16x3", "fp16x2", "fp16x3"):
+        ccut.plan_set_auto_precision(plan, p)
+        assert ccut.plan_get_auto_precision(plan) == p
+    for p in ("fp32", "bf16", "auto"):
+        with pytest.raises(ccut.CcutError) as e:
+            ccut.plan_set_auto_precision(plan, p)
         assert e.value.code == ccut.EINVAL
 
 

@@ -65,6 +65,39 @@ def test_graph_replay_matches_direct(lib):
     graph.free()
 
 
+def test_graph_rebind_runs_other_plans(lib):
+    """One captured graph replays the pipelines of other plans of the same layout (the same
+    brickwork family with other angles) after ccut_graph_rebind: each replay's state is
+    bit-identical to that plan's direct launches, with eager work and synchronizations
+    between replays; a plan of another shape is refused."""
+    ccut, pipeline = lib
+    q, n, d, c = 20, 2, 10, 6
+    runs = {seed: pipeline.CutRun(q, brickwork(q, d, n, c, seed=seed), n) for seed in (2, 3, 4)}
+    base = runs[2]
+    want = {}
+    for seed, r in runs.items():   # direct launches, all in the base run's buffers
+        ccut.simulate_subcircuits(r.plan, base.arena, stream=torch.cuda.current_stream())
+        ccut.merge_full_state(r.plan, base.arena, base.psi, "auto", stream=torch.cuda.current_stream())
+        want[seed] = base.psi.clone()
+    assert not torch.equal(want[2], want[3])
+    s = torch.cuda.Stream()
+    graph = ccut.Graph(base.plan, base.arena, base.psi, "auto", stream=s)
+    for rep, seed in enumerate((3, 4, 2, 4)):
+        base.psi.zero_()
+        scratch = pipeline.uncut(16, brickwork(16, 4, 2, 1, seed=rep))   # eager work between replays
+        torch.cuda.synchronize()
+        graph.rebind(runs[seed].plan, s)
+        graph.launch(s)
+        s.synchronize()
+        assert torch.equal(torch.view_as_real(base.psi), torch.view_as_real(want[seed])), (rep, seed)
+        del scratch
+    other = ccut.cut_plan(q, ccut.gate_array(brickwork(q, d, n, c - 2, seed=2)), n)
+    with pytest.raises(ccut.CcutError) as e:
+        graph.rebind(other, s)
+    assert e.value.code == ccut.EINVAL
+    graph.free()
+
+
 def test_autotune_keeps_results_and_caches(lib, tmp_path):
     ccut, pipeline = lib
     q, n = 22, 2
@@ -91,10 +124,13 @@ def test_autotune_keeps_results_and_caches(lib, tmp_path):
     # every saved line must load back: rewrite the entry with other threads and a tree
     # from level 5 (prefix field 6) and check that a fresh plan takes both
     lines = [ln.split() for ln in open(path) if not ln.startswith("#")]
-    assert len(lines) == 1 and len(lines[0]) == 8
+    assert len(lines) == 1 and len(lines[0]) == 9
     key, fields = lines[0][0], lines[0][1:]
+    assert ccut.plan_get_auto_precision(fresh) == ccut.plan_get_auto_precision(run.plan)
+    assert int(fields[7]) == ccut.PRECISIONS[ccut.plan_get_auto_precision(run.plan)]
     fields[0] = "256" if fields[0] != "256" else "1024"
     fields[6] = "6"
+    fields[7] = str(ccut.PREC_BF16X3 if int(fields[7]) != ccut.PREC_BF16X3 else ccut.PREC_FP16X3)
     edited = str(tmp_path / "edited.txt")
     with open(edited, "w") as f:
         f.write(key + " " + " ".join(fields) + "\n")
@@ -102,6 +138,13 @@ def test_autotune_keeps_results_and_caches(lib, tmp_path):
     fresh = ccut.cut_plan(q, g, n)
     assert ccut.plan_get_launch(fresh)["threads"] == int(fields[0])
     assert ccut.plan_get_prefix_sharing(fresh) and ccut.plan_get_prefix_start(fresh) == 5
+    assert ccut.PRECISIONS[ccut.plan_get_auto_precision(fresh)] == int(fields[7])
+    # a line written before the split-arithmetic field existed still loads (fp16x3 then)
+    old = str(tmp_path / "old.txt")
+    with open(old, "w") as f:
+        f.write(key + " " + " ".join(fields[:7]) + "\n")
+    ccut.autotune_load(old)
+    assert ccut.plan_get_auto_precision(ccut.cut_plan(q, g, n)) == "fp16x3"
 
 
 @pytest.mark.parametrize("prec,c", [("bf16x3", 6), ("fp16x3", 6), ("bf16", 6), ("fp16x2", 6),
