@@ -7,14 +7,13 @@ qubits, two equal segments of 14, depth d = 20, c_total = 6 cut CZs
 Eq. (runtime_decomp): cut_plan on the host (T_pre), every subcircuit variant
 (T_sub) and the merge into the 2^28 complex64 state (T_merge), with the merge
 in the library's default arithmetic (AUTO: the fully split fp16 hi + lo
-product on MFMA at this term count).  The device part of a step is one HIP
-graph replay: the graph is captured once, and every step's freshly built plan
-is rebound into it (its tables copied into the graph's table buffer) before
-the replay.  value = 2^q amplitudes per step / seconds per step.
+product on MFMA at this term count), launched directly on one stream.
+value = 2^q amplitudes per step / seconds per step.  Within the timed steps
+only the merge GEMM (the roofline kernel) is bracketed by HIP events.
 
-Beside the steps it times the merge GEMM with HIP events in a second run of
-direct-launch steps (the roofline kernel), the same steps with the fp16x2
-opt-in merge, the uncut simulation of the same circuit (T_orig), checks the
+Beside the steps it times the same steps as HIP graph replays (captured once;
+each step's fresh plan rebound into the graph), the fp16x2 opt-in merge,
+the uncut simulation of the same circuit (T_orig), checks the
 cut state against the uncut state (1 - F, float64 reductions) and against
 oracle amplitudes at sampled indices, and times the complex128 CPU oracle on
 a bounded sample of the same workload (cpu_baseline), at one thread and on
@@ -39,7 +38,9 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the merge GEMM from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by
 # a 1 GiB copy (2.0 x FETCH + 1.0 x WRITE), keyed by the kernel the bench line names.  Only valid
 # for the kernel revision the counters were taken on: remove an entry whenever that kernel changes.
-MEASURED_TRAFFIC: dict = {}
+MEASURED_TRAFFIC = {
+    "merge_gemm (fp16x3, v4)": 2.2373e+09,   # profiles/merge_gemm_fp16x3_q28_k64_counters.txt
+}
 FP32_PEAK_TFLOPS = 157.3
 # float32 flops per amplitude of a fused dense 2x2 gate (two complex multiply-adds, FMA = 2 flops)
 # and of a diagonal phase (one complex multiply)
@@ -200,6 +201,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing and sampled check")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (for scaling PMC byte counters)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotune cache file: loaded instead of tuning if it exists, else written after tuning "
+                         "(profiled runs reuse the configuration of an unprofiled one)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of "
@@ -232,6 +236,9 @@ def main():
     stream = torch.cuda.Stream()   # graph capture needs a non-default stream (default priority)
     torch.cuda.set_stream(stream)
     garr = ccut.gate_array(gates)
+    cached = bool(args.tune_cache) and os.path.exists(args.tune_cache)
+    if cached:
+        ccut.autotune_load(args.tune_cache)   # plans of this shape start from the cached configuration
     plan0 = ccut.cut_plan(Q, garr, NSEG, sizes)
     info = plan0.info()
     K = info["n_terms"]
@@ -242,9 +249,16 @@ def main():
         f"arena={info['arena_bytes'] / 2**20:.1f} MiB precision={prec}")
 
     # one autotuning pass (outside the timed region); plans of this shape reuse its choice
-    tuned_ms = ccut.autotune(plan0, arena, psi, reps=3, stream=stream)
-    log(f"bench: autotuned launch {ccut.plan_get_launch(plan0)}, merge {ccut.plan_get_merge(plan0)} in "
-        f"{ccut.plan_get_auto_precision(plan0)} ({tuned_ms:.3f} ms)")
+    if cached:
+        log(f"bench: configuration from {args.tune_cache}")
+    else:
+        tuned_ms = ccut.autotune(plan0, arena, psi, reps=3, stream=stream)
+        log(f"bench: autotuned ({tuned_ms:.3f} ms)")
+        if args.tune_cache:
+            ccut.autotune_save(args.tune_cache)
+    log(f"bench: launch {ccut.plan_get_launch(plan0)}, block bits {ccut.plan_get_block_bits(plan0)}, prefix "
+        f"{ccut.plan_get_prefix_sharing(plan0)} from {ccut.plan_get_prefix_start(plan0)}, merge "
+        f"{ccut.plan_get_merge(plan0)} in {ccut.plan_get_auto_precision(plan0)}")
     # plans built from now on start from the tuned configuration, whose tables may
     # need more arena than the untuned plan reserved: size the arena for them
     need = ccut.cut_plan(Q, garr, NSEG, sizes).info()["arena_bytes"]
@@ -257,11 +271,14 @@ def main():
     t_pre = []
     keep = []
 
-    # ---- direct-launch steps: the roofline kernel bracketed by HIP events on its stream
+    # ---- the timed steps: host plan, simulation, merge (direct launches on one stream); only the
+    # roofline kernel is bracketed by HIP events, on the stream it is launched on
     kname = "merge_f32" if used == "fp32" else "merge_gemm"
 
     def direct_step(precision, marks=None):
-        plan = ccut.cut_plan(Q, garr, NSEG, sizes)
+        t0 = time.perf_counter()
+        plan = ccut.cut_plan(Q, garr, NSEG, sizes)   # tables reach the device with the first call
+        t_pre.append(time.perf_counter() - t0)
         if marks:
             marks[0].record(stream)
         ccut.simulate_subcircuits(plan, arena, stream=stream)
@@ -270,58 +287,57 @@ def main():
         ccut.merge_full_state(plan, arena, psi, precision, stream=stream)
         if marks:
             marks[2].record(stream)
-        keep.append(plan)
+        keep.append(plan)   # freed after the timed region (freeing syncs the device)
 
-    def timed_direct(precision, kernel):
-        for _ in range(2):
+    def timed_direct(precision, kernel, warmup, steps):
+        for _ in range(warmup):
             direct_step(precision)
         torch.cuda.synchronize()
         keep.clear()
+        t_pre.clear()
         ccut.profile_reset()
         ccut.profile_mask([kernel])
         ccut.profile_enable(True)
+        torch.cuda.synchronize()
         w0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             direct_step(precision)
         torch.cuda.synchronize()
         w = time.perf_counter() - w0
         ccut.profile_enable(False)
         n, tot = ccut.profile_read()[kernel]
         keep.clear()
-        return 1e3 * w / args.steps, tot / n, n
+        return 1e3 * w / steps, tot / n, n
 
-    # first: these steps also bring clocks and memory to their steady state before the graph steps
-    direct_ms, k_ms, k_launches = timed_direct(prec, kname)
-    log(f"bench: {direct_ms:.3f} ms/step direct; {kname} ({used}) {k_ms:.4f} ms per launch")
+    log(f"bench: timing {args.steps} steps after {args.warmup} warmup steps")
+    ms_step, k_ms, k_launches = timed_direct(prec, kname, args.warmup, args.steps)
+    t_pre_ms = 1e3 * float(np.mean(t_pre))
+    cut_state_check = psi.clone()
+    log(f"bench: {ms_step:.3f} ms/step; {kname} ({used}) {k_ms:.4f} ms per launch")
 
-    # ---- the timed steps: host plan, rebind into the captured graph, one replay
+    # ---- the same steps as HIP graph replays: the graph is captured once, each step's fresh plan
+    # is rebound into it (its tables copied into the graph's table buffer), then replayed
     graph = ccut.Graph(ccut.cut_plan(Q, garr, NSEG, sizes), arena, psi, prec, stream=stream)
 
     def graph_step():
-        t0 = time.perf_counter()
         plan = ccut.cut_plan(Q, garr, NSEG, sizes)
-        t_pre.append(time.perf_counter() - t0)
         graph.rebind(plan, stream)
         graph.launch(stream)
-        keep.append(plan)   # freed after the timed region
+        keep.append(plan)
 
     for _ in range(args.warmup):
         graph_step()
     torch.cuda.synchronize()
     keep.clear()
-    t_pre.clear()
-    log(f"bench: warmup done, timing {args.steps} graph-replayed steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    w0 = time.perf_counter()
     for _ in range(args.steps):
         graph_step()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    graph_ms = 1e3 * (time.perf_counter() - w0) / args.steps
     keep.clear()
-    ms_step = 1e3 * wall / args.steps
-    t_pre_ms = 1e3 * float(np.mean(t_pre))
-    cut_state_check = psi.clone()
-    log(f"bench: {ms_step:.3f} ms/step graph-replayed")
+    graph_state_check = psi.clone()
+    graph.free()
+    log(f"bench: {graph_ms:.3f} ms/step as graph replays")
 
     # Stage breakdown on further (untimed) steps: events between stages, every kernel timed.
     nb = min(10, max(1, args.steps))
@@ -341,7 +357,7 @@ def main():
         f"{np.mean(t_merge):.3f} ms, pre {t_pre_ms:.3f} ms")
 
     # fp16x2 (opt-in: only the high-qubit factor split) on the same direct-launch steps
-    x2_ms, x2_k_ms, _ = timed_direct("fp16x2", "merge_gemm")
+    x2_ms, x2_k_ms, _ = timed_direct("fp16x2", "merge_gemm", 2, args.steps)
     log(f"bench: fp16x2 opt-in {x2_ms:.3f} ms/step direct, merge_gemm {x2_k_ms:.4f} ms")
 
     # uncut baseline on the same GPU
@@ -361,8 +377,10 @@ def main():
     t_orig = e0.elapsed_time(e1) / reps
     stats = ccut.norm_fidelity(cut_state_check, ref, Q, stream=stream)
     one_minus_f = 1.0 - stats["fidelity"]
-    log(f"bench: uncut {t_orig:.3f} ms; graph-replayed cut state vs uncut 1-F {one_minus_f:.3e}, norm drift "
-        f"{abs(stats['norm2'] - 1):.3e}, max-abs {stats['max_abs']:.3e}")
+    gstats = ccut.norm_fidelity(graph_state_check, cut_state_check, Q, stream=stream)
+    log(f"bench: uncut {t_orig:.3f} ms; cut state vs uncut 1-F {one_minus_f:.3e}, norm drift "
+        f"{abs(stats['norm2'] - 1):.3e}, max-abs {stats['max_abs']:.3e}; graph-replayed state vs direct "
+        f"max-abs {gstats['max_abs']:.1e}")
 
     merge_ms = float(np.mean(t_merge))
     merge_bytes = 8 * (1 << Q) + 8 * K * ((1 << sizes[0]) + (1 << sizes[1]))
@@ -381,8 +399,7 @@ def main():
     roof["traffic"] = MEASURED_TRAFFIC.get(roof["kernel"])
     roof["avg_ms"] = k_ms
     roof["launches_timed"] = k_launches
-    roof["timing"] = (f"HIP events around each {kname} launch on its stream, over {args.steps} direct-launch "
-                      f"steps of the same pipeline (graph replays carry no event nodes)")
+    roof["timing"] = f"HIP events around each {kname} launch on its stream, over the {args.steps} timed steps"
     roof["algorithmic_bytes"] = merge_bytes
     roof["algorithmic_flops"] = merge_flops
     # Second kernel: the subcircuit simulation, work counted as the float32 flops of the fused
@@ -444,15 +461,19 @@ def main():
         "config": {"workload": f"brickwork q={Q} n={NSEG} ({sizes[0]}+{sizes[1]}) d={D} c_total={CTOTAL} K={K}",
                    "q": Q, "d": D, "n_seg": NSEG, "c_total": CTOTAL, "seed": SEED,
                    "merge_precision": f"{prec} -> {used}", "merge_gemm_variant": variant,
-                   "step": "host cut_plan + graph rebind + one HIP graph replay (simulation and merge)"},
+                   "step": "host cut_plan + simulation + merge, direct launches on one stream"},
         "stages_ms": {"pre": t_pre_ms, "sub": float(np.mean(t_sub)), "merge": merge_ms,
-                      "uncut": t_orig, "uncut_wall": t_orig_wall, "direct_launch_step": direct_ms,
+                      "uncut": t_orig, "uncut_wall": t_orig_wall,
                       "note": "sub/merge from separate direct-launch steps with every kernel timed"},
         "merge_amps_per_s": (1 << Q) / (merge_ms * 1e-3),
         "cut_vs_uncut": {"speedup": t_orig / ms_step, "one_minus_F": one_minus_f,
                          "norm_drift": abs(stats["norm2"] - 1.0), "max_abs": stats["max_abs"]},
         "roofline": roof,
         "roofline_sim": roof_sim,
+        "graph_replay": {"ms_per_step": graph_ms,
+                         "state_max_abs_vs_direct": gstats["max_abs"],
+                         "note": "the same steps with the device part as one HIP graph replay per step (fresh plan "
+                                 "rebound into the captured graph)"},
         "fp16x2_opt_in": {"ms_per_step_direct": x2_ms, "merge_gemm_ms": x2_k_ms,
                           "gemm_frac": merge_bytes / (x2_k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "note": "opt-in arithmetic (low-qubit factor rounded once to fp16), not the default"},
@@ -470,8 +491,7 @@ def main():
         got = cut_state_check[torch.tensor(xs, device=dev)].cpu().numpy().astype(np.complex128)
         result["oracle_sampled_max_abs"] = float(np.max(np.abs(got - want)))
         result["oracle_sampled_n"] = len(xs)
-        log(f"bench: graph-replayed state, sampled max-abs vs oracle {result['oracle_sampled_max_abs']:.3e}")
-    graph.free()
+        log(f"bench: sampled max-abs vs oracle {result['oracle_sampled_max_abs']:.3e}")
     print(json.dumps(result))
 
 

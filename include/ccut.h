@@ -477,7 +477,8 @@ int ccut_plan_get_prefix_start(const ccut_plan_t* plan, int32_t* out);
  * an untimed simulation, as in the pipeline, and each GEMM candidate is timed in
  * a forward and a backward sweep, median of max(reps, 7) runs each, keeping the
  * better median, since short merges see clock drift; the plan's current split
- * arithmetic, GEMM variant and grid are kept unless another is more than 2 % faster),
+ * arithmetic, GEMM variant and grid are kept unless another is more than 2 % faster;
+ * BF16X3, the less accurate split, is taken only if more than 5 % faster than FP16X3),
  * applies the fastest (AUTO then merges in the chosen split arithmetic)
  * to the plan and records it in a process-wide cache keyed by (architecture,
  * plan shape); later plans of the same shape start from it (their tables, and so

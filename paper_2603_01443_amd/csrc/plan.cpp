@@ -221,7 +221,7 @@ int build_sim_tables(ccut_plan* P, bool first) {
   }
 
   pack_image(P);
-  if (P->dev.blob) {  // a captured graph may still read the old copy: keep it until the plan is freed
+  if (P->dev.blob) {  // launches already enqueued may still read the old copy: keep it until the plan is freed
     P->retired.push_back(P->dev);
     P->dev = DeviceTables();
   }

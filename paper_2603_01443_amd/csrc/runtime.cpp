@@ -459,13 +459,22 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
       if (!rc) tbest[i] = std::min(tbest[i], t);
     }
   }
+  // fp16x3 keeps ~22 significant bits against bf16x3's ~16: bf16x3 must be more than 5 % faster
+  auto weight = [&](size_t i) { return tbest[i] * (cands[i][0] == CCUT_PREC_BF16X3 ? 1.05f : 1.0f); };
+  float wbest = 1e30f;
   for (size_t i = 0; i < cands.size() && !rc; ++i)
-    if (tbest[i] < tmf) { tmf = tbest[i]; best_mode = cands[i][0]; best_epi = cands[i][1]; best_grid = cands[i][2]; }
+    if (weight(i) < wbest) {
+      wbest = weight(i);
+      tmf = tbest[i];
+      best_mode = cands[i][0];
+      best_epi = cands[i][1];
+      best_grid = cands[i][2];
+    }
   // the plan's own choice stays unless another is clearly faster: near ties would
   // otherwise flip with run-to-run noise
   for (size_t i = 0; i < cands.size() && !rc; ++i)
     if (cands[i][0] == saved_mode && cands[i][1] == saved_epi && cands[i][2] == saved_grid &&
-        tbest[i] <= 1.02f * tmf) {
+        weight(i) <= 1.02f * wbest) {
       tmf = tbest[i];
       best_mode = saved_mode;
       best_epi = saved_epi;

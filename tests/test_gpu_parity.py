@@ -455,6 +455,57 @@ def test_bench_config_split_precision(lib):
         assert 1 - st["fidelity"] <= 1e-6
 
 
+@pytest.mark.parametrize("d", [10, 20])
+def test_bench_config_tuned(lib, d):
+    """The measured workload in the launch configuration the bench runs: simulation groups
+    as split-fp16 MFMA, 2^12-amplitude blocks (several LDS passes per 14-qubit state), the
+    prefix tree from level c - 1 = 5, 512-thread workgroups, the R-stationary merge GEMM and
+    AUTO = fp16x3; then the configuration the autotuner picks on this device.  Both at
+    q = 28 (14 + 14), c_total = 6, seed 0: >= 400 sampled amplitudes against the oracle's
+    plain sum at the split-merge bar, 1 - F <= 1e-6 and unit norm against the uncut state."""
+    ccut, pipeline = lib
+    q, n, c = 28, 2, 6
+    sizes = [14, 14]
+    g = brickwork(q, d, n, c, seed=0)
+    ocuts = cutting.find_cuts(q, g, sizes)
+    ostates = cutting.variant_states(q, g, sizes, ocuts)
+    rng = np.random.default_rng(28 + d)
+    xs = sorted(set(int(x) for x in rng.integers(0, 2 ** q, size=420)) | {0, 2 ** q - 1})
+    want = cutting.amplitudes(xs, sizes, ocuts, ostates)
+    ref = pipeline.uncut(q, g)
+    run = pipeline.CutRun(q, g, n)
+    stream = torch.cuda.current_stream()
+
+    def check(label):
+        need = run.plan.info()["arena_bytes"]     # other block sizes need other table room
+        if need > run.arena.numel():
+            run.arena = torch.empty(need, dtype=torch.uint8, device=run.psi.device)
+        psi = run.run("auto")
+        got = to_np(psi[torch.tensor(xs, device=psi.device)])
+        err = np.max(np.abs(got - want))
+        st = ccut.norm_fidelity(psi, ref, q, stream=stream)
+        print(f"q28 d{d} {label}: sampled max-abs {err:.3e} (bar {split_tol(q):.1e}), 1-F vs uncut "
+              f"{1 - st['fidelity']:.3e}, norm drift {abs(st['norm2'] - 1):.2e}", flush=True)
+        assert len(xs) >= 400
+        assert err <= split_tol(q), label
+        assert 1 - st["fidelity"] <= 1e-6, label
+        assert abs(st["norm2"] - 1) < 1e-5, label
+
+    ccut.plan_set_sim_precision(run.plan, "fp16x3")
+    ccut.plan_set_block_bits(run.plan, 12)
+    ccut.plan_set_prefix_sharing(run.plan, 1)
+    ccut.plan_set_prefix_start(run.plan, c - 1)
+    ccut.plan_set_launch(run.plan, threads=512)
+    ccut.plan_set_merge(run.plan, 4, 0)
+    assert ccut.plan_get_auto_precision(run.plan) == "fp16x3"
+    assert ccut.plan_get_block_bits(run.plan) == 12 and ccut.plan_get_prefix_start(run.plan) == c - 1
+    assert ccut.plan_stats(run.plan)["passes"] > 2      # 2^14 states in 2^12 blocks: multi-pass
+    check("bench configuration")
+    ccut.autotune(run.plan, run.arena, run.psi, reps=2, stream=stream)
+    check(f"autotuned {ccut.plan_get_launch(run.plan)} merge {ccut.plan_get_merge(run.plan)} "
+          f"{ccut.plan_get_auto_precision(run.plan)}")
+
+
 def absolute_term_sums(xs, sizes, cuts, states):
     """T[x] = sum over the combinations m of |alpha_m| prod_i |psi_i^(m)[x_i]|: the bound on
     every sum the merge forms for amplitude x, before cancellation."""
