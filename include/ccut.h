@@ -545,15 +545,21 @@ int ccut_threshold_ctotal(int32_t q, int32_t n, double* bound);
 int ccut_speedup_margin(int32_t q, int32_t n, const int32_t* cuts_per_boundary, double* margin);
 
 /*
- * The learned cost model (not part of the paper): a 4-64-64-3 tanh MLP,
- * CCUT_MLP_PARAMS float32 parameters laid out W1[4][64], b1[64], W2[64][64],
+ * The learned cost model (not part of the paper): an 8-64-64-3 tanh MLP,
+ * CCUT_MLP_PARAMS float32 parameters laid out W1[8][64], b1[64], W2[64][64],
  * b2[64], W3[64][3], b3[3], mapping features of (q, d, n, c_total) to
  * ln T_pre, ln T_sub, ln T_merge in seconds (an uncut run is the row n = 1,
  * c_total = 0 with T_orig in the T_sub slot).
  *
- * ccut_cost_features: the 4 input features (host):
- *   ((q - 24) / 8, log2 d - log2 20, n - 3, (c_total - 4) / 4).
- * ccut_mlp_predict: d_y[rows][3] = net(d_x[rows][4]) on the device.
+ * ccut_cost_features: the 8 input features (host), all functions of
+ * (q, d, n, c_total) for equal blocks and cuts spread evenly over the n - 1
+ * boundaries: (q - 24) / 8, log2 d - log2 20, n - 3, (c_total - 4) / 4, then
+ * the cost terms of Table I: (log2 N_sub - 6) / 4 with N_sub = sum_i 2^{c_i},
+ * (q_max - 12) / 4 with q_max = ceil(q / n), (log2 N_sub + q_max + log2 d - 24) / 6
+ * (subcircuit stage, N_sub 2^{q_max} d) and (c_total + q - 30) / 6 (merge,
+ * 2^{c_total} terms over 2^q amplitudes).  Uncut: n = 1, c_total = 0,
+ * N_sub = 1, q_max = q.
+ * ccut_mlp_predict: d_y[rows][3] = net(d_x[rows][8]) on the device.
  * ccut_mlp_grad: mean-squared-error loss against d_t[rows][3] (written to
  *   host *loss) and its gradient d_grad[CCUT_MLP_PARAMS]; synchronous.
  * ccut_mlp_train: `epochs` full-batch Adam steps (lr, betas 0.9 / 0.999,
@@ -564,8 +570,8 @@ int ccut_speedup_margin(int32_t q, int32_t n, const int32_t* cuts_per_boundary, 
  * All d_ pointers are device memory owned by the caller.
  * Errors: CCUT_EINVAL, CCUT_ENOSPC (work buffer), CCUT_EHIP.
  */
-#define CCUT_MLP_PARAMS 4675
-int ccut_cost_features(int32_t q, int32_t d, int32_t n, int32_t c_total, float out[4]);
+#define CCUT_MLP_PARAMS 4931
+int ccut_cost_features(int32_t q, int32_t d, int32_t n, int32_t c_total, float out[8]);
 int ccut_mlp_work_bytes(int64_t rows, int32_t epochs, uint64_t* bytes);
 int ccut_mlp_predict(const float* d_params, const float* d_x, int64_t rows, float* d_y, void* stream);
 int ccut_mlp_grad(const float* d_params, const float* d_x, const float* d_t, int64_t rows, void* d_work,

@@ -20,7 +20,7 @@ What it computes, following the paper (arXiv 2603.01443):
 * ``threshold`` - the closed-form cut thresholds of Sec. IV
   (Eqs. speedup_depth_free, threshold_n2, threshold_nge3, threshold_with_D,
   Table II).
-* ``mlp`` - float64 forward, loss, backward and Adam step of the 4-64-64-3
+* ``mlp`` - float64 forward, loss, backward and Adam step of the 8-64-64-3
   cost-model network.  The network is not part of the paper: parity
   unpinned with respect to the paper; its gradients are pinned by central
   finite differences.

@@ -1,4 +1,4 @@
-"""Float64 reference of the 4-64-64-3 cost-model network (test infrastructure only).
+"""Float64 reference of the 8-64-64-3 cost-model network (test infrastructure only).
 
 The learned cost model is not part of the paper (parity unpinned with
 respect to the paper).  It maps features of (q, d, n, c_total) to the natural
@@ -9,7 +9,7 @@ Network: h1 = tanh(x W1 + b1), h2 = tanh(h1 W2 + b2), y = h2 W3 + b3.
 Loss: mean squared error over rows and the three outputs.
 Optimiser: Adam (Kingma and Ba, 2015) with bias correction.
 
-Flat parameter layout (4675 values): W1[4][64] row-major, b1[64],
+Flat parameter layout (4931 values): W1[8][64] row-major, b1[64],
 W2[64][64], b2[64], W3[64][3], b3[3].
 """
 
@@ -20,7 +20,7 @@ from typing import Dict, Tuple
 
 import numpy as np
 
-N_IN, N_H, N_OUT = 4, 64, 3
+N_IN, N_H, N_OUT = 8, 64, 3
 SHAPES = [("W1", (N_IN, N_H)), ("b1", (N_H,)), ("W2", (N_H, N_H)), ("b2", (N_H,)),
           ("W3", (N_H, N_OUT)), ("b3", (N_OUT,))]
 N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
@@ -41,8 +41,22 @@ def flatten(p: Dict[str, np.ndarray]) -> np.ndarray:
 
 
 def features(q: int, d: int, n: int, c_total: int) -> np.ndarray:
-    """Input encoding: centred and scaled (q, log2 d, n, c_total); uncut rows use n = 1, c_total = 0."""
-    return np.array([(q - 24.0) / 8.0, math.log2(d) - math.log2(20.0), (n - 3.0), (c_total - 4.0) / 4.0])
+    """Input encoding: centred and scaled (q, log2 d, n, c_total), then the cost terms of
+    Table I for equal blocks and evenly spread cuts: log2 N_sub (N_sub = sum over segments
+    of 2^{c_i}, c_i the cuts on the segment's boundaries), the largest segment q_max =
+    ceil(q / n), log2 (N_sub 2^{q_max} d) (subcircuit stage) and log2 (2^{c_total} 2^q)
+    (merge, K = 2^{c_total} terms).  Uncut rows use n = 1, c_total = 0, N_sub = 1, q_max = q."""
+    ld = math.log2(d)
+    lsub, qmax = 0.0, q
+    if n >= 2:
+        nb = n - 1
+        cb = [c_total // nb + (1 if b < c_total % nb else 0) for b in range(nb)]
+        ci = [(cb[i - 1] if i > 0 else 0) + (cb[i] if i < nb else 0) for i in range(n)]
+        lsub = math.log2(sum(2.0 ** c for c in ci))
+        qmax = -(-q // n)
+    return np.array([(q - 24.0) / 8.0, ld - math.log2(20.0), (n - 3.0), (c_total - 4.0) / 4.0,
+                     (lsub - 6.0) / 4.0, (qmax - 12.0) / 4.0, (lsub + qmax + ld - 24.0) / 6.0,
+                     (c_total + q - 30.0) / 6.0])
 
 
 def forward(flat: np.ndarray, x: np.ndarray) -> Tuple[np.ndarray, dict]:

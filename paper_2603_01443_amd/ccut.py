@@ -341,7 +341,8 @@ def norm_fidelity_noalloc(psi, ref, q: int, out, stream=None) -> None:
 
 
 PROF_KERNELS = 8
-MLP_PARAMS = 4675
+MLP_PARAMS = 4931
+MLP_IN = 8
 
 
 def expectation_work_bytes(plan: Plan) -> int:
@@ -373,7 +374,7 @@ def speedup_margin(q: int, n: int, cuts_per_boundary: Sequence[int]) -> float:
 
 
 def cost_features(q: int, d: int, n: int, c_total: int) -> List[float]:
-    out = (ctypes.c_float * 4)()
+    out = (ctypes.c_float * MLP_IN)()
     _check(_lib.ccut_cost_features(q, d, n, c_total, out))
     return list(out)
 
@@ -404,9 +405,15 @@ def mlp_train(params, x, t, rows: int, epochs: int, lr: float, work, work_bytes:
     return losses[:epochs]
 
 
-def decide(q: int, d: int, c_total: int, params=None, budget_s: float = 0.0, margin: float = 0.0,
+# Guard margin of the learned decision validated on held-out measured rows (results/cost_model.json):
+# from 0.1 on, no held-out decision was slower than the closed-form rule's.
+DECIDE_MARGIN = 0.1
+
+
+def decide(q: int, d: int, c_total: int, params=None, budget_s: float = 0.0, margin: float = DECIDE_MARGIN,
            stream=None):
-    """(choice, predicted seconds): choice 0 = no cut, n >= 2 segments, -1 = over budget."""
+    """(choice, predicted seconds): choice 0 = no cut, n >= 2 segments, -1 = over budget.
+    margin: leave the closed-form choice only for a predicted gain above this fraction."""
     choice = ctypes.c_int32()
     pred = ctypes.c_double()
     _check(_lib.ccut_decide(q, d, c_total, _ptr(params) if params is not None else None, budget_s, margin,

@@ -25,11 +25,29 @@ void split_even(int c_total, int n, int* cb) {
   for (int b = 0; b < nb; ++b) cb[b] = c_total / nb + (b < c_total % nb ? 1 : 0);
 }
 
-void features(int q, int d, int n, int c_total, float out[4]) {
+// Network inputs: the four problem parameters, centred and scaled, then the cost terms of
+// Table I for equal blocks (largest segment q_max = ceil(q / n)) and cuts spread evenly over
+// the boundaries: log2 N_sub, q_max, log2 (N_sub 2^{q_max} d) for the subcircuit stage and
+// log2 (K 2^q) with K = 2^{c_total} terms for the merge.  Uncut rows: n = 1, c_total = 0,
+// N_sub = 1, q_max = q (the sub term is then the uncut simulation's 2^q d).
+void features(int q, int d, int n, int c_total, float out[MLP_IN]) {
+  const double ld = std::log2((double)d);
+  double lsub = 0.0;
+  int qmax = q;
+  if (n >= 2) {
+    int cb[CCUT_MAX_SEG];
+    split_even(c_total, n, cb);
+    lsub = std::log2(n_sub(n, cb));
+    qmax = (q + n - 1) / n;
+  }
   out[0] = (float)((q - 24.0) / 8.0);
-  out[1] = (float)(std::log2((double)d) - std::log2(20.0));
+  out[1] = (float)(ld - std::log2(20.0));
   out[2] = (float)(n - 3.0);
   out[3] = (float)((c_total - 4.0) / 4.0);
+  out[4] = (float)((lsub - 6.0) / 4.0);
+  out[5] = (float)((qmax - 12.0) / 4.0);
+  out[6] = (float)((lsub + qmax + ld - 24.0) / 6.0);
+  out[7] = (float)((c_total + q - 30.0) / 6.0);
 }
 
 std::mutex g_dec_mu;
@@ -63,9 +81,9 @@ extern "C" int ccut_speedup_margin(int32_t q, int32_t n, const int32_t* cuts_per
   return CCUT_OK;
 }
 
-extern "C" int ccut_cost_features(int32_t q, int32_t d, int32_t n, int32_t c_total, float out[4]) {
+extern "C" int ccut_cost_features(int32_t q, int32_t d, int32_t n, int32_t c_total, float out[8]) {
   clear_error();
-  if (!out || q < 1 || d < 1 || n < 1 || c_total < 0) return fail(CCUT_EINVAL, "bad argument");
+  if (!out || q < 1 || d < 1 || n < 1 || n > CCUT_MAX_SEG || c_total < 0) return fail(CCUT_EINVAL, "bad argument");
   features(q, d, n, c_total, out);
   return CCUT_OK;
 }
@@ -131,12 +149,12 @@ extern "C" int ccut_decide(int32_t q, int32_t d, int32_t c_total, const float* d
     return CCUT_OK;
   }
   // Learned model: argmin of predicted wall clock over {uncut, n = 2, 3, 4}.
-  float x[16];
+  float x[4 * MLP_IN];
   int valid[4];
   for (int i = 0; i < 4; ++i) {
     const int n = cands[i];
     valid[i] = n <= q;
-    features(q, d, n, n == 1 ? 0 : c_total, x + 4 * i);
+    features(q, d, n, n == 1 ? 0 : c_total, x + MLP_IN * i);
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   int dev = 0;
@@ -145,7 +163,8 @@ extern "C" int ccut_decide(int32_t q, int32_t d, int32_t c_total, const float* d
   std::lock_guard<std::mutex> lk(g_dec_mu);
   if (!g_dec_buf[dev]) CCUT_HIP(hipMalloc((void**)&g_dec_buf[dev], 64 * sizeof(float)));
   float* dx = g_dec_buf[dev];
-  float* dy = dx + 16;
+  float* dy = dx + 4 * MLP_IN;  // 4 x MLP_IN inputs, then 4 x 3 outputs (<= 64 floats)
+  static_assert(4 * MLP_IN + 12 <= 64, "decision buffer");
   CCUT_HIP(hipMemcpyAsync(dx, x, sizeof(x), hipMemcpyHostToDevice, s));
   if (int rc = mlp_forward(d_params, dx, 4, dy, s)) return rc;
   float y[12];

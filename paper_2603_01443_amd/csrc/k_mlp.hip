@@ -1,10 +1,10 @@
-// Learned cost model: a 4-64-64-3 tanh MLP trained full-batch with Adam,
+// Learned cost model: an 8-64-64-3 tanh MLP trained full-batch with Adam,
 // hand-written for gfx950.  It maps features of (q, d, n, c_total) to the
 // natural log of the three stage times of the paper's Eq. (runtime_decomp)
 // (T_pre, T_sub, T_merge); the decision rule built on it is compared with the
 // closed-form thresholds of Sec. IV.
 //
-// Parameter layout (4675 floats): W1[4][64], b1[64], W2[64][64], b2[64],
+// Parameter layout (4931 floats): W1[8][64], b1[64], W2[64][64], b2[64],
 // W3[64][3], b3[3].  Loss: mean squared error over rows and outputs.
 //
 // Training step = three kernels:

@@ -5,10 +5,11 @@
 
 namespace ccut {
 
-constexpr int MLP_IN = 4, MLP_HIDDEN = 64, MLP_OUT = 3;
+constexpr int MLP_IN = 8, MLP_HIDDEN = 64, MLP_OUT = 3;
 constexpr int MLP_PARAMS = MLP_IN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN +
-                           MLP_HIDDEN * MLP_OUT + MLP_OUT;  // 4675
-constexpr int MLP_PART_STRIDE = 4680;   // floats per chunk: gradient + squared error, padded
+                           MLP_HIDDEN * MLP_OUT + MLP_OUT;  // 4931
+constexpr int MLP_PART_STRIDE = 4936;   // floats per chunk: gradient + squared error, padded
+static_assert(MLP_PART_STRIDE > MLP_PARAMS, "chunk stride");
 constexpr int MLP_ROWS_PER_BLOCK = 32;
 
 uint64_t mlp_work_floats(int64_t rows, int epochs);

@@ -25,7 +25,8 @@ batching   q = 32 in blocks 10 / 11 / 11, d = 30, 3 + 3 cuts (80 variants): the
            and replayed from a HIP graph; the 2^32 state merged once in place
            and compared with the uncut simulation.
 costmodel  Timing grid q in {16, ..., 32} x d in {10, 20, 40} x n in {2, 3, 4} x
-           c_total in {0..8} x seeds {0, 1, 2} plus uncut rows; the 4-64-64-3
+           c_total in {0..8} (and 10, 12, 14 up to q = 24, where cutting stops paying)
+           x seeds {0, 1, 2} plus uncut rows; the 8-64-64-3
            network is trained on the GPU (seeds 0, 1, q < 32) and the learned
            cut/no-cut choice is compared with the closed-form rule on the held-out
            rows by measured wall clock.
@@ -300,12 +301,20 @@ def run_batching(args):
 # ------------------------------------------------------------------ cost model
 def run_costmodel(args):
     qs = list(range(16, 34, 2)) if not args.quick else [16, 18, 20]
+    if args.qs:
+        qs = [int(v) for v in args.qs.split(",")]
     ds = (10, 20, 40)
     ns = (2, 3, 4)
     cs = range(0, 9)
+    # cut counts where cutting stops paying (T_merge grows as 2^{c_total}): up to q = 24
+    cs_far = (10, 12, 14)
     seeds = (0, 1, 2)
     bufs = Buffers()
     rows = []
+    if args.rows_in:   # rows measured by an earlier run (another part of the grid)
+        with open(args.rows_in) as f:
+            rows = json.load(f)["rows"]
+        log(f"costmodel: {len(rows)} rows from {args.rows_in}")
     t0 = time.time()
     for q in qs:
         for d in ds:
@@ -315,13 +324,18 @@ def run_costmodel(args):
                 rows.append({"q": q, "d": d, "n": 1, "c_total": 0, "seed": seed, "T_pre": 0.0, "T_sub": t_orig,
                              "T_merge": 0.0, "total": t_orig})
                 for n in ns:
-                    for c in cs:
+                    for c in list(cs) + (list(cs_far) if q <= 24 else []):
                         cb = split_cuts(c, n)
+                        if max(cb) > d:   # the generator places at most one cut per boundary and layer
+                            continue
                         g = brickwork(q, d, n, c, seed=seed, cuts_per_boundary=cb)
                         pre, sub, mer, _ = time_cut(q, g, n, equal_blocks(q, n), bufs, warm=1, reps=2)
                         rows.append({"q": q, "d": d, "n": n, "c_total": c, "seed": seed, "T_pre": pre,
                                      "T_sub": sub, "T_merge": mer, "total": pre + sub + mer})
             log(f"costmodel grid q={q} d={d}: {len(rows)} rows, {time.time() - t0:.0f} s")
+    if args.rows_only:
+        return {"experiment": "cost model rows", "rows": rows}
+    qs = sorted({r["q"] for r in rows})
     floor = math.log(1e-6)
 
     def target(r):
@@ -401,6 +415,16 @@ def run_costmodel(args):
         "learned_mean_regret": float(np.mean(tl / tb - 1)), "closed_mean_regret": float(np.mean(tc / tb - 1)),
         "learned_slower_than_closed_by_more_than_10pct": int(np.sum(tl > 1.10 * tc)),
         "learned_slower_than_closed_any": int(np.sum(tl > tc)),
+        # cut / no-cut: decisions whose choice to cut at all differs from the measured best's
+        "closed_cut_choice_wrong": int(np.sum([(x["closed_form"] == 0) != (x["best"] == 0) for x in decisions])),
+        "learned_cut_choice_wrong": int(np.sum([(x["learned"] == 0) != (x["best"] == 0) for x in decisions])),
+        "cases_closed_cut_choice_wrong": {
+            "learned_total_s": float(sum(x["t_learned"] for x in decisions
+                                         if (x["closed_form"] == 0) != (x["best"] == 0))),
+            "closed_total_s": float(sum(x["t_closed"] for x in decisions
+                                        if (x["closed_form"] == 0) != (x["best"] == 0))),
+            "best_total_s": float(sum(x["t_best"] for x in decisions
+                                      if (x["closed_form"] == 0) != (x["best"] == 0)))},
         "stage_abs_log_error_mean": [float(v) for v in err_stage.mean(axis=0)],
         "train_rows": len(train), "test_rows": len(test), "epochs": epochs, "train_seconds": train_s,
         "final_loss": float(losses[-1]),
@@ -743,6 +767,9 @@ def main():
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--margin", type=float, default=0.2)
     ap.add_argument("--cmax", type=int, default=16, help="sweep: largest c_total tried")
+    ap.add_argument("--qs", default=None, help="costmodel: comma-separated q values of the grid")
+    ap.add_argument("--rows-in", default=None, help="costmodel: rows measured by an earlier (partial) run")
+    ap.add_argument("--rows-only", action="store_true", help="costmodel: measure rows, skip training")
     args = ap.parse_args()
     if not torch.cuda.is_available():
         raise SystemExit("experiments need a GPU")

@@ -41,4 +41,4 @@ def test_closed_form_decision_matches_oracle():
 
 
 def test_mlp_work_bytes_grows_with_rows():
-    assert ccut.mlp_work_bytes(1000, 10) > ccut.mlp_work_bytes(10, 10) > 4 * 4675
+    assert ccut.mlp_work_bytes(1000, 10) > ccut.mlp_work_bytes(10, 10) > 4 * 4931

@@ -26,7 +26,7 @@ def ccut():
 
 def data(rows, seed):
     rng = np.random.default_rng(seed)
-    x = rng.normal(size=(rows, 4))
+    x = rng.normal(size=(rows, omlp.N_IN))
     t = np.stack([0.3 * x[:, 0] - x[:, 1], np.tanh(x[:, 2]) + 0.1 * x[:, 3], x[:, 0] * x[:, 3]], axis=1)
     return x, t
 
@@ -77,7 +77,10 @@ def test_training_tracks_oracle_and_graph_replay_is_exact(ccut):
     pw, hist = omlp.train(p0.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64),
                           t.astype(np.float32).astype(np.float64), epochs, lr)
     assert la[-1] < 0.3 * la[0]
-    assert np.max(np.abs(np.asarray(la, dtype=np.float64) - hist) / np.asarray(hist)) < 1e-3
+    # float32 Adam steps against float64 ones: each update's rounding (~2^-24 relative) is carried
+    # through the optimiser's moments, so the curves drift apart slowly; over 120 epochs of the
+    # 8-input network they stay within 2e-3 relative
+    assert np.max(np.abs(np.asarray(la, dtype=np.float64) - hist) / np.asarray(hist)) < 2e-3
     assert np.max(np.abs(pa.cpu().numpy() - pw)) < 1e-3
 
 
@@ -86,13 +89,81 @@ def test_learned_decision_prefers_cheaper_prediction(ccut):
     # and 1 ms uncut, so the learned rule must keep the circuit uncut
     p = np.zeros(ccut.MLP_PARAMS)
     p[-3:] = np.log(1e-3)
-    choice, pred = ccut.decide(24, 20, 4, dev(p))
+    choice, pred = ccut.decide(24, 20, 4, dev(p), margin=0.0)
     assert choice == 0 and abs(pred - 1e-3) < 1e-8
-    choice, pred = ccut.decide(24, 20, 4, dev(p), budget_s=1e-4)
+    choice, pred = ccut.decide(24, 20, 4, dev(p), budget_s=1e-4, margin=0.0)
     assert choice == -1
     cf = threshold.closed_form_choice(24, 4)
     assert cf != 0 and ccut.decide(24, 20, 4)[0] == cf
+    assert ccut.decide(24, 20, 4, dev(p), margin=0.0)[0] == 0
     # a predicted 3x gain clears a 0.5 guard margin; a 0.7 margin keeps the closed-form choice
     assert ccut.decide(24, 20, 4, dev(p), margin=0.5)[0] == 0
     choice, pred = ccut.decide(24, 20, 4, dev(p), margin=0.7)
     assert choice == cf and abs(pred - 3e-3) < 1e-8
+
+
+def test_learned_model_gain_on_measured_rows(ccut):
+    """The network trained by the library's own kernels on this pipeline's measured stage times
+    (results/cost_model.json: the brickwork grid q = 16..32, d = 10, 20, 40, n = 2, 3, 4, c_total up
+    to 8, and up to 14 for q <= 24 where cutting stops paying; seeds 0, 1 and q < 32 for training)
+    decides the held-out circuits (seed 2 and q = 32) among no cut and n = 2, 3, 4.  Against the
+    closed-form rule of Sec. IV (Eq. speedup_depth_free), judged by measured wall clock: the total
+    is not larger, no decision is more than 10 % slower (run-to-run timing noise of the rows), and
+    on the cases where the closed form chooses wrongly whether to cut at all, the learned choices
+    take less total time and are wrong less often."""
+    import json
+    import math
+    import os
+
+    from inputs.mlp_init import glorot_params as init
+
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "results", "cost_model.json")
+    with open(path) as f:
+        rows = json.load(f)["rows"]
+    qmax = max(r["q"] for r in rows)
+    train = [r for r in rows if r["seed"] != 2 and r["q"] != qmax]
+    test = [r for r in rows if r["seed"] == 2 or r["q"] == qmax]
+    floor = math.log(1e-6)
+
+    def target(r):
+        if r["n"] == 1:
+            return [floor, math.log(r["T_sub"]), floor]
+        return [math.log(max(r[k], 1e-6)) for k in ("T_pre", "T_sub", "T_merge")]
+
+    x = np.array([ccut.cost_features(r["q"], r["d"], r["n"], r["c_total"]) for r in train])
+    t = np.array([target(r) for r in train])
+    epochs = 3000
+    params = dev(init(0))
+    work = torch.empty(ccut.mlp_work_bytes(len(x), epochs), dtype=torch.uint8, device="cuda")
+    losses = ccut.mlp_train(params, dev(x), dev(t), len(x), epochs, 3e-3, work)
+    assert losses[-1] < 0.05 * losses[0]
+
+    uncut = {(r["q"], r["d"], r["seed"]): r["total"] for r in test if r["n"] == 1}
+    cand = {}
+    for r in test:
+        if r["n"] > 1:
+            cand.setdefault((r["q"], r["d"], r["c_total"], r["seed"]), {0: uncut[(r["q"], r["d"], r["seed"])]})[
+                r["n"]] = r["total"]
+    tl, tc, tb, wrong_c, wrong_l, gain_l, gain_c = [], [], [], 0, 0, 0.0, 0.0
+    for (q, d, c, seed), meas in sorted(cand.items()):
+        learned, _ = ccut.decide(q, d, c, params)
+        closed, _ = ccut.decide(q, d, c)
+        best = min(meas, key=meas.get)
+        tl.append(meas[learned])
+        tc.append(meas[closed])
+        tb.append(meas[best])
+        wrong_l += (learned == 0) != (best == 0)
+        if (closed == 0) != (best == 0):
+            wrong_c += 1
+            gain_l += meas[learned]
+            gain_c += meas[closed]
+    tl, tc, tb = map(np.array, (tl, tc, tb))
+    print(f"held-out decisions {len(tl)}: total learned {tl.sum() * 1e3:.2f} ms, closed form {tc.sum() * 1e3:.2f} ms, "
+          f"best {tb.sum() * 1e3:.2f} ms; mean regret learned {np.mean(tl / tb - 1):.3f}, closed "
+          f"{np.mean(tc / tb - 1):.3f}; cut/no-cut wrong: learned {wrong_l}, closed {wrong_c}; on the closed form's "
+          f"wrong cut/no-cut cases: learned {gain_l * 1e3:.3f} ms, closed {gain_c * 1e3:.3f} ms", flush=True)
+    assert tl.sum() <= tc.sum()
+    assert np.all(tl <= 1.10 * tc)
+    assert wrong_c >= 5                       # the held-out set exercises the cut / no-cut choice
+    assert gain_l < gain_c and wrong_l < wrong_c
+    assert np.mean(tl / tb - 1) < np.mean(tc / tb - 1)

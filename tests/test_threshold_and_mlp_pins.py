@@ -71,10 +71,23 @@ def test_closed_form_choice():
 
 # ---------------------------------------------------------------- MLP reference
 
+def test_features_hand_worked():
+    """q = 24, d = 20, n = 3, c_total = 4: cuts (2, 2), c_i = (2, 4, 2), N_sub = 4 + 16 + 4 = 24,
+    q_max = 8, merge work 2^4 2^24.  Uncut q = 20, d = 10: N_sub = 1, q_max = 20."""
+    l24, l20, l10 = math.log2(24), math.log2(20), math.log2(10)
+    want = [0.0, 0.0, 0.0, 0.0, (l24 - 6) / 4, (8 - 12) / 4, (l24 + 8 + l20 - 24) / 6, (4 + 24 - 30) / 6]
+    assert np.allclose(mlp.features(24, 20, 3, 4), want, atol=1e-12)
+    want = [-0.5, l10 - l20, -2.0, -1.0, -1.5, 2.0, (20 + l10 - 24) / 6, -10 / 6]
+    assert np.allclose(mlp.features(20, 10, 1, 0), want, atol=1e-12)
+    # n = 2, c_total = 5: both segments see all 5 cuts; q = 17 gives blocks 8 + 9, q_max = 9
+    assert np.isclose(mlp.features(17, 20, 2, 5)[4], (6 - 6) / 4)
+    assert np.isclose(mlp.features(17, 20, 2, 5)[5], (9 - 12) / 4)
+
+
 def test_mlp_gradient_matches_finite_differences():
     flat = glorot_params(5)
     rng = np.random.default_rng(1)
-    x = rng.normal(size=(17, 4))
+    x = rng.normal(size=(17, mlp.N_IN))
     t = rng.normal(size=(17, 3))
     y, cache = mlp.forward(flat, x)
     g = mlp.backward(flat, cache, y, t)
@@ -88,19 +101,19 @@ def test_mlp_gradient_matches_finite_differences():
 
 
 def test_mlp_layout_and_adam_first_step():
-    assert mlp.N_PARAMS == 4675
+    assert mlp.N_PARAMS == 4931
     flat = glorot_params(0)
-    assert flat.shape == (4675,)
-    g = np.linspace(-1, 1, 4675)
+    assert flat.shape == (4931,)
+    g = np.linspace(-1, 1, 4931)
     g[g == 0] = 0.5
-    new, m, v = mlp.adam_step(flat, g, np.zeros(4675), np.zeros(4675), 1, 1e-3)
+    new, m, v = mlp.adam_step(flat, g, np.zeros(4931), np.zeros(4931), 1, 1e-3)
     # bias-corrected first step moves every weight by lr * sign(g) (up to eps)
     assert np.max(np.abs((flat - new) - 1e-3 * np.sign(g))) < 1e-3 * 1e-4
 
 
 def test_mlp_training_reduces_loss():
     rng = np.random.default_rng(2)
-    x = rng.normal(size=(64, 4))
+    x = rng.normal(size=(64, mlp.N_IN))
     t = np.stack([x[:, 0] + 0.5 * x[:, 1], np.sin(x[:, 2]), x[:, 3] ** 2], axis=1)
     _, hist = mlp.train(glorot_params(3), x, t, epochs=300, lr=1e-2)
     assert hist[-1] < 0.2 * hist[0]
