@@ -408,6 +408,7 @@ def run_costmodel(args):
                                                                            for x in decisions]))}
     summary = {
         "margin_table": margin_table,
+        "learned_margin": args.margin,
         "held_out_decisions": len(decisions),
         "learned_optimal_frac": float(np.mean([x["learned"] == x["best"] for x in decisions])),
         "closed_optimal_frac": float(np.mean([x["closed_form"] == x["best"] for x in decisions])),
@@ -765,7 +766,7 @@ def main():
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--budget-ms", type=float, default=20.0)
     ap.add_argument("--quick", action="store_true")
-    ap.add_argument("--margin", type=float, default=0.2)
+    ap.add_argument("--margin", type=float, default=ccut.DECIDE_MARGIN)
     ap.add_argument("--cmax", type=int, default=16, help="sweep: largest c_total tried")
     ap.add_argument("--qs", default=None, help="costmodel: comma-separated q values of the grid")
     ap.add_argument("--rows-in", default=None, help="costmodel: rows measured by an earlier (partial) run")
