@@ -467,6 +467,22 @@ int ccut_plan_set_prefix_start(ccut_plan_t* plan, int32_t level);
 int ccut_plan_get_prefix_start(const ccut_plan_t* plan, int32_t* out);
 
 /*
+ * Gate fusion in the register stages of the subcircuit simulation (the gates of
+ * Algorithm 2, applied in the same order): on = 1 folds, inside each stage, the
+ * runs of single-qubit gates, diagonal phases, CZ pairs and CX gates that act on
+ * the stage's four register qubits alone into one 16x16 matrix, applied as one
+ * split-float16 MFMA product, and applies the stage's CZ pairs between qubits
+ * outside its register set once, at its end (they commute with everything the
+ * stage does).  The matrices are composed (float64) on the device by every
+ * ccut_simulate_subcircuits call, which costs more than it saves when a plan is
+ * simulated once; off = 0 is the default.  The uncut baseline always fuses: its
+ * programs are cached and their matrices built once.  Results agree to float32
+ * rounding.  Host-only; reschedules the plan.  Errors: CCUT_EINVAL.
+ */
+int ccut_plan_set_fusion(ccut_plan_t* plan, int32_t on);
+int ccut_plan_get_fusion(const ccut_plan_t* plan, int32_t* out);
+
+/*
  * Autotuner: times the simulation kernel over prefix sharing off / on (tree
  * from level 0, 2, 3, 4, c - 2 and c - 1, c the largest c_i) x LDS
  * block sizes (whole segment, 2 and 4 blocks per state; sizes whose tables do

@@ -126,6 +126,8 @@ def _load():
         "ccut_plan_set_prefix_start": [vp, i32],
         "ccut_plan_get_prefix_start": [vp, ctypes.POINTER(i32)],
         "ccut_plan_get_prefix_sharing": [vp, ctypes.POINTER(i32)],
+        "ccut_plan_set_fusion": [vp, i32],
+        "ccut_plan_get_fusion": [vp, ctypes.POINTER(i32)],
         "ccut_plan_get_sim_precision": [vp, ctypes.POINTER(i32)],
         "ccut_plan_get_block_bits": [vp, ctypes.POINTER(i32)],
         "ccut_plan_stats": [vp, ctypes.POINTER(i64)],
@@ -508,6 +510,17 @@ def plan_get_sim_precision(plan: Plan) -> str:
 def plan_set_prefix_sharing(plan: Plan, mode: int) -> None:
     """Prefix sharing in the subcircuit simulation: 0 off, 1 on, -1 automatic."""
     _check(_lib.ccut_plan_set_prefix_sharing(plan.handle, int(mode)))
+
+
+def plan_set_fusion(plan: Plan, on: bool) -> None:
+    """Register-stage gate fusion (ccut_plan_set_fusion)."""
+    _check(_lib.ccut_plan_set_fusion(plan.handle, int(on)))
+
+
+def plan_get_fusion(plan: Plan) -> bool:
+    out = ctypes.c_int32()
+    _check(_lib.ccut_plan_get_fusion(plan.handle, ctypes.byref(out)))
+    return bool(out.value)
 
 
 def plan_get_prefix_sharing(plan: Plan) -> bool:

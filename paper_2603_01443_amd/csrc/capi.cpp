@@ -243,7 +243,7 @@ int compile_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, UncutPro
   std::vector<Pass> passes;
   if (int rc = schedule_passes(pb.prog, UNCUT_BLOCK_BITS, 4, passes)) return rc;
   for (const Pass& p : passes) {
-    int pid = append_pass(p, q, U.descs, U.stages, U.kops, U.grefs);
+    int pid = append_pass(p, q, U.descs, U.stages, U.kops, U.grefs, true);  // tables built once per program
     SimJob j;
     std::memset(&j, 0, sizeof(j));
     j.pass_id = pid;
@@ -288,13 +288,15 @@ extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint6
         const SimJob& job = plan->jobs[L.job_begin + j];
         const int nb = plan->pass_descs[job.pass_id].n_blocks;
         if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, nb, job.wg_begin, T.passes, T.stages, T.ops, gtab,
-                                static_cast<float*>(d_arena), plan->bmax, plan->sim_threads, 0, s))
+                                static_cast<float*>(d_arena), plan->bmax, L.hdr_cap, L.stg_cap, plan->sim_threads,
+                                0, s))
           return rc;
       }
       continue;
     }
     if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, L.total_wg, 0, T.passes, T.stages, T.ops, gtab,
-                            static_cast<float*>(d_arena), plan->bmax, plan->sim_threads, plan->sim_grid_cap, s))
+                            static_cast<float*>(d_arena), plan->bmax, L.hdr_cap, L.stg_cap, plan->sim_threads,
+                            plan->sim_grid_cap, s))
       return rc;
   }
   return CCUT_OK;
@@ -426,8 +428,10 @@ extern "C" int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t 
   U->stamp = ++g_uncut_clock;
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (size_t p = 0; p < U->jobs.size(); ++p) {
-    if (int rc = launch_sim(U->dev.jobs + p, 1, U->descs[p].n_blocks, 0, U->dev.passes, U->dev.stages, U->dev.ops,
-                            U->gtab, static_cast<float*>(d_psi), UNCUT_BLOCK_BITS, UNCUT_THREADS, 0, s))
+    const PassDesc& d = U->descs[p];
+    if (int rc = launch_sim(U->dev.jobs + p, 1, d.n_blocks, 0, U->dev.passes, U->dev.stages, U->dev.ops, U->gtab,
+                            static_cast<float*>(d_psi), UNCUT_BLOCK_BITS, d.stage_count > 0 ? d.op_count : 0,
+                            d.stage_count, UNCUT_THREADS, 0, s))
       return rc;
   }
   return CCUT_OK;

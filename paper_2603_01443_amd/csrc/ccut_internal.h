@@ -76,7 +76,9 @@ struct ProgramBuilder {
 enum KOpType : int32_t {
   KOP_DENSE = 0,   // 2x2 on local bit a
   KOP_DIAG = 1,    // diag(m0, m3) on local bit a
-  KOP_CZL = 2,     // sign flip where sum_t popcount(i & (i >> shift_t) & mask_t) is odd
+  KOP_CZL = 2,     // sign flip where sum_t popcount(i & (i >> shift_t) & mask_t) is odd;
+                   // in register stages the header repeats terms 0 and 1 in (a, b) and
+                   // (pad[0], pad[1]), so that the 32-byte header read brings them
   KOP_SCALAR = 3,  // multiply the block by m0 (bit a of the block base is 0) or m3 (it is 1)
   KOP_CXL = 4,     // CX with local control a, local target b
   KOP_GROUP = 5,   // register stages only: one 2x2 gate per register position (gates on
@@ -86,9 +88,19 @@ enum KOpType : int32_t {
                    // that one 32-byte read gives every matrix address.  pad[0]: first
                    // MFMA operand table of the group, pad[1]: number of members with a
                    // slot (the group has 2^pad[1] tables, one per choice of those slots)
+  KOP_FUSED = 6,   // register stages only: the a records that follow (groups, and
+                   // diagonal, CZ and CX ops confined to the register bits) form one
+                   // 16x16 matrix on the register positions.  The MFMA path applies that
+                   // matrix from its operand tables and skips the records; the float32
+                   // path skips this header and runs the records one by one.  b, slot,
+                   // cond, nterms: the distinct variant slots of the records (the
+                   // first k valid, the rest -1), so that table choice bit j is slot j;
+                   // pad[0]: first operand table, pad[1]: number of slots; m[0..3] (as
+                   // int32): the local bit of each register position
 };
 
 constexpr int KOP_MAX_TERMS = 8;
+constexpr int FUSED_MAX_RECORDS = 48;  // records of one KOP_FUSED run (staged in LDS to build its table)
 
 struct KOp {
   int32_t type;
@@ -102,6 +114,7 @@ struct KOp {
 static_assert(sizeof(KOp) == 96, "KOp layout");
 
 constexpr int PASS_MAX_B = 14;   // 2^14 complex64 = 128 KiB of LDS per block
+constexpr size_t SIM_LDS_MAX = 160 * 1024;  // LDS of one compute unit (gfx950)
 constexpr int REG_BITS = 4;      // amplitudes held per thread in a register stage: 2^4
 constexpr int STAGE_MIN_B = 9;   // blocks of at least 2^9 amplitudes run in register stages
 
@@ -111,28 +124,30 @@ constexpr int STAGE_MIN_B = 9;   // blocks of at least 2^9 amplitudes run in reg
 // Amplitude e of a thread sits at local index base | roff[e] and LDS slot
 // pad(base) + proff[e] (the padding is additive over disjoint bits).  Ops of a
 // stage: KOP_DENSE.a and KOP_CXL.b name register positions (0..REG_BITS-1);
-// every other bit field is a local bit.
+// every other bit field is a local bit.  The kernel reads the first 32 bytes
+// and forms roff / proff from reg[] itself.
 struct StageDesc {
   int32_t op_begin;
   int32_t op_count;
   int32_t reg[REG_BITS];
+  int32_t pad[2];
   int32_t roff[1 << REG_BITS];
   int32_t proff[1 << REG_BITS];
-  int32_t pad[2];
 };
 static_assert(sizeof(StageDesc) == 160, "StageDesc layout");
 
-// MFMA form of a KOP_GROUP (split-float16 register-stage path).  The group's
-// gates form a 16x16 complex matrix G (Kronecker product, position p = bit p of
-// the row and column index) acting on a thread's 16 amplitudes.  As a real
+// MFMA form of a KOP_GROUP or KOP_FUSED run (split-float16 register-stage path).
+// Its records form a 16x16 complex matrix G (for a group, the Kronecker product of
+// its gates; position p = bit p of the row and column index) acting on a thread's
+// 16 amplitudes.  As a real
 // 32x32 matrix on (Re x[0..15], Im x[0..15]) it is the A operand of two
 // v_mfma_f32_32x32x16_f16 steps (k = 0..15: real parts, 16..31: imaginary).
 // Its output rows interleave the parts: row 2 e = Re y_e, row 2 e + 1 = Im y_e.
 // A table holds, per lane l (row m = l % 32, k half h = l / 32), four uint4:
 // hi and lo float16 parts of A[m][16 s + 8 h + e], e = 0..7, for s = 0, 1.
 struct GroupRef {
-  int32_t op;   // GROUP header in the op table
-  int32_t sel;  // bit j: slot choice of the group's j-th member with a slot
+  int32_t op;   // GROUP or FUSED header in the op table
+  int32_t sel;  // bit j: choice of the j-th variant slot named in the header
 };
 constexpr int GROUP_TABLE_UINT4 = 64 * 4;  // uint4 per table (4 KiB)
 constexpr float SIM_MFMA_SCALE = 16384.0f;  // 2^14: state scale inside a pass on the MFMA path
@@ -162,7 +177,11 @@ struct Pass {
 };
 
 // Splits a pass's block-level ops into register stages (stage-level op encoding).
-void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& stages, std::vector<KOp>& out);
+// fuse: fold what acts on a stage's register bits alone into KOP_FUSED runs.  Their
+// operand tables are composed on the device at each call, which pays where a
+// program's tables serve much work (the uncut passes) rather than per-call plans.
+void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& stages, std::vector<KOp>& out,
+                bool fuse);
 
 // Schedule a program into LDS-blocked passes of at most 2^bmax amplitudes.
 // Low qubits [0, low_bits) sit in every block (coalesced runs).  The first pass
@@ -222,9 +241,13 @@ struct ProfScope {
 // makes the launch persistent (each workgroup loops over several blocks).
 // gtab != nullptr selects the split-float16 MFMA path for register-stage groups
 // (operand tables built by launch_group_tables); nullptr keeps float32 VALU.
+// hdr_cap / stg_cap: the most op records and register stages of any pass the
+// launch runs (the kernel copies a pass's op headers and stage heads to LDS).
 int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
                const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax,
-               int threads, int grid_cap, hipStream_t s);
+               int hdr_cap, int stg_cap, int threads, int grid_cap, hipStream_t s);
+// LDS bytes of a simulation workgroup with those capacities.
+size_t sim_shmem_bytes(int bmax, int hdr_cap, int stg_cap);
 
 // Copies `bytes` (a multiple of 16, 16-byte aligned) from pinned host memory to dst.
 int launch_table_copy(void* dst, const void* host_src, uint64_t bytes, hipStream_t s);

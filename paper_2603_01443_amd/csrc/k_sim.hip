@@ -105,8 +105,8 @@ __device__ __forceinline__ f32x16 mfma16(const uint4& a, uint32_t b0, uint32_t b
                                                0, 0);
 }
 
-// y = G x for every lane's 16 amplitudes (the group's operand table gt: this
-// lane's four uint4, hi/lo for k-steps 0 (real parts) and 1 (imaginary parts)).
+// y = G x for every lane's 16 amplitudes (gt: this lane's four uint4 of the
+// operand table, hi/lo for k-steps 0 (real parts) and 1 (imaginary parts)).
 __device__ __forceinline__ void group_mfma(float2 (&a)[R], const uint4* __restrict__ gt) {
   const uint4 ghi0 = gt[0], ghi1 = gt[1], glo0 = gt[2], glo1 = gt[3];
   // B operand planes: element e of re / im, float16 hi and lo, two per dword
@@ -202,36 +202,55 @@ __device__ __forceinline__ OpHead load_head(const KOp* k) {
   return OpHead{x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
 }
 
+// A header from the LDS copy: the same for every lane, so each field is moved to
+// a scalar register (the interpreter branches on them).
+__device__ __forceinline__ OpHead lds_head(const OpHead* p) {
+  const int4* q = reinterpret_cast<const int4*>(p);
+  const int4 x = q[0], y = q[1];
+  return OpHead{__builtin_amdgcn_readfirstlane(x.x), __builtin_amdgcn_readfirstlane(x.y),
+                __builtin_amdgcn_readfirstlane(x.z), __builtin_amdgcn_readfirstlane(x.w),
+                __builtin_amdgcn_readfirstlane(y.x), __builtin_amdgcn_readfirstlane(y.y),
+                __builtin_amdgcn_readfirstlane(y.z), __builtin_amdgcn_readfirstlane(y.w)};
+}
+
+// Operand table of a group or fused run for this variant: bit j of the choice is
+// the variant bit of the j-th slot named in the header.
+__device__ __forceinline__ int table_index(const OpHead& h, int variant) {
+  const int slots[4] = {h.b, h.slot, h.cond, h.nterms};
+  int sel = 0, j = 0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (slots[p] >= 0) {
+      sel |= ((variant >> slots[p]) & 1) << j;
+      ++j;
+    }
+  }
+  return h.pad0 + sel;
+}
+
 // Applies the ops [o0, o1) of a register stage to one thread's amplitudes.  The
-// next op's header is loaded before the current op runs, so its load latency
-// (op tables are read by every workgroup) hides behind the arithmetic.
+// op headers come from the pass's copy in LDS (hdr[i] is op pass_op + i).
 // full_waves: every lane of the wavefront holds a thread slot (the MFMA path
 // exchanges data between lane halves, which needs both halves active).
 template <bool MFMA>
 __device__ __forceinline__ void run_stage_ops(float2 (&a)[R], const int (&idx)[R], const KOp* __restrict__ ops,
-                                              int o0, int o1, uint64_t blockbase, int variant,
-                                              const uint4* __restrict__ gtab, bool full_waves) {
+                                              const OpHead* hdr, int pass_op, int o0, int o1, uint64_t blockbase,
+                                              int variant, const uint4* __restrict__ gtab, bool full_waves) {
   if (o0 >= o1) return;
-  OpHead h = load_head(ops + o0);
+  OpHead h = lds_head(hdr + (o0 - pass_op));
   for (int o = o0; o < o1;) {
     const KOp* k = ops + o;
     const int type = h.type;
-    const int next = o + (type == KOP_GROUP ? 1 + REG_BITS : 1);
+    // operand-table path: a group, or a fused run (whose records are then skipped)
+    const bool table = MFMA && full_waves && (type == KOP_GROUP || type == KOP_FUSED);
+    const int next = o + (type == KOP_GROUP ? 1 + REG_BITS : (type == KOP_FUSED && table) ? 1 + h.a : 1);
     OpHead hn = h;
-    if (next < o1) hn = load_head(ops + next);
-    if (MFMA && full_waves && type == KOP_GROUP) {
-      // table of this choice of the members' slots: bit j = slot bit of the j-th slotted member
-      const int slots[4] = {h.b, h.slot, h.cond, h.nterms};
-      int sel = 0, j = 0;
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        if (slots[p] >= 0) {
-          sel |= ((variant >> slots[p]) & 1) << j;
-          ++j;
-        }
-      }
-      const uint4* gt = gtab + (uint64_t)(h.pad0 + sel) * GROUP_TABLE_UINT4 + (threadIdx.x & 63) * 4;
+    if (next < o1) hn = lds_head(hdr + (next - pass_op));
+    if (table) {
+      const uint4* gt = gtab + (uint64_t)table_index(h, variant) * GROUP_TABLE_UINT4 + (threadIdx.x & 63) * 4;
       group_mfma(a, gt);
+    } else if (type == KOP_FUSED) {
+      // float32 path: the run's records follow and run one by one
     } else if (type == KOP_GROUP) {
       // one 2x2 gate per register position: every matrix address comes from the
       // header, the four matrices are fetched together, then straight-line arithmetic
@@ -266,7 +285,9 @@ __device__ __forceinline__ void run_stage_ops(float2 (&a)[R], const int (&idx)[R
 #pragma unroll
         for (int e = 0; e < R; ++e) par[e] = 0;
         for (int q = 0; q < h.nterms; ++q) {
-          const uint32_t sh = t[2 * q], mk = t[2 * q + 1];
+          // terms 0 and 1 come with the header
+          const uint32_t sh = q == 0 ? (uint32_t)h.a : q == 1 ? (uint32_t)h.pad0 : t[2 * q];
+          const uint32_t mk = q == 0 ? (uint32_t)h.b : q == 1 ? (uint32_t)h.pad1 : t[2 * q + 1];
 #pragma unroll
           for (int e = 0; e < R; ++e) {
             const uint32_t i = (uint32_t)idx[e];
@@ -350,27 +371,51 @@ __device__ __forceinline__ void run_ops_direct(float2* sh, int nb, const KOp* __
   }
 }
 
+// Index of the last job whose first workgroup is <= wg (jobs sorted by wg_begin):
+// a 64-ary search, one round of vector loads per level instead of a chain of
+// dependent scalar loads.  Every wavefront of the workgroup runs it.
+__device__ __forceinline__ int find_job(const SimJob* __restrict__ jobs, int n_jobs, int wg) {
+  const int lane = threadIdx.x & 63;
+  int lo = 0, n = n_jobs;  // the job lies in [lo, lo + n)
+  while (n > 1) {
+    const int step = (n + 63) >> 6;
+    const bool ok = lane * step < n && jobs[lo + lane * step].wg_begin <= wg;
+    const uint64_t m = __ballot(ok);  // lanes 0..i: wg_begin is non-decreasing
+    const int i = 63 - __builtin_clzll(m);
+    lo += i * step;
+    n = min(step, n - i * step);
+  }
+  return lo;
+}
+
+// First 32 bytes of a StageDesc: op range and register bits.
+struct StageHead {
+  int32_t op_begin, op_count, reg[REG_BITS], pad[2];
+};
+
+// hdr_cap / stg_cap: LDS room for the op headers and stage heads of the largest
+// pass of the launch (every pass of the launch has at most that many).
+// At most 128 VGPRs (four wavefronts per SIMD): two 512-thread workgroups share a
+// compute unit where their LDS allows it, one computing while the other waits.
 template <int NT, bool MFMA>
-__global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int n_jobs, int total_wg,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sim(const SimJob* __restrict__ jobs, int n_jobs, int total_wg,
                                             int wg_offset, const PassDesc* __restrict__ passes,
                                             const StageDesc* __restrict__ stages, const KOp* __restrict__ ops,
-                                            const uint4* __restrict__ gtab, float2* __restrict__ base) {
+                                            const uint4* __restrict__ gtab, float2* __restrict__ base, int hdr_cap,
+                                            int stg_cap) {
   const float scale_in = MFMA ? SIM_MFMA_SCALE : 1.0f, scale_out = MFMA ? 1.0f / SIM_MFMA_SCALE : 1.0f;
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* lo_tab = reinterpret_cast<uint64_t*>(smem);
   uint64_t* hi_tab = lo_tab + TAB;
-  float2* sh = reinterpret_cast<float2*>(hi_tab + TAB);
+  OpHead* hdr = reinterpret_cast<OpHead*>(hi_tab + TAB);
+  StageHead* stg = reinterpret_cast<StageHead*>(hdr + hdr_cap);
+  float2* sh = reinterpret_cast<float2*>(stg + stg_cap);
   const int tid = threadIdx.x;
 
   for (int w = blockIdx.x; w < total_wg; w += gridDim.x) {
     const int wg = w + wg_offset;
-    // job lookup: last job whose first workgroup is <= wg
-    int lo = 0, hi = n_jobs - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (jobs[mid].wg_begin <= wg) lo = mid; else hi = mid - 1;
-    }
-    const SimJob job = jobs[lo];
+    // the same index in every lane: readfirstlane lets the compiler keep the job in scalar registers
+    const SimJob job = jobs[n_jobs > 1 ? __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, wg)) : 0];
     const PassDesc* P = passes + job.pass_id;
     const int b = P->b;
     const int nb = 1 << b;
@@ -392,6 +437,18 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
         int u = t - TAB;
         for (int j = 0; j < b - 7; ++j) off |= (uint64_t)((u >> j) & 1) << P->group[7 + j];
         hi_tab[u] = off;
+      }
+    }
+    // the pass's op headers and stage heads, copied to LDS in one burst: the stages
+    // then read them without a scalar-cache miss each (one workgroup per compute
+    // unit finds nothing of them cached)
+    if (P->stage_count > 0) {
+      for (int t = tid; t < P->op_count; t += NT) hdr[t] = load_head(ops + P->op_begin + t);
+      for (int t = tid; t < P->stage_count; t += NT) {
+        const int4* q = reinterpret_cast<const int4*>(stages + P->stage_begin + t);
+        int4* d = reinterpret_cast<int4*>(stg + t);
+        d[0] = q[0];
+        d[1] = q[1];
       }
     }
     __syncthreads();
@@ -431,12 +488,17 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
       const int active = nb >> REG_BITS;  // thread slots per stage
       for (int si = 0; si < P->stage_count; ++si) {
         const StageDesc* S = stages + P->stage_begin + si;
+        const int4* sq = reinterpret_cast<const int4*>(stg + si);
+        const int4 s0 = sq[0], s1 = sq[1];
+        const int op_begin = __builtin_amdgcn_readfirstlane(s0.x), op_count = __builtin_amdgcn_readfirstlane(s0.y);
+        const int reg[REG_BITS] = {__builtin_amdgcn_readfirstlane(s0.z), __builtin_amdgcn_readfirstlane(s0.w),
+                                   __builtin_amdgcn_readfirstlane(s1.x), __builtin_amdgcn_readfirstlane(s1.y)};
         for (int tt = tid; tt < active; tt += NT) {
           // insert a zero at each register bit (ascending) to get the thread's base index
           int tb = tt;
 #pragma unroll
           for (int k = 0; k < REG_BITS; ++k) {
-            const int r = S->reg[k];
+            const int r = reg[k];
             tb = ((tb >> r) << (r + 1)) | (tb & ((1 << r) - 1));
           }
           const int pb = pad(tb);
@@ -447,8 +509,8 @@ __global__ __launch_bounds__(NT) void k_sim(const SimJob* __restrict__ jobs, int
             idx[e] = tb | S->roff[e];
             a[e] = sh[pb + S->proff[e]];
           }
-          run_stage_ops<MFMA>(a, idx, ops, S->op_begin, S->op_begin + S->op_count, blockbase, job.variant, gtab,
-                              (active & 63) == 0);
+          run_stage_ops<MFMA>(a, idx, ops, hdr, P->op_begin, op_begin, op_begin + op_count, blockbase, job.variant,
+                              gtab, (active & 63) == 0);
 #pragma unroll
           for (int e = 0; e < R; ++e) sh[pb + S->proff[e]] = a[e];
         }
@@ -473,63 +535,165 @@ __global__ __launch_bounds__(256) void k_table_copy(uint4* __restrict__ dst, con
     dst[i] = src[i];
 }
 
-constexpr size_t shmem_bytes(int bmax) {
-  return 2 * TAB * sizeof(uint64_t) + sizeof(float2) * (((size_t)1 << bmax) + ((size_t)1 << bmax) / 16);
+constexpr size_t shmem_bytes(int bmax, int hdr_cap, int stg_cap) {
+  return 2 * TAB * sizeof(uint64_t) + (size_t)hdr_cap * sizeof(OpHead) + (size_t)stg_cap * sizeof(StageHead) +
+         sizeof(float2) * (((size_t)1 << bmax) + ((size_t)1 << bmax) / 16);
 }
 
-// One wavefront per (group, slot choice): lane l writes its four uint4 of the
-// real 32x32 A operand (row m = l % 32, columns 16 s + 8 (l / 32) + e).
+// ---- operand tables: the 16x16 matrix of a group or fused run
+
+__device__ __forceinline__ double2 dmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 dadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// Applies one record of a fused run to the matrix G[row][col] held in LDS (float64),
+// every lane taking its share of the rows and columns.  Amplitude index e has bit p
+// of e at register position p (local bit lb[p]).  hdr: the slot fields of the run's
+// header (bit j of the table choice sel is the j-th non-negative one).  The caller
+// orders consecutive records with a barrier.
+__device__ __forceinline__ void fused_apply(const KOp* __restrict__ k, double2 (*G)[R + 1], const int (&hdr)[REG_BITS], int sel,
+                            const int (&lb)[REG_BITS], int lane) {
+  int bit = 0;
+  if (k->slot >= 0) {
+    int j = 0;
+#pragma unroll
+    for (int p = 0; p < REG_BITS; ++p) {
+      if (hdr[p] >= 0) {
+        if (hdr[p] == k->slot) bit = (sel >> j) & 1;
+        ++j;
+      }
+    }
+  }
+  const float* m = k->m + 8 * bit;
+  auto pos = [&](int local) {
+    int p = 0;
+#pragma unroll
+    for (int q = 0; q < REG_BITS; ++q)
+      if (lb[q] == local) p = q;
+    return p;
+  };
+  const int type = k->type;
+  if (type == KOP_DENSE || type == KOP_CXL) {
+    // 8 row pairs x 16 columns: two (pair, column) units per lane
+    const int p = type == KOP_DENSE ? k->a : k->b;
+    const int pc = type == KOP_CXL ? pos(k->a) : 0;
+    const double2 m00 = make_double2(m[0], m[1]), m01 = make_double2(m[2], m[3]);
+    const double2 m10 = make_double2(m[4], m[5]), m11 = make_double2(m[6], m[7]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int u = lane + 64 * i, col = u & 15, t = u >> 4;
+      const int e0 = ((t >> p) << (p + 1)) | (t & ((1 << p) - 1)), e1 = e0 | (1 << p);
+      const double2 x = G[e0][col], y = G[e1][col];
+      if (type == KOP_DENSE) {
+        G[e0][col] = dadd(dmul(m00, x), dmul(m01, y));
+        G[e1][col] = dadd(dmul(m10, x), dmul(m11, y));
+      } else if ((e0 >> pc) & 1) {
+        G[e0][col] = y;
+        G[e1][col] = x;
+      }
+    }
+  } else if (type == KOP_DIAG || type == KOP_CZL) {
+    // 256 entries: four per lane
+    const int pd = type == KOP_DIAG ? pos(k->a) : 0;
+    const double2 d0 = make_double2(m[0], m[1]), d1 = make_double2(m[6], m[7]);
+    const uint32_t* t = reinterpret_cast<const uint32_t*>(k->m);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int u = lane + 64 * i, row = u >> 4, col = u & 15;
+      if (type == KOP_DIAG) {
+        G[row][col] = dmul(((row >> pd) & 1) ? d1 : d0, G[row][col]);
+      } else {
+        uint32_t li = 0;
+#pragma unroll
+        for (int q = 0; q < REG_BITS; ++q) li |= (uint32_t)((row >> q) & 1) << lb[q];
+        uint32_t par = 0;
+        for (int q = 0; q < k->nterms; ++q) par += __popc(li & (li >> t[2 * q]) & t[2 * q + 1]);
+        if (par & 1) G[row][col] = make_double2(-G[row][col].x, -G[row][col].y);
+      }
+    }
+  }
+  // a group header inside the run: its member records follow
+}
+
+// One wavefront per (group or fused run, slot choice); lane l writes its four
+// uint4 of the real 32x32 A operand (row m = l % 32, columns 16 s + 8 (l / 32) + e):
+// hi and lo float16 parts, rounded to nearest.  A group's entries are products of
+// its four 2x2 matrices (float32, each lane its own); a fused run's matrix is
+// composed in LDS (float64), its records staged in LDS and applied in order to
+// the identity.
 __global__ __launch_bounds__(64) void k_group_tables(const KOp* __restrict__ ops, const GroupRef* __restrict__ refs,
                                                      uint4* __restrict__ gtab) {
+  __shared__ double2 G[R][R + 1];  // G[row][col]
+  __shared__ __align__(16) KOp recs[FUSED_MAX_RECORDS];
   const GroupRef ref = refs[blockIdx.x];
   const KOp* g = ops + ref.op;
   const int lane = threadIdx.x;
-  // 2x2 matrix of position p for this slot choice: u[p][2 * row + col]
-  float2 u[4][4];
-  int j = 0;
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const KOp* k = g + 1 + p;
-    int bit = 0;
-    if (k->slot >= 0) {
-      bit = (ref.sel >> j) & 1;
-      ++j;
-    }
-    const float* m = k->m + 8 * bit;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) u[p][t] = make_float2(m[2 * t], m[2 * t + 1]);
-  }
   const int m = lane & 31, h = lane >> 5;
   // output rows interleaved: row 2 e = Re y_e, row 2 e + 1 = Im y_e, so that each
   // amplitude's two parts land in adjacent accumulator registers
   const int row = m >> 1;
   const bool imag_row = m & 1;
   uint32_t hi[2][4], lo[2][4];
+  // entries (A[m][16 st + 8 h + c], c and c + 1) to float16 hi / lo pairs
+  auto pack = [&](int st, int c, double v0, double v1) {
+    const _Float16 h0 = (_Float16)(float)v0, h1 = (_Float16)(float)v1;
+    const _Float16 l0 = (_Float16)(float)(v0 - (double)h0), l1 = (_Float16)(float)(v1 - (double)h1);
+    hi[st][c / 2] = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+    lo[st][c / 2] = (uint32_t)__builtin_bit_cast(uint16_t, l0) | ((uint32_t)__builtin_bit_cast(uint16_t, l1) << 16);
+  };
+  // row 2 e: Re y = Re G Re x - Im G Im x;  row 2 e + 1: Im y = Im G Re x + Re G Im x
+  if (g->type == KOP_FUSED) {
+    const int hdr[REG_BITS] = {g->b, g->slot, g->cond, g->nterms};
+    const int32_t* bits = reinterpret_cast<const int32_t*>(g->m);
+    int lb[REG_BITS];
 #pragma unroll
-  for (int e = 0; e < 8; e += 2) {
-    float v0[2], v1[2];  // [k-step]
+    for (int p = 0; p < REG_BITS; ++p) lb[p] = bits[p];
+    const int n = g->a;
+    constexpr int U4 = (int)(sizeof(KOp) / 16);
+    for (int i = lane; i < n * U4; i += 64)
+      reinterpret_cast<uint4*>(recs)[i] = reinterpret_cast<const uint4*>(g + 1)[i];
 #pragma unroll
-    for (int d = 0; d < 2; ++d) {
-      const int col = 8 * h + e + d;
-      float2 gv = make_float2(1.f, 0.f);
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const bool rb = (row >> p) & 1, cb = (col >> p) & 1;  // selects, no indexed register array
-        const float2 f = rb ? (cb ? u[p][3] : u[p][2]) : (cb ? u[p][1] : u[p][0]);
-        gv = cmul(gv, f);
-      }
-      // row 2 e: Re y = Re G Re x - Im G Im x;  row 2 e + 1: Im y = Im G Re x + Re G Im x
-      const float s0 = imag_row ? gv.y : gv.x;
-      const float s1 = imag_row ? gv.x : -gv.y;
-      if (d == 0) { v0[0] = s0; v0[1] = s1; } else { v1[0] = s0; v1[1] = s1; }
+    for (int i = 0; i < 4; ++i) {
+      const int u = lane + 64 * i;
+      G[u >> 4][u & 15] = make_double2((u >> 4) == (u & 15) ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    for (int r = 0; r < n; ++r) {
+      fused_apply(recs + r, G, hdr, ref.sel, lb, lane);
+      __syncthreads();
     }
 #pragma unroll
-    for (int st = 0; st < 2; ++st) {
-      // float16 hi / lo of the float32 products: round to nearest for the table
-      const _Float16 h0 = (_Float16)v0[st], h1 = (_Float16)v1[st];
-      const _Float16 l0 = (_Float16)(v0[st] - (float)h0), l1 = (_Float16)(v1[st] - (float)h1);
-      hi[st][e / 2] = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
-      lo[st][e / 2] = (uint32_t)__builtin_bit_cast(uint16_t, l0) | ((uint32_t)__builtin_bit_cast(uint16_t, l1) << 16);
+    for (int c = 0; c < 8; c += 2) {
+      const double2 g0 = G[row][8 * h + c], g1 = G[row][8 * h + c + 1];
+      pack(0, c, imag_row ? g0.y : g0.x, imag_row ? g1.y : g1.x);
+      pack(1, c, imag_row ? g0.x : -g0.y, imag_row ? g1.x : -g1.y);
+    }
+  } else {
+    // 2x2 matrix of position p for this slot choice, in LDS: u[p][2 * row + col]
+    // (read below at lane-dependent indices)
+    __shared__ float2 u[REG_BITS][4];
+    if (lane < 16) {
+      const int p = lane >> 2, t = lane & 3;
+      int j = 0;
+#pragma unroll
+      for (int q = 0; q < REG_BITS; ++q) j += q < p && g[1 + q].slot >= 0;
+      const KOp* k = g + 1 + p;
+      const int bit = k->slot >= 0 ? (ref.sel >> j) & 1 : 0;
+      u[p][t] = make_float2(k->m[8 * bit + 2 * t], k->m[8 * bit + 2 * t + 1]);
+    }
+    __syncthreads();
+    auto entry = [&](int col) {
+      float2 gv = make_float2(1.f, 0.f);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) gv = cmul(gv, u[p][2 * ((row >> p) & 1) + ((col >> p) & 1)]);
+      return gv;
+    };
+#pragma unroll
+    for (int c = 0; c < 8; c += 2) {
+      const float2 g0 = entry(8 * h + c), g1 = entry(8 * h + c + 1);
+      pack(0, c, imag_row ? g0.y : g0.x, imag_row ? g1.y : g1.x);
+      pack(1, c, imag_row ? g0.x : -g0.y, imag_row ? g1.x : -g1.y);
     }
   }
   uint4* out = gtab + (uint64_t)blockIdx.x * GROUP_TABLE_UINT4 + lane * 4;
@@ -541,36 +705,36 @@ __global__ __launch_bounds__(64) void k_group_tables(const KOp* __restrict__ ops
 
 template <int NT, bool MFMA>
 int launch_sim_t(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
-                 const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int grid,
-                 hipStream_t s) {
-  const size_t shmem = shmem_bytes(bmax);
+                 const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int hdr_cap,
+                 int stg_cap, int grid, hipStream_t s) {
+  const size_t shmem = shmem_bytes(bmax, hdr_cap, stg_cap);
   static bool attr_set = false;
   if (!attr_set) {
     CCUT_HIP(hipFuncSetAttribute((const void*)k_sim<NT, MFMA>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)shmem_bytes(PASS_MAX_B)));
+                                 (int)SIM_LDS_MAX));
     attr_set = true;
   }
   ProfScope prof(PROF_SIM, s);
   hipLaunchKernelGGL((k_sim<NT, MFMA>), dim3(grid), dim3(NT), shmem, s, d_jobs, n_jobs, total_wg, wg_offset,
-                     d_passes, d_stages, d_ops, gtab, reinterpret_cast<float2*>(base));
+                     d_passes, d_stages, d_ops, gtab, reinterpret_cast<float2*>(base), hdr_cap, stg_cap);
   CCUT_HIP(hipGetLastError());
   return 0;
 }
 
 template <bool MFMA>
 int launch_sim_m(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
-                 const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax,
-                 int threads, int grid, hipStream_t s) {
+                 const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int hdr_cap,
+                 int stg_cap, int threads, int grid, hipStream_t s) {
   switch (threads) {
     case 256:
       return launch_sim_t<256, MFMA>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base,
-                                     bmax, grid, s);
+                                     bmax, hdr_cap, stg_cap, grid, s);
     case 512:
       return launch_sim_t<512, MFMA>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base,
-                                     bmax, grid, s);
+                                     bmax, hdr_cap, stg_cap, grid, s);
     case 1024:
       return launch_sim_t<1024, MFMA>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base,
-                                      bmax, grid, s);
+                                      bmax, hdr_cap, stg_cap, grid, s);
     default:
       return fail(CCUT_EINVAL, "unsupported workgroup size %d", threads);
   }
@@ -578,17 +742,22 @@ int launch_sim_m(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, 
 
 }  // namespace
 
+size_t sim_shmem_bytes(int bmax, int hdr_cap, int stg_cap) { return shmem_bytes(bmax, hdr_cap, stg_cap); }
+
 int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
-               const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int threads,
-               int grid_cap, hipStream_t s) {
+               const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int hdr_cap,
+               int stg_cap, int threads, int grid_cap, hipStream_t s) {
   if (total_wg <= 0 || n_jobs <= 0) return 0;
   if (bmax < 1 || bmax > PASS_MAX_B) return fail(CCUT_EINVAL, "bad block bits %d", bmax);
+  if (hdr_cap < 0 || stg_cap < 0 || shmem_bytes(bmax, hdr_cap, stg_cap) > SIM_LDS_MAX)
+    return fail(CCUT_EUNSUPPORTED, "simulation pass needs %zu bytes of LDS (at most %zu)",
+                shmem_bytes(bmax, hdr_cap, stg_cap), (size_t)SIM_LDS_MAX);
   const int grid = (grid_cap > 0 && grid_cap < total_wg) ? grid_cap : total_wg;
   if (gtab)
     return launch_sim_m<true>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base, bmax,
-                              threads, grid, s);
+                              hdr_cap, stg_cap, threads, grid, s);
   return launch_sim_m<false>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, nullptr, base, bmax,
-                             threads, grid, s);
+                             hdr_cap, stg_cap, threads, grid, s);
 }
 
 int launch_table_copy(void* dst, const void* host_src, uint64_t bytes, hipStream_t s) {

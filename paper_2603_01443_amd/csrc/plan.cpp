@@ -15,7 +15,7 @@ namespace ccut {
 uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<StageDesc>& stages,
-                std::vector<KOp>& kops, std::vector<GroupRef>& grefs) {
+                std::vector<KOp>& kops, std::vector<GroupRef>& grefs, bool fuse) {
   PassDesc d;
   std::memset(&d, 0, sizeof(d));
   d.b = (int32_t)p.group.size();
@@ -37,7 +37,7 @@ int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector
     // register stages carry their own (stage-level) op ranges
     std::vector<StageDesc> st;
     std::vector<KOp> sk;
-    stage_kops(p.kops, d.b, st, sk);
+    stage_kops(p.kops, d.b, st, sk, fuse);
     const int32_t base = (int32_t)kops.size();
     for (StageDesc& s : st) s.op_begin += base;
     d.stage_begin = (int32_t)stages.size();
@@ -46,16 +46,16 @@ int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector
     d.op_count = (int32_t)sk.size();
     stages.insert(stages.end(), st.begin(), st.end());
     kops.insert(kops.end(), sk.begin(), sk.end());
-    // one MFMA operand table per group and choice of its members' slots
+    // one MFMA operand table per group (or fused run) and choice of its slots; the
+    // records inside a fused run need none (the float32 path reads their matrices)
     for (size_t i = base; i < kops.size(); ++i) {
       KOp& g = kops[i];
-      if (g.type != KOP_GROUP) continue;
-      int nslot = 0;
-      for (int m = 1; m <= REG_BITS; ++m) nslot += kops[i + m].slot >= 0;
+      if (g.type != KOP_GROUP && g.type != KOP_FUSED) continue;
+      const int nslot = (g.b >= 0) + (g.slot >= 0) + (g.cond >= 0) + (g.nterms >= 0);
       g.pad[0] = (int32_t)grefs.size();
       g.pad[1] = nslot;
       for (int sel = 0; sel < (1 << nslot); ++sel) grefs.push_back(GroupRef{(int32_t)i, sel});
-      i += REG_BITS;
+      i += g.type == KOP_GROUP ? REG_BITS : g.a;
     }
   } else {
     kops.insert(kops.end(), p.kops.begin(), p.kops.end());
@@ -137,7 +137,7 @@ int build_tree_launches(ccut_plan* P) {
       std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P->segs[a].q > P->segs[b].q; });
       for (int i : order) {
         auto& S = P->segs[i];
-        int pid = append_pass(S.chunk_passes[l][p], S.q, P->pass_descs, P->stage_descs, P->kops, P->grefs);
+        int pid = append_pass(S.chunk_passes[l][p], S.q, P->pass_descs, P->stage_descs, P->kops, P->grefs, P->fuse);
         int nb = P->pass_descs[pid].n_blocks;
         const uint64_t half = S.c > 0 ? ((uint64_t)1 << (S.c - 1)) << S.q : 0;  // elements per ping-pong half
         for (int64_t u = 0; u < ((int64_t)1 << l); ++u) {
@@ -200,7 +200,7 @@ int build_sim_tables(ccut_plan* P, bool first) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P->segs[a].q > P->segs[b].q; });
     for (int i : order) {
       auto& S = P->segs[i];
-      int pid = append_pass(S.passes[p], S.q, P->pass_descs, P->stage_descs, P->kops, P->grefs);
+      int pid = append_pass(S.passes[p], S.q, P->pass_descs, P->stage_descs, P->kops, P->grefs, P->fuse);
       int nb = P->pass_descs[pid].n_blocks;
       for (int64_t r = 0; r < ((int64_t)1 << S.c); ++r) {
         SimJob j;
@@ -218,6 +218,16 @@ int build_sim_tables(ccut_plan* P, bool first) {
     }
     P->launches.push_back(L);
   }
+  }
+
+  for (auto& L : P->launches) {
+    for (int j = L.job_begin; j < L.job_begin + L.n_jobs; ++j) {
+      const PassDesc& d = P->pass_descs[P->jobs[j].pass_id];
+      if (d.stage_count > 0) {
+        L.hdr_cap = std::max(L.hdr_cap, d.op_count);
+        L.stg_cap = std::max(L.stg_cap, d.stage_count);
+      }
+    }
   }
 
   pack_image(P);

@@ -47,12 +47,14 @@ struct ccut_plan {
   int prefix_mode = -1;                       // prefix sharing: 0 off, 1 on, -1 automatic
   int prefix_start = 0;                       // first tree level (the slots below it run flat)
   bool prefix_on = false;                     // in use by the current tables
+  bool fuse = false;                          // register-stage gate fusion (ccut_plan_set_fusion)
   std::vector<ccut::PassDesc> pass_descs;
   std::vector<ccut::StageDesc> stage_descs;
   std::vector<ccut::KOp> kops;
   std::vector<ccut::GroupRef> grefs;  // MFMA operand tables of the register-stage groups
   std::vector<ccut::SimJob> jobs;
-  struct Launch { int job_begin, n_jobs, total_wg; };
+  // hdr_cap / stg_cap: LDS room for the op headers and stage heads of its passes
+  struct Launch { int job_begin, n_jobs, total_wg, hdr_cap = 0, stg_cap = 0; };
   std::vector<Launch> launches;
 
   // Packed table image (ops | passes | jobs | weights) and where it sits in the arena.
@@ -97,9 +99,9 @@ uint64_t align256(uint64_t x);
 int auto_block_bits(const ccut_plan* P);
 // (Re)schedules the simulation at the plan's block size and repacks its tables.
 int build_sim_tables(ccut_plan* P, bool first);
-// Appends a pass to the device tables; returns its PassDesc index.
+// Appends a pass to the device tables; returns its PassDesc index (fuse: see stage_kops).
 int append_pass(const Pass& p, int nq, std::vector<PassDesc>& descs, std::vector<StageDesc>& stages,
-                std::vector<KOp>& kops, std::vector<GroupRef>& grefs);
+                std::vector<KOp>& kops, std::vector<GroupRef>& grefs, bool fuse);
 int gate_matrix(const ccut_gate_t& g, cd m[4]);
 void release_device(DeviceTables& t);
 // Copies a table image to a new device allocation (synchronous).

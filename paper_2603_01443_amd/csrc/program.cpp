@@ -348,9 +348,139 @@ void kop_roles(const KOp& k, int* nd, int* n_nd, int* dg, int* n_dg) {
   }
 }
 
+// Adds the CZ pairs (j, j + shift) of the bits in `mask` to a KOP_CZL record.
+// Returns false (record unchanged) when a new shift does not fit.
+bool add_cz_terms(KOp& k, uint32_t shift, uint32_t mask) {
+  if (!mask) return true;
+  uint32_t* t = reinterpret_cast<uint32_t*>(k.m);
+  for (int i = 0; i < k.nterms; ++i)
+    if (t[2 * i] == shift) {
+      t[2 * i + 1] ^= mask;  // CZ twice on one pair is the identity
+      return true;
+    }
+  if (k.nterms == KOP_MAX_TERMS) return false;
+  t[2 * k.nterms] = shift;
+  t[2 * k.nterms + 1] = mask;
+  ++k.nterms;
+  return true;
+}
+
+// Emits one stage's items (single ops, or a KOP_GROUP with its members) in
+// order, folding what acts on the register positions alone into KOP_FUSED runs:
+// - a run collects groups, and diagonal phases, CZ pairs and CX gates whose bits
+//   are all register bits, with at most four distinct variant slots; it becomes a
+//   KOP_FUSED record (one 16x16 matrix) when it holds a group and something more;
+// - diagonal ops on bits outside the register set (phases, CZ pairs with both
+//   bits outside, block-wide scalars) commute with every op of the stage, whose
+//   non-diagonal actions are all on register bits: they are applied after it;
+// - a CZ pair with one bit inside and one outside (a Z on a register position,
+//   conditioned per thread) and every other op end the run.
+void emit_fused(const std::vector<std::vector<KOp>>& items, const std::vector<int>& reg,
+                const std::vector<int>& pos_of, std::vector<KOp>& out) {
+  const int nb = (int)pos_of.size();
+  auto in_reg = [&](int j) { return j >= 0 && j < nb && pos_of[j] >= 0; };
+  std::vector<KOp> run, tail;
+  std::vector<int> run_slots;
+  int run_groups = 0, run_other = 0;
+  KOp outside = blank(KOP_CZL);
+  auto flush = [&]() {
+    if (run_groups >= 2 || (run_groups == 1 && run_other > 0)) {
+      KOp h = blank(KOP_FUSED);
+      h.a = (int32_t)run.size();
+      int sl[REG_BITS] = {-1, -1, -1, -1};
+      for (size_t i = 0; i < run_slots.size(); ++i) sl[i] = run_slots[i];
+      h.b = sl[0];
+      h.slot = sl[1];
+      h.cond = sl[2];
+      h.nterms = sl[3];
+      int32_t bits[REG_BITS];
+      for (int p = 0; p < REG_BITS; ++p) bits[p] = reg[p];
+      std::memcpy(h.m, bits, sizeof(bits));
+      out.push_back(h);
+    }
+    out.insert(out.end(), run.begin(), run.end());
+    run.clear();
+    run_slots.clear();
+    run_groups = run_other = 0;
+  };
+  // slots the records would add to the run; false if more than four in all
+  auto fits = [&](const std::vector<KOp>& rec, std::vector<int>& slots) {
+    slots = run_slots;
+    for (const KOp& k : rec)
+      if (k.type != KOP_GROUP && k.slot >= 0 && std::find(slots.begin(), slots.end(), k.slot) == slots.end())
+        slots.push_back(k.slot);
+    return slots.size() <= (size_t)REG_BITS;
+  };
+  auto join = [&](const std::vector<KOp>& rec, bool group) {
+    std::vector<int> slots;
+    if (!fits(rec, slots) || run.size() + rec.size() > (size_t)FUSED_MAX_RECORDS) {
+      flush();
+      fits(rec, slots);
+    }
+    run_slots = slots;
+    run.insert(run.end(), rec.begin(), rec.end());
+    (group ? run_groups : run_other) += 1;
+  };
+  auto defer = [&](const KOp& k) { tail.push_back(k); };
+  for (const auto& rec : items) {
+    const KOp& k = rec[0];
+    switch (k.type) {
+      case KOP_GROUP:
+        join(rec, true);
+        break;
+      case KOP_DIAG:
+        if (!in_reg(k.a)) defer(k);
+        else if (k.cond < 0) join(rec, false);
+        else { flush(); out.push_back(k); }
+        break;
+      case KOP_SCALAR:
+        defer(k);
+        break;
+      case KOP_CXL:
+        if (in_reg(k.a)) join(rec, false);
+        else { flush(); out.push_back(k); }
+        break;
+      case KOP_CZL: {
+        KOp inside = blank(KOP_CZL), cross = blank(KOP_CZL);
+        const uint32_t* t = reinterpret_cast<const uint32_t*>(k.m);
+        for (int i = 0; i < k.nterms; ++i) {
+          const uint32_t sh = t[2 * i], mk = t[2 * i + 1];
+          uint32_t mi = 0, mc = 0, mo = 0;
+          for (int j = 0; j < 32; ++j) {
+            if (!((mk >> j) & 1)) continue;
+            const bool a_in = in_reg(j), b_in = in_reg(j + (int)sh);
+            (a_in && b_in ? mi : (a_in || b_in) ? mc : mo) |= 1u << j;
+          }
+          add_cz_terms(inside, sh, mi);  // at most the record's own term count
+          add_cz_terms(cross, sh, mc);
+          if (!add_cz_terms(outside, sh, mo)) {
+            defer(outside);
+            outside = blank(KOP_CZL);
+            add_cz_terms(outside, sh, mo);
+          }
+        }
+        if (inside.nterms > 0) join({inside}, false);
+        if (cross.nterms > 0) {
+          flush();
+          out.push_back(cross);
+        }
+        break;
+      }
+      default:  // conditional 2x2 gates
+        flush();
+        out.push_back(k);
+        break;
+    }
+  }
+  flush();
+  if (outside.nterms > 0) out.push_back(outside);
+  out.insert(out.end(), tail.begin(), tail.end());
+}
+
 }  // namespace
 
-void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& stages, std::vector<KOp>& out) {
+void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& stages, std::vector<KOp>& out,
+                bool fuse) {
   std::vector<int> pending(kops.size());
   for (size_t i = 0; i < pending.size(); ++i) pending[i] = (int)i;
   while (!pending.empty()) {
@@ -396,13 +526,14 @@ void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& sta
     }
     // Runs of unconditional 2x2 gates on distinct register positions become one
     // KOP_GROUP (they act on different qubits, so their order inside the run is free).
+    std::vector<std::vector<KOp>> items;
     for (size_t t = 0; t < take.size();) {
       const KOp& k0 = kops[take[t]];
       if (k0.type != KOP_DENSE || k0.cond >= 0) {
         KOp k = k0;
         if (k.type == KOP_DENSE) k.a = pos_of[k.a];
         if (k.type == KOP_CXL) k.b = pos_of[k.b];
-        out.push_back(k);
+        items.push_back({k});
         ++t;
         continue;
       }
@@ -431,8 +562,23 @@ void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& sta
       g.slot = members[1].slot;
       g.cond = members[2].slot;
       g.nterms = members[3].slot;
-      out.push_back(g);
-      for (int p = 0; p < REG_BITS; ++p) out.push_back(members[p]);
+      items.push_back({g});
+      for (int p = 0; p < REG_BITS; ++p) items.back().push_back(members[p]);
+    }
+    const size_t first = out.size();
+    if (fuse) {
+      emit_fused(items, reg, pos_of, out);
+    } else {
+      for (const auto& rec : items) out.insert(out.end(), rec.begin(), rec.end());
+    }
+    for (size_t i = first; i < out.size(); ++i) {
+      KOp& k = out[i];
+      if (k.type != KOP_CZL) continue;
+      const uint32_t* t = reinterpret_cast<const uint32_t*>(k.m);
+      k.a = (int32_t)t[0];
+      k.b = (int32_t)t[1];
+      k.pad[0] = k.nterms > 1 ? (int32_t)t[2] : 0;
+      k.pad[1] = k.nterms > 1 ? (int32_t)t[3] : 0;
     }
     st.op_count = (int32_t)out.size() - st.op_begin;
     stages.push_back(st);

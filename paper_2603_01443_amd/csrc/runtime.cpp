@@ -112,7 +112,7 @@ uint64_t layout_key(const ccut_plan* P) {
   h = mix(h, u, sizeof(u));
   const int32_t v[] = {P->bmax, P->prefix_on ? 1 : 0, P->prefix_start, P->sim_threads, P->sim_grid_cap,
                        P->sim_per_variant, P->sim_precision, P->merge_epilogue, P->merge_grid_cap,
-                       P->auto_mfma_min_k, P->auto_mfma_mode, (int32_t)P->grefs.size()};
+                       P->auto_mfma_min_k, P->auto_mfma_mode, (int32_t)P->grefs.size(), P->fuse ? 1 : 0};
   h = mix(h, v, sizeof(v));
   for (const auto& L : P->launches) h = mix(h, &L, sizeof(L));
   for (const auto& st : P->stages) h = mix(h, &st, sizeof(st));
@@ -179,6 +179,7 @@ extern "C" int ccut_plan_work(const ccut_plan_t* plan, double out[5]) {
     const PassDesc& pd = plan->pass_descs[d];
     for (int i = pd.op_begin; i < pd.op_begin + pd.op_count; ++i) {
       const KOp& k = plan->kops[i];
+      if (k.type == KOP_FUSED) continue;  // header only: its records follow
       if (k.type == KOP_GROUP) {
         per[d][0] += __builtin_popcount((unsigned)k.a);
         i += REG_BITS;  // its member records
@@ -227,6 +228,7 @@ extern "C" int ccut_plan_stats(const ccut_plan_t* plan, int64_t out[8]) {
   int64_t dense = 0, diag = 0;
   for (size_t i = 0; i < plan->kops.size(); ++i) {
     const KOp& k = plan->kops[i];
+    if (k.type == KOP_FUSED) continue;  // header only: its records follow
     if (k.type == KOP_GROUP) {
       dense += __builtin_popcount((unsigned)k.a);
       i += REG_BITS;  // its member records
@@ -313,6 +315,27 @@ extern "C" int ccut_plan_get_prefix_start(const ccut_plan_t* plan, int32_t* out)
   clear_error();
   if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
   *out = plan->prefix_start;
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_set_fusion(ccut_plan_t* plan, int32_t on) {
+  clear_error();
+  if (!plan) return fail(CCUT_EINVAL, "plan is NULL");
+  if (on != 0 && on != 1) return fail(CCUT_EINVAL, "fusion %d (0 off, 1 on)", on);
+  const bool saved = plan->fuse;
+  plan->fuse = on == 1;
+  if (int rc = build_sim_tables(plan, false)) {
+    plan->fuse = saved;
+    (void)build_sim_tables(plan, false);
+    return rc;
+  }
+  return CCUT_OK;
+}
+
+extern "C" int ccut_plan_get_fusion(const ccut_plan_t* plan, int32_t* out) {
+  clear_error();
+  if (!plan || !out) return fail(CCUT_EINVAL, "NULL argument");
+  *out = plan->fuse ? 1 : 0;
   return CCUT_OK;
 }
 

@@ -215,6 +215,28 @@ def test_prefix_sharing_tree_shape():
             ccut.plan_set_prefix_sharing(plan, bad)
 
 
+def test_gate_fusion_option():
+    """Fusion reschedules the stages but not the work: the same gate applications and
+    passes; off by default; only 0 and 1 accepted; the graph layout changes with it."""
+    q, n = 20, 2
+    plan = ccut.cut_plan(q, brickwork(q, 10, n, 4, seed=3), n)
+    ccut.plan_set_block_bits(plan, 12)
+    assert not ccut.plan_get_fusion(plan)
+    flat_work, flat_stats = ccut.plan_work(plan), ccut.plan_stats(plan)
+    ccut.plan_set_fusion(plan, True)
+    assert ccut.plan_get_fusion(plan)
+    fused_work, fused_stats = ccut.plan_work(plan), ccut.plan_stats(plan)
+    for k in ("dense_amp_ops", "diag_amp_ops", "amps_moved", "flat_dense_amp_ops"):
+        assert fused_work[k] == flat_work[k], k
+    assert fused_stats["passes"] == flat_stats["passes"] and fused_stats["stages"] == flat_stats["stages"]
+    assert fused_stats["device_ops"] > flat_stats["device_ops"]   # run headers, split CZ records
+    ccut.plan_set_fusion(plan, False)
+    assert ccut.plan_stats(plan) == flat_stats
+    for bad in (-1, 2):
+        with pytest.raises(ccut.CcutError):
+            ccut.plan_set_fusion(plan, bad)
+
+
 def test_expectation_argument_checks():
     """Label and workspace errors come back before anything touches the GPU."""
     plan = ccut.cut_plan(12, brickwork(12, 4, 2, 2, seed=0), 2)

@@ -258,6 +258,52 @@ def test_prefix_sharing_matches_oracle(lib, prec, bits, start):
             assert metrics.one_minus_fidelity(ref, got) < 1e-9, (prec, bits, i, r)
 
 
+@pytest.mark.parametrize("prec,bits,prefix,start", [("fp16x3", 13, 0, 0), ("fp16x3", 12, 1, 2), ("fp16x3", 11, 1, 0),
+                                                     ("fp32", 12, 0, 0), ("fp16x3", 9, 0, 0)])
+def test_gate_fusion_matches_oracle(lib, prec, bits, prefix, start):
+    """Register-stage gate fusion (one 16x16 matrix per run of gates confined to a stage's
+    register qubits, composed on the device per slot choice; CZ pairs outside the register set
+    applied at the stage's end) gives the oracle's subcircuit states: MFMA and float32 stages,
+    flat and tree schedules, several passes, and blocks below the MFMA minimum."""
+    ccut, pipeline = lib
+    o = _q26_oracle()
+    run = pipeline.CutRun(26, o["g"], 2)
+    ccut.plan_set_sim_precision(run.plan, prec)
+    ccut.plan_set_block_bits(run.plan, bits)
+    ccut.plan_set_prefix_sharing(run.plan, prefix)
+    if prefix:
+        ccut.plan_set_prefix_start(run.plan, start)
+    ccut.plan_set_fusion(run.plan, True)
+    assert ccut.plan_get_fusion(run.plan)
+    run.arena.zero_()
+    run.simulate_subcircuits()
+    torch.cuda.synchronize()
+    pcuts = run.plan.cuts()
+    worst = 0.0
+    for i in range(2):
+        for r in range(16):
+            ref = o["ostates"][oracle_key(pcuts, o["ocuts"], i, r)]
+            got = to_np(run.variant_state(i, r))
+            worst = max(worst, metrics.max_abs_error(ref, got))
+            assert metrics.one_minus_fidelity(ref, got) < 1e-9, (prec, bits, i, r)
+    print(f"fused {prec} bits {bits} prefix {prefix}/{start}: worst max-abs {worst:.3e}", flush=True)
+    assert worst < fp32_tol(13)
+
+
+@pytest.mark.parametrize("q,n,c,kind", [(15, 3, 6, "brickwork"), (12, 3, 4, "staircase")])
+def test_gate_fusion_full_pipeline(lib, q, n, c, kind):
+    """Fused stages through the whole pipeline (three segments, CX cuts with H S H on the
+    target side) against the oracle's plain sum."""
+    ccut, pipeline = lib
+    g = brickwork(q, 12, n, c, seed=q + c) if kind == "brickwork" else staircase(q, c // (n - 1))
+    sizes = equal_blocks(q, n)
+    run = pipeline.CutRun(q, g, n, sizes)
+    ccut.plan_set_fusion(run.plan, True)
+    psi = to_np(run.run("fp32"))
+    ref = cutting.cut_simulate(q, g, sizes)
+    check_state(ref, psi, q, f"fused q{q} n{n} c{c} {kind}")
+
+
 @pytest.mark.parametrize("q,n,c,kind,start", [(20, 2, 8, "brickwork", 0), (12, 3, 4, "staircase", 0),
                                               (15, 3, 6, "brickwork", 0), (20, 2, 8, "brickwork", 3),
                                               (15, 3, 6, "brickwork", 4)])
