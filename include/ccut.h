@@ -387,10 +387,14 @@ int ccut_plan_work(const ccut_plan_t* plan, double out[5]);
  * wavefront).  epilogue 4 is the R-stationary kernel: one 16-wavefront
  * workgroup per CU keeps a 128-column strip of the low-qubit factor (all
  * terms, hi and lo) in LDS and sweeps all rows of its strip; it covers up to
- * K = 64 terms per stage and runs larger stages as epilogue 1.
+ * K = 64 terms per stage and runs larger stages as epilogue 1.  epilogue 5 is
+ * the LDS-staged kernel for many terms: one 8-wavefront workgroup per CU loops
+ * over 256-row x 256-column tiles, loading each MFMA step's fragments of both
+ * factors once per tile (two steps ahead) into LDS (double-buffered) for all its
+ * wavefronts; stages with fewer than 256 rows run as epilogue 1.
  * grid_cap 0 launches one workgroup per tile, > 0 a persistent grid of at most
- * grid_cap workgroups looping over tiles (ignored by epilogue 4, whose grid is
- * one workgroup per CU).  Results do not depend on either.
+ * grid_cap workgroups looping over tiles (ignored by epilogues 4 and 5, whose
+ * grid is one workgroup per CU).  Results do not depend on either.
  * Host-only.  Errors: CCUT_EINVAL.
  */
 int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap);

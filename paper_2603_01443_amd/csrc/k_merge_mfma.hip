@@ -473,9 +473,227 @@ __global__ __launch_bounds__(RS_WAVES * 64) void k_merge_gemm_rs(
   }
 }
 
+// 16-byte items as a native vector type: HIP's uint4 is copied through memcpy,
+// which keeps arrays of it out of registers
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+
+// ------------------------------------------ LDS-staged GEMM (large K)
+// For many MFMA steps the tiled kernel above loads every wavefront's fragments
+// from L2 on their own (3 to 5 times the output size in all).  Here a workgroup
+// of 8 wavefronts (4 x 2) owns a 256-row x 256-column tile, each wavefront
+// 64 x 128 (2 x 4 blocks of 32 x 32): per MFMA step the tile's 8 L and 8 R
+// fragments (both planes: 32 KiB in the three-product modes) are loaded from L2
+// once, two steps ahead (two register sets), and copied into one of two LDS
+// buffers, from which every wavefront reads its own.  Per step and output block
+// the products run in the tiled kernel's order (lo.hi, hi.lo, hi.hi), so the
+// results are the same bit for bit.  One workgroup per CU, persistent over the
+// tiles; the stream of steps runs on across tiles, so a tile's stores (through LDS,
+// 16-row slabs, 512-byte row segments) are issued after the next tile's first
+// loads.  Measured at q = 30, K = 256: as fast as the tiled kernel for fp16x3 and
+// bf16x3, 14 % faster unsplit, 10 % slower for fp16x2 (the autotuner chooses):
+// after each step's barrier all wavefronts read LDS before their MFMAs start.
+constexpr int LK_WAVES = 8;
+
+template <int PER>
+struct LkSrc {  // per copied item: its plane's base (lane included), block offset, L or R
+  const u32x4* src[PER];
+  uint64_t off[PER];
+  bool is_l[PER];
+};
+
+template <int PER>
+__device__ __forceinline__ void lk_fetch(u32x4 (&pre)[PER], const LkSrc<PER>& q, uint64_t l_off, uint64_t r_off,
+                                         uint64_t st) {
+#pragma unroll
+  for (int j = 0; j < PER; ++j) pre[j] = q.src[j][(q.is_l[j] ? l_off : r_off) + q.off[j] + st];
+}
+
+template <int MODE>
+__global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
+    const uint4* __restrict__ Lhi, const uint4* __restrict__ Llo, const uint4* __restrict__ Rhi,
+    const uint4* __restrict__ Rlo, uint64_t l_bstride, uint64_t r_bstride, float* __restrict__ out,
+    uint64_t out_bstride, int qx, int S, int col_tiles, int row_tiles) {
+  constexpr bool L_SPLIT = MODE != MERGE_BF16;
+  constexpr bool R_SPLIT = MODE == MERGE_BF16X3 || MODE == MERGE_FP16X3;
+  constexpr int LP = L_SPLIT ? 2 : 1, RP = R_SPLIT ? 2 : 1;
+  constexpr int NF = 8 * LP + 8 * RP;             // fragments per step: L (block, plane), then R
+  constexpr int PER = NF * 64 / (LK_WAVES * 64);  // 16-byte items each thread copies per step
+  constexpr int BUF = NF * 64;                    // items per LDS buffer
+  constexpr int SLAB = 16 * EPI_LDS_ROW;          // floats of one wavefront's epilogue slab
+  __shared__ u32x4 ops_lds[2 * BUF];              // operand buffers of steps g and g + 1
+  __shared__ float slabs[LK_WAVES * SLAB];        // epilogue, apart: the next tile's first step
+                                                  // is already in an operand buffer
+  const int beta = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;  // 2 row blocks and 4 column blocks each
+  const float scale = is_f16(MODE) ? (1.0f / 268435456.0f) : 1.0f;  // 2^-28
+  const uint64_t ncols = (uint64_t)2 << qx;
+  float* ob = out + beta * out_bstride;
+  const uint64_t lstep = (uint64_t)S * 64;
+  const u32x4* lbh = reinterpret_cast<const u32x4*>(Lhi + beta * l_bstride);
+  const u32x4* lbl = reinterpret_cast<const u32x4*>(Llo + beta * l_bstride);
+  const u32x4* rbh = reinterpret_cast<const u32x4*>(Rhi + beta * r_bstride);
+  const u32x4* rbl = reinterpret_cast<const u32x4*>(Rlo + beta * r_bstride);
+
+  // Tiles of this workgroup.  Workgroup b runs on XCD b % 8.  Grouped order (a grid
+  // of 8 x 32 workgroups): XCD x owns the column band of tiles [x band, (x + 1) band)
+  // and its 32 workgroups take 4 x 8 tiles of it at a time, rounds sweeping the
+  // band's 8-tile column groups, then its 4-tile row groups, so that L2 serves each
+  // row tile's fragments to 8 workgroups and each column tile's to 4.  Otherwise,
+  // banded or plain order as in the tiled kernel.
+  const int ntiles = col_tiles * row_tiles;
+  const int per_xcd = (int)(gridDim.x >> 3);
+  const bool grouped = (gridDim.x & 7) == 0 && per_xcd == 32 && col_tiles % 64 == 0 && row_tiles % 4 == 0;
+  const bool banded = !grouped && (col_tiles & 7) == 0 && (gridDim.x & 7) == 0;
+  const int band = col_tiles >> 3;
+  const int w = (int)(blockIdx.x >> 3), xcd = (int)(blockIdx.x & 7);
+  int mine;
+  if (grouped) {
+    mine = ntiles / (int)gridDim.x;  // every round gives each workgroup one tile
+  } else {
+    const int tstep = banded ? per_xcd : (int)gridDim.x;
+    const int first = banded ? w : (int)blockIdx.x;
+    const int limit = banded ? ntiles >> 3 : ntiles;
+    mine = (limit - first + tstep - 1) / tstep;  // >= 1: the grid never exceeds the tiles
+  }
+  const int steps = mine * S;
+  const int cgroups = band / 8;  // grouped: 8-tile column groups per band
+  // t-th tile of this workgroup (selects, no branches: the loads must stay in one basic
+  // block with the MFMAs they overlap, or the compiler sinks them to their use)
+  auto tile_rc = [&](int t, int& tr, int& tc) {
+    const int tstep = banded ? per_xcd : (int)gridDim.x;
+    const int i = (banded ? w : (int)blockIdx.x) + t * tstep;
+    const int div = banded ? band : col_tiles;
+    const int gr = t / cgroups, gc = t % cgroups;
+    tr = grouped ? gr * 4 + (w >> 3) : i / div;
+    tc = grouped ? xcd * band + gc * 8 + (w & 7) : (banded ? xcd * band : 0) + i % div;
+  };
+
+  // this thread's share of a step's fragments: item g = j * 512 + tid is lane g % 64
+  // of fragment g / 64 (f < 8 LP: L block f / LP, plane f % LP; then R block
+  // (f - 8 LP) / RP, plane (f - 8 LP) % RP): fixed per thread, only tile and step move
+  LkSrc<PER> q;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int g = j * LK_WAVES * 64 + tid, f = g >> 6, l = g & 63;
+    q.is_l[j] = f < 8 * LP;
+    const int blk = q.is_l[j] ? f / LP : (f - 8 * LP) / RP;
+    const int pl = q.is_l[j] ? f % LP : (f - 8 * LP) % RP;
+    q.src[j] = (q.is_l[j] ? (pl ? lbl : lbh) : (pl ? rbl : rbh)) + l;
+    q.off[j] = (uint64_t)blk * lstep;
+  }
+  // step g of this workgroup's stream (past the last: the last, in bounds and unused)
+  auto fetch = [&](u32x4 (&v)[PER], int g) {
+    g = g < steps ? g : steps - 1;
+    int tr, tc;
+    tile_rc(g / S, tr, tc);
+    lk_fetch(v, q, (uint64_t)tr * 8 * lstep, (uint64_t)tc * 8 * lstep, (uint64_t)(g % S) * 64);
+  };
+  auto stash = [&](const u32x4 (&v)[PER], int g) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) ops_lds[(g & 1) * BUF + j * LK_WAVES * 64 + tid] = v[j];
+  };
+
+  f32x16 acc[2][4];
+  // one step: its fragments from LDS, its MFMAs in the tiled kernel's order
+  auto compute = [&](int g) {
+    const u32x4* b = ops_lds + (g & 1) * BUF + lane;
+    uint4 a_hi[2], a_lo[2], b_hi[4], b_lo[4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      a_hi[r] = __builtin_bit_cast(uint4, b[((wr * 2 + r) * LP) * 64]);
+      if (L_SPLIT) a_lo[r] = __builtin_bit_cast(uint4, b[((wr * 2 + r) * LP + 1) * 64]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      b_hi[c] = __builtin_bit_cast(uint4, b[(8 * LP + (wc * 4 + c) * RP) * 64]);
+      if (R_SPLIT) b_lo[c] = __builtin_bit_cast(uint4, b[(8 * LP + (wc * 4 + c) * RP + 1) * 64]);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (L_SPLIT) acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
+        if (R_SPLIT) acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
+        acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
+      }
+  };
+  // 16-row half slabs per wavefront through LDS, 512-byte row segments
+  auto epilogue = [&](int t) {
+    int tr, tc;
+    tile_rc(t, tr, tc);
+    float* my = slabs + wave * SLAB;
+    const int rb0 = tr * 8 + wr * 2, cb0 = tc * 8 + wc * 4;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int v = 8 * h; v < 8 * h + 8; ++v) {
+            const int row = (v & 3) + 4 * (lane >> 5) + 8 * ((v >> 2) & 1);
+            my[row * EPI_LDS_ROW + c * 32 + (lane & 31)] = acc[r][c][v];
+          }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t col0 = (uint64_t)cb0 * 32 + 4 * (lane & 31);
+#pragma unroll
+        for (int rr = 0; rr < 16; rr += 2) {
+          const int row = rr + (lane >> 5);
+          f32x4 v = *reinterpret_cast<const f32x4*>(my + row * EPI_LDS_ROW + 4 * (lane & 31));
+          v *= scale;
+          const uint64_t grow = (uint64_t)(rb0 + r) * 32 + 16 * h + row;
+          __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(ob + grow * ncols + col0));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  };
+  auto clear = [&]() {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.f;
+  };
+
+  // Two register sets in flight: at step g the set that held step g (already in LDS)
+  // takes step g + 2, and the set holding step g + 1 (loaded a step ago) goes to LDS
+  // after step g's MFMAs.  Unrolled by two so that the sets keep their registers.
+  u32x4 pa[PER], pb[PER];
+  fetch(pa, 0);
+  fetch(pb, 1);
+  stash(pa, 0);
+  __syncthreads();
+  clear();
+  auto half = [&](u32x4 (&cur)[PER], u32x4 (&nxt)[PER], int g) {
+    fetch(cur, g + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(g);
+    __builtin_amdgcn_sched_barrier(0);
+    stash(nxt, g + 1);  // after the last step: a buffer no step reads
+    __syncthreads();
+    if (g % S == S - 1) {  // the tile's last step: store it, start the next
+      epilogue(g / S);
+      clear();
+    }
+  };
+  for (int g = 0; g < steps; g += 2) {
+    half(pa, pb, g);
+    if (g + 1 < steps) half(pb, pa, g + 1);
+  }
+}
+
 // S in {1, 2, 4, 8} (K <= 64; K is a power of two) and row offsets of a 32-row block
 // within 32 bits (the buffer stores' scalar offset): 2^(qx + 1) floats per row, qx <= 23
 bool merge_rs_supported(int qx, int S) { return qx >= 7 && qx <= 23 && (S == 1 || S == 2 || S == 4 || S == 8); }
+
+// 256 x 256 tiles: at least one tile each way
+bool merge_lk_supported(int qx, int qy) { return qx >= 7 && qy >= 8; }
 
 int cu_count() {
   int dev = 0, c = 0;
@@ -523,7 +741,22 @@ int launch_mode(const MergeMfmaArgs& a, int variant, int grid_cap, hipStream_t s
     CCUT_HIP(hipGetLastError());
     return 0;
   }
-  if (variant == 4) variant = 1;  // shapes the R-stationary kernel does not take
+  if (variant == 5 && merge_lk_supported(a.qx, a.qy)) {
+    const int col_tiles = 1 << (a.qx + 1 - 8);
+    const int row_tiles = 1 << (a.qy - 8);
+    const int ntiles = col_tiles * row_tiles;
+    // one workgroup per CU over all batch entries, a multiple of the 8 XCDs
+    int per = std::max(1, cu_count() / std::max(1, a.batch));
+    if (per >= 8) per &= ~7;
+    dim3 grid((unsigned)std::min(ntiles, per), a.batch);
+    const uint64_t r_bstride = a.r_batch > 1 ? a.r_plane_stride : 0;
+    ProfScope prof(PROF_MERGE_GEMM, s);
+    hipLaunchKernelGGL((k_merge_gemm_lk<MODE>), grid, dim3(LK_WAVES * 64), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo,
+                       a.l_plane_stride, r_bstride, a.out, a.out_bstride * 2, a.qx, S, col_tiles, row_tiles);
+    CCUT_HIP(hipGetLastError());
+    return 0;
+  }
+  if (variant >= 4) variant = 1;  // shapes the R-stationary or LDS-staged kernels do not take
   const int col_tiles = 1 << (a.qx + 1 - 8);                      // 256 real columns per tile
   const int row_tiles = 1 << (a.qy - ((variant & 2) ? 6 : 7));    // 64 or 128 rows per tile
   const int ntiles = col_tiles * row_tiles;

@@ -466,7 +466,7 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
   for (int mode : {CCUT_PREC_FP16X3, CCUT_PREC_BF16X3})
     for (int epi = 0; epi < MERGE_VARIANTS; ++epi)
       for (int gc : {0, 512, 1024, 2048})
-        if (epi != 4 || gc == 0) cands.push_back({mode, epi, gc});  // variant 4 sizes its own grid
+        if (epi < 4 || gc == 0) cands.push_back({mode, epi, gc});  // variants 4 and 5 size their own grid
   std::vector<float> tbest(cands.size(), 1e30f);
   const int mreps = std::max(reps, 7);
   for (int sweep = 0; sweep < 2 && !rc; ++sweep) {

@@ -461,8 +461,8 @@ def run_gemm(args):
         alg = 8 * (1 << q) + 8 * (2 ** c) * 2 * (1 << (q // 2))
         ccut.profile_enable(True)
         for prec in ("bf16x3", "fp16x3", "fp16x2", "bf16"):
-            for v in range(4):
-                for gc in (0, 1024):
+            for v in range(6):
+                for gc in ((0, 1024) if v < 4 else (0,)):   # variants 4 and 5: one workgroup per CU
                     ccut.plan_set_merge(plan, v, gc)
                     ccut.merge_full_state(plan, arena, psi, prec, stream=s)
                     torch.cuda.synchronize()
