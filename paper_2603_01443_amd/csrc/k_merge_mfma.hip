@@ -483,8 +483,9 @@ typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 // of 8 wavefronts (4 x 2) owns a 256-row x 256-column tile, each wavefront
 // 64 x 128 (2 x 4 blocks of 32 x 32): per MFMA step the tile's 8 L and 8 R
 // fragments (both planes: 32 KiB in the three-product modes) are loaded from L2
-// once, two steps ahead (two register sets), and copied into one of two LDS
-// buffers, from which every wavefront reads its own.  Per step and output block
+// once, three steps ahead (two register sets), and copied into one of three LDS
+// buffers; every wavefront reads its own fragments of the next step right after
+// issuing the MFMAs of the current one, so the reads overlap the MFMA pipe.  Per step and output block
 // the products run in the tiled kernel's order (lo.hi, hi.lo, hi.hi), so the
 // results are the same bit for bit.  One workgroup per CU, persistent over the
 // tiles; the stream of steps runs on across tiles, so a tile's stores (through LDS,
@@ -519,10 +520,10 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
   constexpr int NF = 8 * LP + 8 * RP;             // fragments per step: L (block, plane), then R
   constexpr int PER = NF * 64 / (LK_WAVES * 64);  // 16-byte items each thread copies per step
   constexpr int BUF = NF * 64;                    // items per LDS buffer
-  constexpr int SLAB = 16 * EPI_LDS_ROW;          // floats of one wavefront's epilogue slab
-  __shared__ u32x4 ops_lds[2 * BUF];              // operand buffers of steps g and g + 1
-  __shared__ float slabs[LK_WAVES * SLAB];        // epilogue, apart: the next tile's first step
-                                                  // is already in an operand buffer
+  constexpr int SLAB = 8 * EPI_LDS_ROW;           // floats of one wavefront's epilogue slab
+  __shared__ u32x4 ops_lds[3 * BUF];              // operand buffers of steps g, g + 1, g + 2
+  __shared__ float slabs[LK_WAVES * SLAB];        // epilogue, apart: the next tile's first steps
+                                                  // are already in operand buffers
   const int beta = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -591,35 +592,41 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
     lk_fetch(v, q, (uint64_t)tr * 8 * lstep, (uint64_t)tc * 8 * lstep, (uint64_t)(g % S) * 64);
   };
   auto stash = [&](const u32x4 (&v)[PER], int g) {
+    u32x4* d = ops_lds + (g % 3) * BUF + tid;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) ops_lds[(g & 1) * BUF + j * LK_WAVES * 64 + tid] = v[j];
+    for (int j = 0; j < PER; ++j) d[j * LK_WAVES * 64] = v[j];
   };
 
   f32x16 acc[2][4];
-  // one step: its fragments from LDS, its MFMAs in the tiled kernel's order
-  auto compute = [&](int g) {
-    const u32x4* b = ops_lds + (g & 1) * BUF + lane;
+  struct Frags {
     uint4 a_hi[2], a_lo[2], b_hi[4], b_lo[4];
+  };
+  // a step's fragments of this wavefront, from LDS
+  auto read = [&](Frags& f, int g) {
+    const u32x4* b = ops_lds + (g % 3) * BUF + lane;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      a_hi[r] = __builtin_bit_cast(uint4, b[((wr * 2 + r) * LP) * 64]);
-      if (L_SPLIT) a_lo[r] = __builtin_bit_cast(uint4, b[((wr * 2 + r) * LP + 1) * 64]);
+      f.a_hi[r] = __builtin_bit_cast(uint4, b[((wr * 2 + r) * LP) * 64]);
+      if (L_SPLIT) f.a_lo[r] = __builtin_bit_cast(uint4, b[((wr * 2 + r) * LP + 1) * 64]);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      b_hi[c] = __builtin_bit_cast(uint4, b[(8 * LP + (wc * 4 + c) * RP) * 64]);
-      if (R_SPLIT) b_lo[c] = __builtin_bit_cast(uint4, b[(8 * LP + (wc * 4 + c) * RP + 1) * 64]);
+      f.b_hi[c] = __builtin_bit_cast(uint4, b[(8 * LP + (wc * 4 + c) * RP) * 64]);
+      if (R_SPLIT) f.b_lo[c] = __builtin_bit_cast(uint4, b[(8 * LP + (wc * 4 + c) * RP + 1) * 64]);
     }
+  };
+  // a step's MFMAs in the tiled kernel's order
+  auto compute = [&](const Frags& f) {
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        if (L_SPLIT) acc[r][c] = mfma<MODE>(a_lo[r], b_hi[c], acc[r][c]);
-        if (R_SPLIT) acc[r][c] = mfma<MODE>(a_hi[r], b_lo[c], acc[r][c]);
-        acc[r][c] = mfma<MODE>(a_hi[r], b_hi[c], acc[r][c]);
+        if (L_SPLIT) acc[r][c] = mfma<MODE>(f.a_lo[r], f.b_hi[c], acc[r][c]);
+        if (R_SPLIT) acc[r][c] = mfma<MODE>(f.a_hi[r], f.b_lo[c], acc[r][c]);
+        acc[r][c] = mfma<MODE>(f.a_hi[r], f.b_hi[c], acc[r][c]);
       }
   };
-  // 16-row half slabs per wavefront through LDS, 512-byte row segments
+  // 8-row slabs per wavefront through LDS, 512-byte row segments
   auto epilogue = [&](int t) {
     int tr, tc;
     tile_rc(t, tr, tc);
@@ -628,23 +635,25 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < 4; ++h) {  // accumulator registers 4 h .. 4 h + 3: rows 8 (h / 2) + 4 (lane / 32) + (v & 3) ... of the block
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-          for (int v = 8 * h; v < 8 * h + 8; ++v) {
-            const int row = (v & 3) + 4 * (lane >> 5) + 8 * ((v >> 2) & 1);
+          for (int v = 4 * h; v < 4 * h + 4; ++v) {
+            const int row = (v & 3) + 4 * (lane >> 5);  // 0..7 within the slab
             my[row * EPI_LDS_ROW + c * 32 + (lane & 31)] = acc[r][c][v];
           }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         const uint64_t col0 = (uint64_t)cb0 * 32 + 4 * (lane & 31);
 #pragma unroll
-        for (int rr = 0; rr < 16; rr += 2) {
+        for (int rr = 0; rr < 8; rr += 2) {
           const int row = rr + (lane >> 5);
           f32x4 v = *reinterpret_cast<const f32x4*>(my + row * EPI_LDS_ROW + 4 * (lane & 31));
           v *= scale;
-          const uint64_t grow = (uint64_t)(rb0 + r) * 32 + 16 * h + row;
+          // slab row j holds block row (j & 3) + 8 h' + 4 (j >> 2) with h' = h (register group)
+          const int brow = (row & 3) + 8 * h + 4 * (row >> 2);
+          const uint64_t grow = (uint64_t)(rb0 + r) * 32 + brow;
           __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(ob + grow * ncols + col0));
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -661,21 +670,29 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
         for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.f;
   };
 
-  // Two register sets in flight: at step g the set that held step g (already in LDS)
-  // takes step g + 2, and the set holding step g + 1 (loaded a step ago) goes to LDS
-  // after step g's MFMAs.  Unrolled by two so that the sets keep their registers.
+  // Entering step g: its fragments are in registers, LDS holds steps g + 1 and (being
+  // copied) g + 2.  Step g loads step g + 3 from L2 into the register set that held
+  // step g + 1's items, issues its MFMAs, copies step g + 2 into LDS, reads step g + 1's
+  // fragments from LDS while the MFMA pipe works through step g, and ends with the
+  // barrier.  Unrolled by two so that the load register sets keep their registers.
   u32x4 pa[PER], pb[PER];
   fetch(pa, 0);
   fetch(pb, 1);
   stash(pa, 0);
+  stash(pb, 1);
+  fetch(pa, 2);
   __syncthreads();
+  Frags f;
+  read(f, 0);
   clear();
   auto half = [&](u32x4 (&cur)[PER], u32x4 (&nxt)[PER], int g) {
-    fetch(cur, g + 2);
+    // cur holds step g + 2 (loaded a step ago); nxt takes step g + 3
+    fetch(nxt, g + 3);
     __builtin_amdgcn_sched_barrier(0);
-    compute(g);
+    compute(f);
     __builtin_amdgcn_sched_barrier(0);
-    stash(nxt, g + 1);  // after the last step: a buffer no step reads
+    stash(cur, g + 2);  // past the last step: buffers no step reads
+    read(f, g + 1);
     __syncthreads();
     if (g % S == S - 1) {  // the tile's last step: store it, start the next
       epilogue(g / S);
