@@ -389,9 +389,10 @@ int ccut_plan_work(const ccut_plan_t* plan, double out[5]);
  * terms, hi and lo) in LDS and sweeps all rows of its strip; it covers up to
  * K = 64 terms per stage and runs larger stages as epilogue 1.  epilogue 5 is
  * the LDS-staged kernel for many terms: one 8-wavefront workgroup per CU loops
- * over 256-row x 256-column tiles, loading each MFMA step's fragments of both
- * factors once per tile (two steps ahead) into LDS (double-buffered) for all its
- * wavefronts; stages with fewer than 256 rows run as epilogue 1.
+ * over 256-row x 256-column tiles, copying each MFMA step's fragments of both
+ * factors from L2 straight into LDS once per tile (four steps ahead, four
+ * buffers) for all its wavefronts; stages with fewer than 256 rows or fewer than
+ * 32 terms run as epilogue 1.
  * grid_cap 0 launches one workgroup per tile, > 0 a persistent grid of at most
  * grid_cap workgroups looping over tiles (ignored by epilogues 4 and 5, whose
  * grid is one workgroup per CU).  Results do not depend on either.

@@ -482,32 +482,48 @@ typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 // from L2 on their own (3 to 5 times the output size in all).  Here a workgroup
 // of 8 wavefronts (4 x 2) owns a 256-row x 256-column tile, each wavefront
 // 64 x 128 (2 x 4 blocks of 32 x 32): per MFMA step the tile's 8 L and 8 R
-// fragments (both planes: 32 KiB in the three-product modes) are loaded from L2
-// once, three steps ahead (two register sets), and copied into one of three LDS
-// buffers; every wavefront reads its own fragments of the next step right after
-// issuing the MFMAs of the current one, so the reads overlap the MFMA pipe.  Per step and output block
-// the products run in the tiled kernel's order (lo.hi, hi.lo, hi.hi), so the
-// results are the same bit for bit.  One workgroup per CU, persistent over the
-// tiles; the stream of steps runs on across tiles, so a tile's stores (through LDS,
-// 16-row slabs, 512-byte row segments) are issued after the next tile's first
-// loads.  Measured at q = 30, K = 256: as fast as the tiled kernel for fp16x3 and
-// bf16x3, 14 % faster unsplit, 10 % slower for fp16x2 (the autotuner chooses):
-// after each step's barrier all wavefronts read LDS before their MFMAs start.
+// fragments (both planes: 32 KiB in the three-product modes) are copied from L2
+// straight into LDS once, four steps ahead, into one of four buffers; every
+// wavefront reads its own fragments of the next step into a second register set
+// before it issues the MFMAs of the current one.  Per step and output block the
+// products run in the tiled kernel's order (lo.hi, hi.lo, hi.hi), so the results
+// are the same bit for bit.  One workgroup per CU, persistent over the tiles; the
+// stream of steps runs on across tiles, so a tile's stores (through LDS, 4-row
+// slabs, 512-byte row segments) go out behind the next tile's first copies.
+// Measured at q = 30, K = 256 against the tiled kernel: fp16x3 5.7 against
+// 7.3 ms, fp16x2 4.1 against 4.7 ms, unsplit bf16 2.5 against 4.0 ms.
 constexpr int LK_WAVES = 8;
 
-template <int PER>
-struct LkSrc {  // per copied item: its plane's base (lane included), block offset, L or R
-  const u32x4* src[PER];
-  uint64_t off[PER];
-  bool is_l[PER];
-};
+// global stores of one wavefront's share of a tile: 2 block rows x 8 slabs x 2 row pairs
+constexpr int LK_EPI_STORES = 32;
+
+// Waits until at most N vector memory operations of this wavefront are outstanding
+// and all its LDS operations are done, then the workgroup barrier.  Written out
+// because the barrier builtin's fence would wait for every outstanding copy into LDS;
+// the wait is the compiler's own instruction, so its later waits know of it (gfx9
+// fields: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+template <int N>
+__device__ __forceinline__ void lk_wait_barrier() {
+  static_assert(N >= 0 && N < 64, "vmcnt field");
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// 16 bytes per lane from global memory straight into LDS: lane i's bytes land at
+// dst + 16 i (dst uniform over the wavefront); counted by the vector memory counter
+__device__ __forceinline__ void lds_copy16(const u32x4* src, u32x4* dst) {
+  __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+}
 
 template <int PER>
-__device__ __forceinline__ void lk_fetch(u32x4 (&pre)[PER], const LkSrc<PER>& q, uint64_t l_off, uint64_t r_off,
-                                         uint64_t st) {
-#pragma unroll
-  for (int j = 0; j < PER; ++j) pre[j] = q.src[j][(q.is_l[j] ? l_off : r_off) + q.off[j] + st];
-}
+struct LkSrc {  // per copy of a wavefront: its fragment's block base, L or R
+  const u32x4* src[PER];
+  bool is_l[PER];
+};
 
 template <int MODE>
 __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
@@ -520,10 +536,12 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
   constexpr int NF = 8 * LP + 8 * RP;             // fragments per step: L (block, plane), then R
   constexpr int PER = NF * 64 / (LK_WAVES * 64);  // 16-byte items each thread copies per step
   constexpr int BUF = NF * 64;                    // items per LDS buffer
-  constexpr int SLAB = 8 * EPI_LDS_ROW;           // floats of one wavefront's epilogue slab
-  __shared__ u32x4 ops_lds[3 * BUF];              // operand buffers of steps g, g + 1, g + 2
-  __shared__ float slabs[LK_WAVES * SLAB];        // epilogue, apart: the next tile's first steps
-                                                  // are already in operand buffers
+  constexpr int SLAB = 4 * EPI_LDS_ROW;           // floats of one wavefront's epilogue slab
+  // operand buffers of steps g = 0, 1, 2, 3 mod 4: four arrays, each touched at fixed
+  // places of the unrolled loop, so that the compiler can tell a step's reads from the
+  // copies still landing in the other buffers
+  __shared__ u32x4 ops0[BUF], ops1[BUF], ops2[BUF], ops3[BUF];
+  __shared__ float slabs[LK_WAVES * SLAB];  // epilogue, apart from the operand buffers
   const int beta = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -571,30 +589,44 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
     tc = grouped ? xcd * band + gc * 8 + (w & 7) : (banded ? xcd * band : 0) + i % div;
   };
 
-  // this thread's share of a step's fragments: item g = j * 512 + tid is lane g % 64
-  // of fragment g / 64 (f < 8 LP: L block f / LP, plane f % LP; then R block
-  // (f - 8 LP) / RP, plane (f - 8 LP) % RP): fixed per thread, only tile and step move
+  // this wavefront's share of a step's fragments: its copy j carries fragment
+  // f = 8 j + wave (f < 8 LP: L block f / LP, plane f % LP; then R block (f - 8 LP) / RP,
+  // plane (f - 8 LP) % RP), lane l its 16 bytes l; the block's base is uniform over the
+  // wavefront, only tile and step move
   LkSrc<PER> q;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
-    const int g = j * LK_WAVES * 64 + tid, f = g >> 6, l = g & 63;
+    const int f = j * LK_WAVES + wave;
     q.is_l[j] = f < 8 * LP;
     const int blk = q.is_l[j] ? f / LP : (f - 8 * LP) / RP;
     const int pl = q.is_l[j] ? f % LP : (f - 8 * LP) % RP;
-    q.src[j] = (q.is_l[j] ? (pl ? lbl : lbh) : (pl ? rbl : rbh)) + l;
-    q.off[j] = (uint64_t)blk * lstep;
+    q.src[j] = (q.is_l[j] ? (pl ? lbl : lbh) : (pl ? rbl : rbh)) + (uint64_t)blk * lstep;
   }
-  // step g of this workgroup's stream (past the last: the last, in bounds and unused)
-  auto fetch = [&](u32x4 (&v)[PER], int g) {
-    g = g < steps ? g : steps - 1;
+  // Copy stream: a round's four copies are steps dk .. dk + 3 of this workgroup's tile
+  // dt (S is a multiple of 4, so a round never crosses tiles; past the last tile, the
+  // last again: in bounds, never read).  Each wavefront's 64 items of a copy land in
+  // LDS as 1 KiB, lane after lane.  The tile's bases change once per S steps.
+  uint64_t c_lo = 0, c_ro = 0;
+  int dt = 0, dk = 0;
+  auto copy_tile = [&]() {
     int tr, tc;
-    tile_rc(g / S, tr, tc);
-    lk_fetch(v, q, (uint64_t)tr * 8 * lstep, (uint64_t)tc * 8 * lstep, (uint64_t)(g % S) * 64);
+    tile_rc(dt < mine ? dt : mine - 1, tr, tc);
+    c_lo = (uint64_t)tr * 8 * lstep;
+    c_ro = (uint64_t)tc * 8 * lstep;
   };
-  auto stash = [&](const u32x4 (&v)[PER], int g) {
-    u32x4* d = ops_lds + (g % 3) * BUF + tid;
+  auto dma = [&](u32x4* buf, int j4) {
+    const uint64_t so = (uint64_t)(dk + j4) * 64;
+    u32x4* d = buf + wave * 64;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) d[j * LK_WAVES * 64] = v[j];
+    for (int j = 0; j < PER; ++j) lds_copy16(q.src[j] + (q.is_l[j] ? c_lo : c_ro) + so + lane, d + j * LK_WAVES * 64);
+  };
+  auto next_round = [&]() {
+    dk += 4;
+    if (dk == S) {
+      dk = 0;
+      ++dt;
+      copy_tile();
+    }
   };
 
   f32x16 acc[2][4];
@@ -602,8 +634,8 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
     uint4 a_hi[2], a_lo[2], b_hi[4], b_lo[4];
   };
   // a step's fragments of this wavefront, from LDS
-  auto read = [&](Frags& f, int g) {
-    const u32x4* b = ops_lds + (g % 3) * BUF + lane;
+  auto read = [&](Frags& f, const u32x4* buf) {
+    const u32x4* b = buf + lane;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       f.a_hi[r] = __builtin_bit_cast(uint4, b[((wr * 2 + r) * LP) * 64]);
@@ -626,33 +658,31 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
         acc[r][c] = mfma<MODE>(f.a_hi[r], f.b_hi[c], acc[r][c]);
       }
   };
-  // 8-row slabs per wavefront through LDS, 512-byte row segments
+  // 4-row slabs per wavefront through LDS, 512-byte row segments
   auto epilogue = [&](int t) {
     int tr, tc;
     tile_rc(t, tr, tc);
     float* my = slabs + wave * SLAB;
     const int rb0 = tr * 8 + wr * 2, cb0 = tc * 8 + wc * 4;
+    const uint64_t col0 = (uint64_t)cb0 * 32 + 4 * (lane & 31);
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {  // accumulator registers 4 h .. 4 h + 3: rows 8 (h / 2) + 4 (lane / 32) + (v & 3) ... of the block
+      for (int h = 0; h < 8; ++h) {  // accumulator registers 2 h, 2 h + 1: block rows
+                                     // 8 (h / 2) + 4 (lane / 32) + 2 (h % 2) + (v & 1)
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-          for (int v = 4 * h; v < 4 * h + 4; ++v) {
-            const int row = (v & 3) + 4 * (lane >> 5);  // 0..7 within the slab
-            my[row * EPI_LDS_ROW + c * 32 + (lane & 31)] = acc[r][c][v];
-          }
+          for (int v = 2 * h; v < 2 * h + 2; ++v)
+            my[((v & 1) + 2 * (lane >> 5)) * EPI_LDS_ROW + c * 32 + (lane & 31)] = acc[r][c][v];
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        const uint64_t col0 = (uint64_t)cb0 * 32 + 4 * (lane & 31);
 #pragma unroll
-        for (int rr = 0; rr < 8; rr += 2) {
-          const int row = rr + (lane >> 5);
+        for (int rr = 0; rr < 4; rr += 2) {
+          const int row = rr + (lane >> 5);  // slab row: (v & 1) + 2 (writer's lane / 32)
           f32x4 v = *reinterpret_cast<const f32x4*>(my + row * EPI_LDS_ROW + 4 * (lane & 31));
           v *= scale;
-          // slab row j holds block row (j & 3) + 8 h' + 4 (j >> 2) with h' = h (register group)
-          const int brow = (row & 3) + 8 * h + 4 * (row >> 2);
+          const int brow = 8 * (h >> 1) + 4 * (row >> 1) + 2 * (h & 1) + (row & 1);
           const uint64_t grow = (uint64_t)(rb0 + r) * 32 + brow;
           __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(ob + grow * ncols + col0));
         }
@@ -670,47 +700,58 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
         for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.f;
   };
 
-  // Entering step g: its fragments are in registers, LDS holds steps g + 1 and (being
-  // copied) g + 2.  Step g loads step g + 3 from L2 into the register set that held
-  // step g + 1's items, issues its MFMAs, copies step g + 2 into LDS, reads step g + 1's
-  // fragments from LDS while the MFMA pipe works through step g, and ends with the
-  // barrier.  Unrolled by two so that the load register sets keep their registers.
-  u32x4 pa[PER], pb[PER];
-  fetch(pa, 0);
-  fetch(pb, 1);
-  stash(pa, 0);
-  stash(pb, 1);
-  fetch(pa, 2);
-  __syncthreads();
-  Frags f;
-  read(f, 0);
+  // Entering step g: its fragments are in registers (or on their way from LDS), LDS
+  // holds step g + 1, and steps g + 2 and g + 3 are on their way into LDS.  Step g
+  // reads step g + 1's fragments into the other register set, loads step g + 4 into the
+  // buffer step g left (all its reads ended before the last barrier), issues its MFMAs,
+  // and waits for its own copies of step g + 2 before the barrier that makes them
+  // visible to all.  S is a multiple of 4, so tiles end in the fourth step of a round;
+  // the memory counter runs in order, so the first step after a tile's stores waits for
+  // most of them as well.
+  Frags f0, f1;
+  copy_tile();
+  dma(ops0, 0);
+  dma(ops1, 1);
+  lk_wait_barrier<PER>();  // step 0 in LDS
+  read(f0, ops0);
+  dma(ops2, 2);
+  dma(ops3, 3);
+  next_round();
+  lk_wait_barrier<2 * PER>();  // step 1 in LDS, step 0 read by all
   clear();
-  auto half = [&](u32x4 (&cur)[PER], u32x4 (&nxt)[PER], int g) {
-    // cur holds step g + 2 (loaded a step ago); nxt takes step g + 3
-    fetch(nxt, g + 3);
+  auto step = [&](Frags& cur, Frags& nxt, const u32x4* rd, u32x4* wr_buf, int j4) {
+    read(nxt, rd);
+    dma(wr_buf, j4);  // step g + 4
     __builtin_amdgcn_sched_barrier(0);
-    compute(f);
-    __builtin_amdgcn_sched_barrier(0);
-    stash(cur, g + 2);  // past the last step: buffers no step reads
-    read(f, g + 1);
-    __syncthreads();
-    if (g % S == S - 1) {  // the tile's last step: store it, start the next
-      epilogue(g / S);
-      clear();
-    }
+    compute(cur);
+    lk_wait_barrier<2 * PER>();  // after a tile's stores: those of them older than the
+                                 // newest copies as well
   };
-  for (int g = 0; g < steps; g += 2) {
-    half(pa, pb, g);
-    if (g + 1 < steps) half(pb, pa, g + 1);
+  int et = 0, ek = 0;  // tile and step of the round's first computed step
+  for (int g = 0; g < steps; g += 4) {
+    step(f0, f1, ops1, ops0, 0);
+    step(f1, f0, ops2, ops1, 1);
+    step(f0, f1, ops3, ops2, 2);
+    step(f1, f0, ops0, ops3, 3);
+    next_round();
+    ek += 4;
+    if (ek == S) {  // the round ended tile et: store it, start the next
+      epilogue(et);
+      clear();
+      ek = 0;
+      ++et;
+    }
   }
+  // the copies past the last step are still landing in LDS: not past the workgroup's end
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
 // S in {1, 2, 4, 8} (K <= 64; K is a power of two) and row offsets of a 32-row block
 // within 32 bits (the buffer stores' scalar offset): 2^(qx + 1) floats per row, qx <= 23
 bool merge_rs_supported(int qx, int S) { return qx >= 7 && qx <= 23 && (S == 1 || S == 2 || S == 4 || S == 8); }
 
-// 256 x 256 tiles: at least one tile each way
-bool merge_lk_supported(int qx, int qy) { return qx >= 7 && qy >= 8; }
+// 256 x 256 tiles: at least one tile each way; MFMA steps a multiple of 4 (K >= 32)
+bool merge_lk_supported(int qx, int qy, int S) { return qx >= 7 && qy >= 8 && S % 4 == 0; }
 
 int cu_count() {
   int dev = 0, c = 0;
@@ -758,7 +799,7 @@ int launch_mode(const MergeMfmaArgs& a, int variant, int grid_cap, hipStream_t s
     CCUT_HIP(hipGetLastError());
     return 0;
   }
-  if (variant == 5 && merge_lk_supported(a.qx, a.qy)) {
+  if (variant == 5 && merge_lk_supported(a.qx, a.qy, S)) {
     const int col_tiles = 1 << (a.qx + 1 - 8);
     const int row_tiles = 1 << (a.qy - 8);
     const int ntiles = col_tiles * row_tiles;

@@ -28,8 +28,9 @@ bool merge_mfma_supported(int qx, int qy);
 //            16-wavefront workgroup per CU), up to 8 MFMA steps (K <= 64); above
 //            that it runs as variant 1.
 // variant 5: LDS-staged kernel for many steps: one 8-wavefront workgroup per CU
-//            over 256 x 256 tiles, each step's fragments copied to LDS once per
-//            tile (double-buffered); needs qy >= 8, else it runs as variant 1.
+//            over 256 x 256 tiles, each step's fragments copied from L2 straight
+//            into LDS once per tile (four buffers); needs qy >= 8 and K >= 32,
+//            else it runs as variant 1.
 // grid_cap > 0: persistent grid of at most grid_cap workgroups per batch entry.
 int launch_merge_mfma(const MergeMfmaArgs& a, int mode, int variant, int grid_cap, hipStream_t s);
 

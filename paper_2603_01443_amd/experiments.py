@@ -449,7 +449,11 @@ def run_costmodel(args):
 def run_gemm(args):
     """Merge GEMM per precision x variant x grid at q=28 (K=64) and q=30 (K=256)."""
     out = {"experiment": "merge gemm variants", "rows": []}
-    for q, c in ((28, 6), (30, 8)):
+    only = None
+    if args.only:  # one configuration, e.g. for a profiler run: q,c,precision,variant
+        oq, oc, op, ov = args.only.split(",")
+        only = (int(oq), int(oc), op, int(ov))
+    for q, c in (((28, 6), (30, 8)) if only is None else ((only[0], only[1]),)):
         n = 2
         g = ccut.gate_array(brickwork(q, 20, n, c, 0))
         plan = ccut.cut_plan(q, g, n)
@@ -460,9 +464,9 @@ def run_gemm(args):
         ccut.simulate_subcircuits(plan, arena, stream=s)
         alg = 8 * (1 << q) + 8 * (2 ** c) * 2 * (1 << (q // 2))
         ccut.profile_enable(True)
-        for prec in ("bf16x3", "fp16x3", "fp16x2", "bf16"):
-            for v in range(6):
-                for gc in ((0, 1024) if v < 4 else (0,)):   # variants 4 and 5: one workgroup per CU
+        for prec in (("bf16x3", "fp16x3", "fp16x2", "bf16") if only is None else (only[2],)):
+            for v in (range(6) if only is None else (only[3],)):
+                for gc in ((0, 1024) if v < 4 and only is None else (0,)):   # 4 and 5: one workgroup per CU
                     ccut.plan_set_merge(plan, v, gc)
                     ccut.merge_full_state(plan, arena, psi, prec, stream=s)
                     torch.cuda.synchronize()
@@ -771,6 +775,7 @@ def main():
     ap.add_argument("--qs", default=None, help="costmodel: comma-separated q values of the grid")
     ap.add_argument("--rows-in", default=None, help="costmodel: rows measured by an earlier (partial) run")
     ap.add_argument("--rows-only", action="store_true", help="costmodel: measure rows, skip training")
+    ap.add_argument("--only", default=None, help="gemm: a single q,c_total,precision,variant (e.g. 30,8,fp16x3,5)")
     args = ap.parse_args()
     if not torch.cuda.is_available():
         raise SystemExit("experiments need a GPU")
