@@ -490,8 +490,10 @@ typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 // are the same bit for bit.  One workgroup per CU, persistent over the tiles; the
 // stream of steps runs on across tiles, so a tile's stores (through LDS, 4-row
 // slabs, 512-byte row segments) go out behind the next tile's first copies.
-// Measured at q = 30, K = 256 against the tiled kernel: fp16x3 5.7 against
-// 7.3 ms, fp16x2 4.1 against 4.7 ms, unsplit bf16 2.5 against 4.0 ms.
+// Measured at q = 30, K = 256 against the tiled kernel: fp16x3 5.6 against
+// 7.4 ms, fp16x2 4.0 against 4.8 ms, unsplit bf16 2.4 against 3.9 ms; the clock
+// drops to about 1.5 GHz under this load (8.7 M shader cycles for fp16x3, 72 % of
+// them with the MFMA pipe busy).
 constexpr int LK_WAVES = 8;
 
 // global stores of one wavefront's share of a tile: 2 block rows x 8 slabs x 2 row pairs
@@ -719,11 +721,25 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
   next_round();
   lk_wait_barrier<2 * PER>();  // step 1 in LDS, step 0 read by all
   clear();
+  constexpr int NRD = 2 * LP + 4 * RP;  // LDS reads of a step's fragments
+  constexpr int NMF = 8 * (LP + RP - 1);  // MFMAs of a step
   auto step = [&](Frags& cur, Frags& nxt, const u32x4* rd, u32x4* wr_buf, int j4) {
     read(nxt, rd);
     dma(wr_buf, j4);  // step g + 4
-    __builtin_amdgcn_sched_barrier(0);
     compute(cur);
+    // issue order: the first MFMAs right after the barrier, the reads and copies in
+    // between the MFMAs, so that the MFMA pipe does not wait for their issue
+#pragma unroll
+    for (int i = 0; i < NRD / 2; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);  // LDS reads
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // copy into LDS
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, NMF - NRD / 2 - PER, 0);
     lk_wait_barrier<2 * PER>();  // after a tile's stores: those of them older than the
                                  // newest copies as well
   };
