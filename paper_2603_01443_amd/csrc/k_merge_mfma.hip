@@ -31,6 +31,8 @@
 #include "ccut_internal.h"
 #include "merge_mfma.h"
 
+#include <type_traits>
+
 namespace ccut {
 
 namespace {
@@ -490,10 +492,11 @@ typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 // are the same bit for bit.  One workgroup per CU, persistent over the tiles; the
 // stream of steps runs on across tiles, so a tile's stores (through LDS, 4-row
 // slabs, 512-byte row segments) go out behind the next tile's first copies.
-// Measured at q = 30, K = 256 against the tiled kernel: fp16x3 5.6 against
-// 7.4 ms, fp16x2 4.0 against 4.8 ms, unsplit bf16 2.4 against 3.9 ms; the clock
-// drops to about 1.5 GHz under this load (8.7 M shader cycles for fp16x3, 72 % of
-// them with the MFMA pipe busy).
+// Measured at q = 30, K = 256 against the tiled kernel: fp16x3 5.0 to 5.9 ms
+// against 7.4 ms, fp16x2 3.7 to 4.0 against 4.8 ms, unsplit bf16 2.4 against
+// 3.9 ms.  The shader clock drops to 1.35 to 1.6 GHz under this load; in cycles
+// the fp16x3 kernel takes 7.38 M, of which its MFMAs need 6.29 M and the tile
+// stores (256 KiB per CU and tile through the vector memory path) most of the rest.
 constexpr int LK_WAVES = 8;
 
 // global stores of one wavefront's share of a tile: 2 block rows x 8 slabs x 2 row pairs
@@ -723,7 +726,9 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
   clear();
   constexpr int NRD = 2 * LP + 4 * RP;  // LDS reads of a step's fragments
   constexpr int NMF = 8 * (LP + RP - 1);  // MFMAs of a step
-  auto step = [&](Frags& cur, Frags& nxt, const u32x4* rd, u32x4* wr_buf, int j4) {
+  using Plain = std::integral_constant<bool, false>;
+  using AfterStores = std::integral_constant<bool, true>;
+  auto step = [&](Frags& cur, Frags& nxt, const u32x4* rd, u32x4* wr_buf, int j4, auto after_stores) {
     read(nxt, rd);
     dma(wr_buf, j4);  // step g + 4
     compute(cur);
@@ -740,23 +745,31 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
       __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // copy into LDS
     }
     __builtin_amdgcn_sched_group_barrier(0x008, NMF - NRD / 2 - PER, 0);
-    lk_wait_barrier<2 * PER>();  // after a tile's stores: those of them older than the
-                                 // newest copies as well
+    if constexpr (decltype(after_stores)::value)
+      lk_wait_barrier<2 * PER + LK_EPI_STORES>();  // the tile's stores may stay in flight
+    else
+      lk_wait_barrier<2 * PER>();
   };
-  int et = 0, ek = 0;  // tile and step of the round's first computed step
-  for (int g = 0; g < steps; g += 4) {
-    step(f0, f1, ops1, ops0, 0);
-    step(f1, f0, ops2, ops1, 1);
-    step(f0, f1, ops3, ops2, 2);
-    step(f1, f0, ops0, ops3, 3);
+  // a round of four steps; in the first round after a tile's stores the first two steps
+  // wait only for the copies older than the stores (the third waits for them as well)
+  auto round = [&](auto after_stores) {
+    step(f0, f1, ops1, ops0, 0, after_stores);
+    step(f1, f0, ops2, ops1, 1, after_stores);
+    step(f0, f1, ops3, ops2, 2, Plain{});
+    step(f1, f0, ops0, ops3, 3, Plain{});
     next_round();
-    ek += 4;
-    if (ek == S) {  // the round ended tile et: store it, start the next
-      epilogue(et);
-      clear();
-      ek = 0;
-      ++et;
-    }
+  };
+  // tile by tile, the first apart (no stores before it): each code path keeps the same
+  // number of operations in flight, so the compiler's own waits stay exact
+  const int rounds = S / 4;
+  for (int r = 0; r < rounds; ++r) round(Plain{});
+  epilogue(0);
+  clear();
+  for (int t = 1; t < mine; ++t) {
+    round(AfterStores{});
+    for (int r = 1; r < rounds; ++r) round(Plain{});
+    epilogue(t);
+    clear();
   }
   // the copies past the last step are still landing in LDS: not past the workgroup's end
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
