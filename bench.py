@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # a 1 GiB copy (2.0 x FETCH + 1.0 x WRITE), keyed by the kernel the bench line names.  Only valid
 # for the kernel revision the counters were taken on: remove an entry whenever that kernel changes.
 MEASURED_TRAFFIC = {
-    "merge_gemm (fp16x3, v4)": 2.2373e+09,   # profiles/merge_gemm_fp16x3_q28_k64_counters.txt
+    "merge_gemm (fp16x3, v4)": 2.234e+09,   # profiles/merge_gemm_fp16x3_q28_k64_counters.txt
 }
 FP32_PEAK_TFLOPS = 157.3
 # float32 flops per amplitude of a fused dense 2x2 gate (two complex multiply-adds, FMA = 2 flops)
