@@ -395,7 +395,8 @@ int ccut_plan_work(const ccut_plan_t* plan, double out[5]);
  * 32 terms run as epilogue 1.
  * grid_cap 0 launches one workgroup per tile, > 0 a persistent grid of at most
  * grid_cap workgroups looping over tiles (ignored by epilogues 4 and 5, whose
- * grid is one workgroup per CU).  Results do not depend on either.
+ * grid is one workgroup per CU).  Results do not depend on either.  A new plan
+ * starts at epilogue 4 when no stage has more than 64 terms, else at 5.
  * Host-only.  Errors: CCUT_EINVAL.
  */
 int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap);
