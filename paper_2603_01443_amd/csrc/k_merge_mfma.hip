@@ -42,6 +42,20 @@ typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
+// 16-byte stores whose data registers the next vector instructions may overwrite.  The
+// store reads its four data registers over several cycles after it issues, and the
+// compiler does not keep a following vector write away from them: in a GEMM variant
+// that wrote one instruction behind such a store, the last quarter of each 16-lane
+// group stored the new value of the first register (wrong .x words in 16-amplitude
+// pieces, different from run to run).  Nothing is scheduled in the few cycles after
+// these stores.
+__device__ __forceinline__ void store16_nt(f32x4 v, f32x4* p) {
+  __builtin_nontemporal_store(v, p);
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_nop 4" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
   u += 0x7FFFu + ((u >> 16) & 1u);
@@ -322,7 +336,7 @@ __global__ __launch_bounds__(256) void k_merge_gemm(const uint4* __restrict__ Lh
             f32x4 v = *reinterpret_cast<const f32x4*>(my + row * EPI_LDS_ROW + 4 * (lane & 31));
             v *= scale;
             const uint64_t grow = (uint64_t)(rb0 + r) * 32 + 16 * h + row;
-            __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(ob + grow * ncols + col0));
+            store16_nt(v, reinterpret_cast<f32x4*>(ob + grow * ncols + col0));
           }
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           __builtin_amdgcn_wave_barrier();
@@ -689,7 +703,7 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
           v *= scale;
           const int brow = 8 * (h >> 1) + 4 * (row >> 1) + 2 * (h & 1) + (row & 1);
           const uint64_t grow = (uint64_t)(rb0 + r) * 32 + brow;
-          __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(ob + grow * ncols + col0));
+          store16_nt(v, reinterpret_cast<f32x4*>(ob + grow * ncols + col0));
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
