@@ -173,6 +173,27 @@ def test_merge_gemm_variants_bit_identical(lib, prec, c):
             assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref)), (variant, cap)
 
 
+@pytest.mark.parametrize("prec", ["fp16x3", "fp16x2"])
+def test_merge_gemm_repeatable(lib, prec):
+    """Every GEMM variant writes the same bits run after run (a 16-byte epilogue store
+    whose first data register a vector write reused one instruction later had made a few
+    words differ from run to run in the f16 modes): q = 24, K = 64, four runs each."""
+    ccut, pipeline = lib
+    q, n, c = 24, 2, 6
+    g = brickwork(q, 6, n, c, seed=3)
+    run = pipeline.CutRun(q, g, n)
+    run.simulate_subcircuits()
+    ref = None
+    for variant in range(6):
+        ccut.plan_set_merge(run.plan, variant, 0)
+        for rep in range(4):
+            run.psi.zero_()
+            out = run.merge(prec).clone()
+            if ref is None:
+                ref = out
+            assert torch.equal(torch.view_as_real(out), torch.view_as_real(ref)), (variant, rep)
+
+
 @pytest.mark.parametrize("prec", ["fp16x3", "fp16x2", "bf16x3"])
 def test_merge_gemm_variants_bit_identical_chain(lib, prec):
     """Three segments (8 + 8 + 8 qubits, 2 + 2 cuts): the chain's first stage is a batch of
