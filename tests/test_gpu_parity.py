@@ -501,6 +501,32 @@ def test_bench_config_split_precision(lib):
         assert 1 - st["fidelity"] <= 1e-6
 
 
+def test_large_k_split_precision_sampled(lib):
+    """The large-K configuration (q = 30, 15 + 15, d = 20, K = 256) at full size: the plan's
+    default GEMM there is the LDS-staged variant; 300 sampled amplitudes against the
+    oracle's variant states (Alg. 3 term by term) and 1 - F against the uncut state."""
+    ccut, pipeline = lib
+    q, d, n, c = 30, 20, 2, 8
+    g = brickwork(q, d, n, c, seed=0)
+    run = pipeline.CutRun(q, g, n)
+    assert ccut.plan_get_merge(run.plan)["variant"] == 5
+    ref = pipeline.uncut(q, g)
+    sizes = [15, 15]
+    ocuts = cutting.find_cuts(q, g, sizes)
+    ostates = cutting.variant_states(q, g, sizes, ocuts)
+    rng = np.random.default_rng(5)
+    xs = sorted(set(int(x) for x in rng.integers(0, 2 ** q, size=300)))
+    want = cutting.amplitudes(xs, sizes, ocuts, ostates)
+    for prec in ("fp16x3", "bf16x3", "fp16x2"):
+        psi = run.run(prec)
+        got = to_np(psi[torch.tensor(xs, device=psi.device)])
+        st = ccut.norm_fidelity(psi, ref, q)
+        print(f"q30 K256 {prec}: sampled max-abs {np.max(np.abs(got - want)):.3e}, 1-F vs uncut "
+              f"{1 - st['fidelity']:.3e}", flush=True)
+        assert np.max(np.abs(got - want)) < split_tol(q, prec)
+        assert 1 - st["fidelity"] <= 1e-6
+
+
 @pytest.mark.parametrize("d", [10, 20])
 def test_bench_config_tuned(lib, d):
     """The measured workload in the launch configuration the bench runs: simulation groups
