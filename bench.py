@@ -6,8 +6,9 @@ qubits, two equal segments of 14, depth d = 20, c_total = 6 cut CZs
 (K = 64 merge terms), seed 0.  One step is the whole cut pipeline of
 Eq. (runtime_decomp): cut_plan on the host (T_pre), every subcircuit variant
 (T_sub) and the merge into the 2^28 complex64 state (T_merge), with the merge
-in the library's default arithmetic (AUTO: the fully split fp16 hi + lo
-product on MFMA at this term count), launched directly on one stream.
+in the library's default arithmetic (AUTO: the fully split hi + lo product on
+MFMA at this term count, fp16 or bf16 halves as the autotuner finds faster),
+launched directly on one stream.
 value = 2^q amplitudes per step / seconds per step.  Within the timed steps
 only the merge GEMM (the roofline kernel) is bracketed by HIP events.
 
@@ -39,7 +40,9 @@ HBM_PEAK_GBS = 8000.0
 # a 1 GiB copy (2.0 x FETCH + 1.0 x WRITE), keyed by the kernel the bench line names.  Only valid
 # for the kernel revision the counters were taken on: remove an entry whenever that kernel changes.
 MEASURED_TRAFFIC = {
-    "merge_gemm (fp16x3, v4)": 2.234e+09,   # profiles/merge_gemm_fp16x3_q28_k64_counters.txt
+    "merge_gemm (fp16x3, v4)": 2.234e+09,   # profiles/merge_gemm_rs_fp16x3_q28_k64_counters.txt
+    "merge_gemm (fp16x3, v6)": 2.232e+09,   # profiles/merge_gemm_rc_fp16x3_q28_k64_counters.txt
+    "merge_gemm (bf16x3, v6)": 2.233e+09,   # profiles/merge_gemm_rc_bf16x3_q28_k64_counters.txt
 }
 FP32_PEAK_TFLOPS = 157.3
 # float32 flops per amplitude of a fused dense 2x2 gate (two complex multiply-adds, FMA = 2 flops)

@@ -392,11 +392,16 @@ int ccut_plan_work(const ccut_plan_t* plan, double out[5]);
  * over 256-row x 256-column tiles, copying each MFMA step's fragments of both
  * factors from L2 straight into LDS once per tile (four steps ahead, four
  * buffers) for all its wavefronts; stages with fewer than 256 rows or fewer than
- * 32 terms run as epilogue 1.
+ * 32 terms run as epilogue 1.  epilogue 6 is the column-stationary kernel: each
+ * wavefront of an 8-wavefront workgroup keeps one 32-column block of a 128-column
+ * strip of the low-qubit factor in registers, the workgroup sweeps its rows 32 at
+ * a time with the high-qubit factor's fragments in LDS, and stores each 32-row
+ * tile through LDS as whole 1 KiB row segments (two workgroups per CU); it covers
+ * up to K = 64 terms per stage and runs larger stages as epilogue 1.
  * grid_cap 0 launches one workgroup per tile, > 0 a persistent grid of at most
- * grid_cap workgroups looping over tiles (ignored by epilogues 4 and 5, whose
- * grid is one workgroup per CU).  Results do not depend on either.  A new plan
- * starts at epilogue 4 when no stage has more than 64 terms, else at 5.
+ * grid_cap workgroups looping over tiles (ignored by epilogues 4 to 6, which size
+ * their own grids).  Results do not depend on either.  A new plan starts at
+ * epilogue 6 when no stage has more than 64 terms, else at 5.
  * Host-only.  Errors: CCUT_EINVAL.
  */
 int ccut_plan_set_merge(ccut_plan_t* plan, int32_t epilogue, int32_t grid_cap);
@@ -500,7 +505,7 @@ int ccut_plan_get_fusion(const ccut_plan_t* plan, int32_t* out);
  * a forward and a backward sweep, median of max(reps, 7) runs each, keeping the
  * better median, since short merges see clock drift; the plan's current split
  * arithmetic, GEMM variant and grid are kept unless another is more than 2 % faster;
- * BF16X3, the less accurate split, is taken only if more than 5 % faster than FP16X3),
+ * BF16X3, the less accurate split, is taken only if more than 2 % faster than FP16X3),
  * applies the fastest (AUTO then merges in the chosen split arithmetic)
  * to the plan and records it in a process-wide cache keyed by (architecture,
  * plan shape); later plans of the same shape start from it (their tables, and so

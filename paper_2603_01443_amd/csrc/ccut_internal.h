@@ -13,7 +13,7 @@
 namespace ccut {
 
 // MFMA merge GEMM variants (0..3 tiled, 4 R-stationary, 5 LDS-staged; see merge_mfma.h)
-constexpr int MERGE_VARIANTS = 6;
+constexpr int MERGE_VARIANTS = 7;
 
 // ----------------------------------------------------------------- errors
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));

@@ -575,10 +575,10 @@ extern "C" int ccut_cut_plan(int32_t q, const ccut_gate_t* gates, int64_t n_gate
     if (S.c > 0) P->tree_bytes = align256(P->tree_bytes + (((uint64_t)8 << S.q) << S.c));
   }
 
-  // MFMA merge GEMM: the R-stationary kernel up to K = 64, else the LDS-staged one
+  // MFMA merge GEMM: the column-stationary kernel up to K = 64, else the LDS-staged one
   int kmax = 1;
   for (const MergeStage& st : P->stages) kmax = std::max(kmax, st.K);
-  P->merge_epilogue = kmax <= 64 ? 4 : 5;
+  P->merge_epilogue = kmax <= 64 ? 6 : 5;
 
   apply_tuned(P);
   if (int rc = build_sim_tables(P, true)) return rc;

@@ -465,8 +465,8 @@ def run_gemm(args):
         alg = 8 * (1 << q) + 8 * (2 ** c) * 2 * (1 << (q // 2))
         ccut.profile_enable(True)
         for prec in (("bf16x3", "fp16x3", "fp16x2", "bf16") if only is None else (only[2],)):
-            for v in (range(6) if only is None else (only[3],)):
-                for gc in ((0, 1024) if v < 4 and only is None else (0,)):   # 4 and 5: one workgroup per CU
+            for v in (range(7) if only is None else (only[3],)):
+                for gc in ((0, 1024) if v < 4 and only is None else (0,)):   # 4 to 6: one workgroup per CU
                     ccut.plan_set_merge(plan, v, gc)
                     ccut.merge_full_state(plan, arena, psi, prec, stream=s)
                     torch.cuda.synchronize()

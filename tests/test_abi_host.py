@@ -117,12 +117,12 @@ def test_error_codes():
 
 
 def test_merge_variant_range():
-    """Merge GEMM variants 0..5 are accepted and read back; 6 and negative grids are not."""
+    """Merge GEMM variants 0..6 are accepted and read back; 7 and negative grids are not."""
     plan = ccut.cut_plan(16, brickwork(16, 4, 2, 3, seed=1), 2)
-    for v in range(6):
+    for v in range(7):
         ccut.plan_set_merge(plan, v, 256)
         assert ccut.plan_get_merge(plan) == {"variant": v, "grid_cap": 256}
-    for v, cap in ((6, 0), (-1, 0), (3, -1)):
+    for v, cap in ((7, 0), (-1, 0), (3, -1)):
         with pytest.raises(ccut.CcutError) as e:
             ccut.plan_set_merge(plan, v, cap)
         assert e.value.code == ccut.EINVAL

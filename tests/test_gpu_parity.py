@@ -531,8 +531,8 @@ def test_large_k_split_precision_sampled(lib):
 def test_bench_config_tuned(lib, d):
     """The measured workload in the launch configuration the bench runs: simulation groups
     as split-fp16 MFMA, 2^12-amplitude blocks (several LDS passes per 14-qubit state), the
-    prefix tree from level c - 1 = 5, 512-thread workgroups, the R-stationary merge GEMM and
-    AUTO = fp16x3; then the configuration the autotuner picks on this device.  Both at
+    prefix tree from level c - 1 = 5, 512-thread workgroups, the column-stationary merge GEMM
+    and AUTO = fp16x3; then the configuration the autotuner picks on this device.  Both at
     q = 28 (14 + 14), c_total = 6, seed 0: >= 400 sampled amplitudes against the oracle's
     plain sum at the split-merge bar, 1 - F <= 1e-6 and unit norm against the uncut state."""
     ccut, pipeline = lib
@@ -568,7 +568,7 @@ def test_bench_config_tuned(lib, d):
     ccut.plan_set_prefix_sharing(run.plan, 1)
     ccut.plan_set_prefix_start(run.plan, c - 1)
     ccut.plan_set_launch(run.plan, threads=512)
-    ccut.plan_set_merge(run.plan, 4, 0)
+    ccut.plan_set_merge(run.plan, 6, 0)
     assert ccut.plan_get_auto_precision(run.plan) == "fp16x3"
     assert ccut.plan_get_block_bits(run.plan) == 12 and ccut.plan_get_prefix_start(run.plan) == c - 1
     assert ccut.plan_stats(run.plan)["passes"] > 2      # 2^14 states in 2^12 blocks: multi-pass

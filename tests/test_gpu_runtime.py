@@ -153,7 +153,7 @@ def test_autotune_keeps_results_and_caches(lib, tmp_path):
                                     ("fp16x2", 3), ("bf16", 5), ("fp16x2", 7), ("fp16x3", 8), ("bf16x3", 8)])
 def test_merge_gemm_variants_bit_identical(lib, prec, c):
     """Store path (direct / LDS transpose), tile height, persistent grids, the
-    R-stationary kernel and the LDS-staged kernel change only data movement: every
+    R-stationary, LDS-staged and column-stationary kernels change only data movement: every
     variant writes the same bits, also at K = 8, 32, 128 and 256 (c = 3, 5, 7, 8: one,
     four, sixteen and thirty-two MFMA steps; from sixteen on the R-stationary strip
     runs the tiled kernel instead)."""
@@ -163,7 +163,7 @@ def test_merge_gemm_variants_bit_identical(lib, prec, c):
     run = pipeline.CutRun(q, g, n)
     run.simulate_subcircuits()
     ref = None
-    for variant in range(6):
+    for variant in range(7):
         for cap in (0, 37, 512):
             ccut.plan_set_merge(run.plan, variant, cap)
             run.psi.zero_()
@@ -184,7 +184,7 @@ def test_merge_gemm_repeatable(lib, prec):
     run = pipeline.CutRun(q, g, n)
     run.simulate_subcircuits()
     ref = None
-    for variant in range(6):
+    for variant in range(7):
         ccut.plan_set_merge(run.plan, variant, 0)
         for rep in range(4):
             run.psi.zero_()
@@ -199,15 +199,15 @@ def test_merge_gemm_variants_bit_identical_chain(lib, prec):
     """Three segments (8 + 8 + 8 qubits, 2 + 2 cuts): the chain's first stage is a batch of
     four merges with one weighted factor per batch entry; every GEMM variant writes the same
     bits there and in the final stage, the R-stationary kernel splits its rows over
-    several workgroups per strip at these small shapes, and the LDS-staged kernel runs
-    its persistent grid over the batch."""
+    several workgroups per strip at these small shapes (the column-stationary kernel
+    too), and the LDS-staged kernel runs its persistent grid over the batch."""
     ccut, pipeline = lib
     q, n = 24, 3
     g = brickwork(q, 8, n, 4, seed=5)
     run = pipeline.CutRun(q, g, n)
     run.simulate_subcircuits()
     ref = None
-    for variant in range(6):
+    for variant in range(7):
         ccut.plan_set_merge(run.plan, variant, 0)
         run.psi.zero_()
         out = run.merge(prec).clone()
