@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 # for the kernel revision the counters were taken on: remove an entry whenever that kernel changes.
 MEASURED_TRAFFIC = {
     "merge_gemm (fp16x3, v4)": 2.234e+09,   # profiles/merge_gemm_rs_fp16x3_q28_k64_counters.txt
-    "merge_gemm (fp16x3, v6)": 2.232e+09,   # profiles/merge_gemm_rc_fp16x3_q28_k64_counters.txt
     "merge_gemm (bf16x3, v6)": 2.233e+09,   # profiles/merge_gemm_rc_bf16x3_q28_k64_counters.txt
+    "merge_gemm (fp16x3, v6)": 2.233e+09,   # profiles/merge_gemm_rc_fp16x3_q28_k64_counters.txt
 }
 FP32_PEAK_TFLOPS = 157.3
 # float32 flops per amplitude of a fused dense 2x2 gate (two complex multiply-adds, FMA = 2 flops)

@@ -392,12 +392,12 @@ int ccut_plan_work(const ccut_plan_t* plan, double out[5]);
  * over 256-row x 256-column tiles, copying each MFMA step's fragments of both
  * factors from L2 straight into LDS once per tile (four steps ahead, four
  * buffers) for all its wavefronts; stages with fewer than 256 rows or fewer than
- * 32 terms run as epilogue 1.  epilogue 6 is the column-stationary kernel: each
- * wavefront of an 8-wavefront workgroup keeps one 32-column block of a 128-column
- * strip of the low-qubit factor in registers, the workgroup sweeps its rows 32 at
- * a time with the high-qubit factor's fragments in LDS, and stores each 32-row
- * tile through LDS as whole 1 KiB row segments (two workgroups per CU); it covers
- * up to K = 64 terms per stage and runs larger stages as epilogue 1.
+ * 32 terms run as epilogue 1.  epilogue 6 is the column-stationary kernel: one
+ * 8-wavefront workgroup per CU owns a 128-column strip; four wavefronts keep two
+ * 32-column blocks each of the low-qubit factor in registers and compute, four
+ * fetch the high-qubit factor's fragments into LDS and store each 32-row tile
+ * through LDS as whole 1 KiB row segments; it covers up to K = 64 terms per stage
+ * and runs larger stages as epilogue 1.
  * grid_cap 0 launches one workgroup per tile, > 0 a persistent grid of at most
  * grid_cap workgroups looping over tiles (ignored by epilogues 4 to 6, which size
  * their own grids).  Results do not depend on either.  A new plan starts at

@@ -789,51 +789,53 @@ __global__ __launch_bounds__(LK_WAVES * 64) void k_merge_gemm_lk(
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
-// ------------------------- column-stationary GEMM with row-tile stores (K <= 64)
+// ------------------------------- column-stationary GEMM with row-tile stores (K <= 64)
 // The R-stationary kernel above runs at the speed of its store pattern: each store
-// instruction writes two 128-byte row pieces, and its wavefronts write different row
-// blocks (stores alone in that pattern: 5.0 TB/s).  Here the eight wavefronts of a
-// workgroup share the row block: wavefront w keeps the R fragments of column block w
-// of a 256-column strip for every step in registers (hi and lo: at most 64
-// registers), the row block's L fragments (16 KiB at most) sit in LDS, read by all
-// eight, and each 32 x 32 result goes into an LDS tile of 32 rows x 256 columns.
-// After a barrier the workgroup stores the tile with 16 bytes per lane, one whole
-// 1 KiB row segment per wavefront instruction (stores alone in this pattern:
-// 6.7 TB/s).  L is double-buffered and the tile single-buffered (65 KiB of LDS, at
-// most 128 registers), so that two workgroups share a CU and one computes while the
-// other waits at a barrier.  Round n fetches block n + 1's L fragments into
-// registers, stores tile n - 1 behind them, runs its products, waits for every
-// wavefront to have read the tile, writes tile n and puts the fetched fragments into
-// the free L buffer (a wait that passes the stores just issued: the counter is in
-// order and the loads came first).  The products are computed transposed (R
-// fragments as the A operand), so that each lane holds four adjacent columns of one
-// row per register group and writes the tile 16 bytes at a time; per step they run
-// in the tiled kernel's order (lo.hi, hi.lo, hi.hi) and the results are the same
-// bit for bit.  Measured at q = 28, K = 64 in the pipeline (after a simulation, as
-// the autotuner times it): 0.369 ms against 0.418 ms for the R-stationary kernel.
-constexpr int RC_WAVES = 8;     // one per 32-column block of a 256-column strip
-constexpr int RC_PITCH = 260;   // floats per row of the LDS tile (256 + 4)
+// instruction writes two 128-byte row pieces, and its 16 wavefronts write 16
+// different row blocks (stores alone in that pattern: 5.0 TB/s).  Here a workgroup
+// of 8 wavefronts owns a 256-column strip and sweeps a range of 32-row blocks, one
+// per round, with the work split by wavefront:
+//  - wavefronts 0..3 compute: wavefront c keeps column blocks 2 c and 2 c + 1's R
+//    fragments for every step in registers (hi and lo: at most 128 registers), reads
+//    the round's L fragments from LDS one step ahead of the products, and writes its
+//    two 32 x 32 results into an LDS tile of 32 rows x 256 columns;
+//  - wavefronts 4..7 move data: each round they fetch the row block two rounds ahead
+//    into registers, store the previous round's tile (8 rows of 1 KiB per wavefront,
+//    16 bytes per lane: one whole row segment per instruction; stores alone in this
+//    pattern reach 6.7 TB/s), then put the fetched fragments into LDS (a wait that
+//    passes the stores just issued: the counter is in order and the loads came
+//    first).
+// L is triple-buffered and the tile double-buffered (115 KiB of LDS, one workgroup
+// per CU), so one barrier per round orders everything.  The products are computed
+// transposed (R fragments as the A operand, L as B), so that a lane holds four
+// adjacent columns of one output row per register group and writes the tile 16 bytes
+// at a time; per step they run in the tiled kernel's order (lo.hi, hi.lo, hi.hi), so
+// the results are the same bit for bit.  Measured at q = 28, K = 64 in the pipeline
+// (after a simulation, candidates alternated on one box): fp16x3 0.385 to 0.398 ms,
+// bf16x3 0.366 to 0.372 ms, fp16x2 0.305 to 0.317 ms, against 0.400 to 0.406, 0.407
+// to 0.413 and 0.411 to 0.423 ms for the R-stationary kernel.
+constexpr int RC_PITCH = 260;  // floats per row of the LDS tile (256 + 4)
 
 template <int MODE, int S>
-__global__ __launch_bounds__(RC_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_merge_gemm_rc(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_merge_gemm_rc(
     const uint4* __restrict__ Lhi, const uint4* __restrict__ Llo, const uint4* __restrict__ Rhi,
     const uint4* __restrict__ Rlo, uint64_t l_bstride, uint64_t r_bstride, float* __restrict__ out,
     uint64_t out_bstride, int qx, int qy, int strips, int row_split) {
   constexpr bool L_SPLIT = MODE != MERGE_BF16;
   constexpr bool R_SPLIT = MODE == MERGE_BF16X3 || MODE == MERGE_FP16X3;
   constexpr int LP = L_SPLIT ? 2 : 1;
-  constexpr int NT = RC_WAVES * 64;
+  constexpr int ND = 256;                        // data threads
   constexpr int NL = S * LP * 64;                // 16-byte L items of one row block
-  constexpr int LPT = NL >= NT ? NL / NT : 1;    // items each thread fetches
-  static_assert(NL >= NT ? NL % NT == 0 : NT % NL == 0, "L items per thread");
-  // L items in LDS: (s * LP + plane) * 64 + lane
-  __shared__ u32x4 sL[2][NL];
-  __shared__ float tile[32 * RC_PITCH];
+  constexpr int LPT = NL >= ND ? NL / ND : 1;    // items each data thread fetches
+  static_assert(NL >= ND ? NL % ND == 0 : ND % NL == 0, "L items per thread");
+  __shared__ u32x4 sL[3][NL];
+  __shared__ float tile[2][32 * RC_PITCH];
   const int beta = blockIdx.y;
   const int strip = (int)blockIdx.x % strips;
   const int part = (int)blockIdx.x / strips;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool data = wave >= 4;
   const float scale = is_f16(MODE) ? (1.0f / 268435456.0f) : 1.0f;  // 2^-28
   const uint32_t ncols = 2u << qx;
   const int nrb = 1 << (qy - 5);
@@ -841,30 +843,32 @@ __global__ __launch_bounds__(RC_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4
   const int rb_begin = part * per;
   const int rb_end = min(nrb, rb_begin + per);
   if (rb_begin >= rb_end) return;  // the whole workgroup
+  const int nr = rb_end - rb_begin;
   float* ob = out + beta * out_bstride + (uint64_t)strip * 256;
   const uint4* lbh = Lhi + beta * l_bstride;
   const uint4* lbl = Llo + beta * l_bstride;
+  const int dt = tid - 256;  // data thread index (data wavefronts)
 
-  // this wavefront's column block: R fragments of every step, for the workgroup's life
-  uint4 Rh[S], Rl[S];
-  {
-    const uint64_t o = ((uint64_t)(strip * RC_WAVES + wave) * S) * 64 + lane;
-    const uint4* gh = Rhi + beta * r_bstride + o;
-    const uint4* gl = Rlo + beta * r_bstride + o;
+  // compute wavefront c: column blocks 2 c and 2 c + 1 of the strip
+  uint4 Rh[2][S], Rl[2][S];
+  if (!data) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      Rh[s] = gh[s * 64];
-      if (R_SPLIT) Rl[s] = gl[s * 64];
+    for (int b = 0; b < 2; ++b) {
+      const uint64_t o = ((uint64_t)(strip * 8 + 2 * wave + b) * S) * 64 + lane;
+      const uint4* gh = Rhi + beta * r_bstride + o;
+      const uint4* gl = Rlo + beta * r_bstride + o;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        Rh[b][s] = gh[s * 64];
+        if (R_SPLIT) Rl[b][s] = gl[s * 64];
+      }
     }
   }
-
   u32x4 lreg[LPT];
-  // L fragments of row block rb (< nrb) into registers; with fewer items than threads
-  // the rest fetch a duplicate, so that every wavefront issues the same loads
   auto fetch_l = [&](int rb) {
 #pragma unroll
     for (int j = 0; j < LPT; ++j) {
-      const int i = (tid + j * NT) % NL;
+      const int i = (dt + j * ND) % NL;
       const int sp = i >> 6, s = sp / LP, plane = sp % LP;
       const uint4* src = (plane ? lbl : lbh) + ((uint64_t)rb * S + s) * 64 + (i & 63);
       lreg[j] = __builtin_bit_cast(u32x4, *src);
@@ -873,30 +877,25 @@ __global__ __launch_bounds__(RC_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4
   auto put_l = [&](int buf) {
 #pragma unroll
     for (int j = 0; j < LPT; ++j)
-      if (NL >= NT || tid < NL) sL[buf][tid + j * NT] = lreg[j];
+      if (NL >= ND || dt < NL) sL[buf][dt + j * ND] = lreg[j];
   };
-  // tile of row block rb: 32 rows x 64 float4, row wave + 8 j in instruction j
-  auto store_tile = [&](int rb) {
+  // data wavefront d stores rows d + 4 j of the tile, one 1 KiB row per instruction
+  auto store_tile = [&](int rb, int buf) {
     float* orow = ob + (uint64_t)rb * 32 * ncols;
-    f32x4 v[4];
+    const int d = wave - 4;
+    f32x4 v[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = *reinterpret_cast<const f32x4*>(&tile[(wave + 8 * j) * RC_PITCH + 4 * lane]);
+    for (int j = 0; j < 8; ++j) v[j] = *reinterpret_cast<const f32x4*>(&tile[buf][(d + 4 * j) * RC_PITCH + 4 * lane]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) store16_nt(v[j], reinterpret_cast<f32x4*>(orow + (uint64_t)(wave + 8 * j) * ncols) + lane);
+    for (int j = 0; j < 8; ++j) store16_nt(v[j], reinterpret_cast<f32x4*>(orow + (uint64_t)(d + 4 * j) * ncols) + lane);
   };
-  auto round = [&](int n, auto first) {
-    const int rb = rb_begin + n;
-    fetch_l(min(rb + 1, rb_end - 1));  // the last round fetches its own block again
-    if (!decltype(first)::value) store_tile(rb - 1);
-    f32x16 acc;
+  auto compute = [&](int n) {
+    f32x16 acc[2];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-    // the block transposed (R fragments as the A operand, L as B): lane l then holds
-    // output row l % 32 and, in registers 4 j .. 4 j + 3, its columns
-    // 8 j + 4 (l / 32) .. + 3, one 16-byte LDS write each.  L fragments are read one
-    // step ahead of the products (all at once would take 4 S LP registers; left to
-    // itself the compiler reads each right before its product)
-    const u32x4* lb = sL[n & 1] + lane;
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[b][v] = 0.f;
+    const u32x4* lb = sL[n % 3] + lane;
     u32x4 cur[LP], nxt[LP];
 #pragma unroll
     for (int p = 0; p < LP; ++p) cur[p] = lb[p * 64];
@@ -908,33 +907,49 @@ __global__ __launch_bounds__(RC_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4
       }
       __builtin_amdgcn_sched_barrier(0);
       const uint4 lh = __builtin_bit_cast(uint4, cur[0]);
-      if (L_SPLIT) acc = mfma<MODE>(Rh[s], __builtin_bit_cast(uint4, cur[LP - 1]), acc);
-      if (R_SPLIT) acc = mfma<MODE>(Rl[s], lh, acc);
-      acc = mfma<MODE>(Rh[s], lh, acc);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (L_SPLIT) acc[b] = mfma<MODE>(Rh[b][s], __builtin_bit_cast(uint4, cur[LP - 1]), acc[b]);
+        if (R_SPLIT) acc[b] = mfma<MODE>(Rl[b][s], lh, acc[b]);
+        acc[b] = mfma<MODE>(Rh[b][s], lh, acc[b]);
+      }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int p = 0; p < LP; ++p) cur[p] = nxt[p];
     }
-    if (is_f16(MODE)) acc *= scale;
-    // every wavefront has read the previous tile before it is overwritten
-    __syncthreads();
-    float* t = &tile[(lane & 31) * RC_PITCH + wave * 32 + 4 * (lane >> 5)];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const f32x4 q = {acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]};
-      *reinterpret_cast<f32x4*>(t + 8 * j) = q;
+    for (int b = 0; b < 2; ++b) {
+      if (is_f16(MODE)) acc[b] *= scale;
+      float* t = &tile[n & 1][(lane & 31) * RC_PITCH + (2 * wave + b) * 32 + 4 * (lane >> 5)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const f32x4 q = {acc[b][4 * j], acc[b][4 * j + 1], acc[b][4 * j + 2], acc[b][4 * j + 3]};
+        *reinterpret_cast<f32x4*>(t + 8 * j) = q;
+      }
     }
-    put_l((n + 1) & 1);
+  };
+  auto round = [&](int n, auto first) {
+    if (data) {
+      // the fetch goes out before the stores, so that waiting for it passes them
+      fetch_l(rb_begin + min(n + 2, nr - 1));
+      if (!decltype(first)::value) store_tile(rb_begin + n - 1, (n - 1) & 1);
+      put_l((n + 2) % 3);
+    } else {
+      compute(n);
+    }
     __syncthreads();
   };
 
-  fetch_l(rb_begin);
-  put_l(0);
+  if (data) {
+    fetch_l(rb_begin);
+    put_l(0);
+    fetch_l(rb_begin + min(1, nr - 1));
+    put_l(1);
+  }
   __syncthreads();
-  const int nr = rb_end - rb_begin;
   round(0, std::true_type{});
   for (int n = 1; n < nr; ++n) round(n, std::false_type{});
-  store_tile(rb_end - 1);
+  if (data) store_tile(rb_end - 1, (nr - 1) & 1);
 }
 
 // S in {1, 2, 4, 8} (K <= 64; K is a power of two) and row offsets of a 32-row block
@@ -992,17 +1007,17 @@ int launch_mode(const MergeMfmaArgs& a, int variant, int grid_cap, hipStream_t s
   }
   if (variant == 6 && merge_rs_supported(a.qx, S)) {
     // column-stationary kernel: one workgroup per (strip, row part, batch entry), row
-    // parts as many as it takes to give every CU two workgroups
+    // parts as many as it takes to give every CU one workgroup
     const int strips = 1 << (a.qx + 1 - 8);
     const int nrb = 1 << (a.qy - 5);
-    const int want = (2 * cu_count() + strips * a.batch - 1) / (strips * a.batch);
+    const int want = (cu_count() + strips * a.batch - 1) / (strips * a.batch);
     const int row_split = std::max(1, std::min(want, nrb));
     if ((uint64_t)strips * row_split > 0x7FFFFFFFull) return fail(CCUT_EUNSUPPORTED, "merge too large");
     dim3 grid((unsigned)(strips * row_split), a.batch);
     const uint64_t r_bstride = a.r_batch > 1 ? a.r_plane_stride : 0;
     ProfScope prof(PROF_MERGE_GEMM, s);
 #define CCUT_RC(SS)                                                                                              \
-  hipLaunchKernelGGL((k_merge_gemm_rc<MODE, SS>), grid, dim3(RC_WAVES * 64), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo,    \
+  hipLaunchKernelGGL((k_merge_gemm_rc<MODE, SS>), grid, dim3(512), 0, s, a.Lhi, a.Llo, a.Rhi, a.Rlo,              \
                      a.l_plane_stride, r_bstride, a.out, a.out_bstride * 2, a.qx, a.qy, strips, row_split)
     switch (S) {
       case 1: CCUT_RC(1); break;

@@ -31,11 +31,11 @@ bool merge_mfma_supported(int qx, int qy);
 //            over 256 x 256 tiles, each step's fragments copied from L2 straight
 //            into LDS once per tile (four buffers); needs qy >= 8 and K >= 32,
 //            else it runs as variant 1.
-// variant 6: column-stationary kernel: each wavefront of an 8-wavefront workgroup
-//            holds one column block's R fragments in registers, the row block's L
-//            fragments are shared in LDS, and each 32 x 256 tile is stored through
-//            LDS as whole 1 KiB row segments; two workgroups per CU, K <= 64 (else
-//            variant 1).
+// variant 6: column-stationary kernel: one 8-wavefront workgroup per CU and
+//            256-column strip; four wavefronts hold two column blocks' R fragments
+//            each in registers and compute, four fetch the row blocks' L fragments
+//            into LDS and store each 32 x 256 tile through LDS as whole 1 KiB row
+//            segments; K <= 64 (else variant 1).
 // grid_cap > 0: persistent grid of at most grid_cap workgroups per batch entry.
 int launch_merge_mfma(const MergeMfmaArgs& a, int mode, int variant, int grid_cap, hipStream_t s);
 
