@@ -241,7 +241,7 @@ int compile_uncut(int32_t q, const ccut_gate_t* gates, int64_t n_gates, UncutPro
     pb.gate(g, 0);
   }
   std::vector<Pass> passes;
-  if (int rc = schedule_passes(pb.prog, UNCUT_BLOCK_BITS, 4, passes)) return rc;
+  if (int rc = schedule_passes(pb.prog, UNCUT_BLOCK_BITS, 4, passes, true, true)) return rc;
   for (const Pass& p : passes) {
     int pid = append_pass(p, q, U.descs, U.stages, U.kops, U.grefs, true);  // tables built once per program
     SimJob j;
@@ -288,14 +288,14 @@ extern "C" int ccut_simulate_subcircuits(ccut_plan_t* plan, void* d_arena, uint6
         const SimJob& job = plan->jobs[L.job_begin + j];
         const int nb = plan->pass_descs[job.pass_id].n_blocks;
         if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, nb, job.wg_begin, T.passes, T.stages, T.ops, gtab,
-                                static_cast<float*>(d_arena), plan->bmax, L.hdr_cap, L.stg_cap, plan->sim_threads,
+                                static_cast<float*>(d_arena), plan->bmax, L.rec_cap, plan->sim_threads,
                                 0, s))
           return rc;
       }
       continue;
     }
     if (int rc = launch_sim(T.jobs + L.job_begin, L.n_jobs, L.total_wg, 0, T.passes, T.stages, T.ops, gtab,
-                            static_cast<float*>(d_arena), plan->bmax, L.hdr_cap, L.stg_cap, plan->sim_threads,
+                            static_cast<float*>(d_arena), plan->bmax, L.rec_cap, plan->sim_threads,
                             plan->sim_grid_cap, s))
       return rc;
   }
@@ -430,8 +430,8 @@ extern "C" int ccut_simulate_uncut(int32_t q, const ccut_gate_t* gates, int64_t 
   for (size_t p = 0; p < U->jobs.size(); ++p) {
     const PassDesc& d = U->descs[p];
     if (int rc = launch_sim(U->dev.jobs + p, 1, d.n_blocks, 0, U->dev.passes, U->dev.stages, U->dev.ops, U->gtab,
-                            static_cast<float*>(d_psi), UNCUT_BLOCK_BITS, d.stage_count > 0 ? d.op_count : 0,
-                            d.stage_count, UNCUT_THREADS, 0, s))
+                            static_cast<float*>(d_psi), UNCUT_BLOCK_BITS,
+                            d.stage_count > 0 ? d.op_count + d.stage_count : 0, UNCUT_THREADS, 0, s))
       return rc;
   }
   return CCUT_OK;

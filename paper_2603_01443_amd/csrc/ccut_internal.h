@@ -185,8 +185,11 @@ void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& sta
 
 // Schedule a program into LDS-blocked passes of at most 2^bmax amplitudes.
 // Low qubits [0, low_bits) sit in every block (coalesced runs).  The first pass
-// starts from |0...0> (from_zero) or from a source state the job names.
-int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out, bool from_zero = true);
+// starts from |0...0> (from_zero) or from a source state the job names.  A pass
+// whose register-stage records would not fit in LDS beside its block (fuse: as
+// stage_kops builds them) is split into consecutive passes over the same qubits.
+int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out, bool from_zero = true,
+                    bool fuse = false);
 
 // A launch entry: one state (or a batch position) processed by one pass.
 struct SimJob {
@@ -241,13 +244,13 @@ struct ProfScope {
 // makes the launch persistent (each workgroup loops over several blocks).
 // gtab != nullptr selects the split-float16 MFMA path for register-stage groups
 // (operand tables built by launch_group_tables); nullptr keeps float32 VALU.
-// hdr_cap / stg_cap: the most op records and register stages of any pass the
-// launch runs (the kernel copies a pass's op headers and stage heads to LDS).
+// rec_cap: the most op records plus register stages of any pass the launch runs
+// (the kernel copies a pass's op headers and stage heads to LDS, 32 bytes each).
 int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
                const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax,
-               int hdr_cap, int stg_cap, int threads, int grid_cap, hipStream_t s);
-// LDS bytes of a simulation workgroup with those capacities.
-size_t sim_shmem_bytes(int bmax, int hdr_cap, int stg_cap);
+               int rec_cap, int threads, int grid_cap, hipStream_t s);
+// LDS bytes of a simulation workgroup with that capacity.
+size_t sim_shmem_bytes(int bmax, int rec_cap);
 
 // Copies `bytes` (a multiple of 16, 16-byte aligned) from pinned host memory to dst.
 int launch_table_copy(void* dst, const void* host_src, uint64_t bytes, hipStream_t s);

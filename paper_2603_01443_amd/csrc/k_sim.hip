@@ -393,23 +393,22 @@ struct StageHead {
   int32_t op_begin, op_count, reg[REG_BITS], pad[2];
 };
 
-// hdr_cap / stg_cap: LDS room for the op headers and stage heads of the largest
-// pass of the launch (every pass of the launch has at most that many).
+// rec_cap: LDS room (32-byte records) for the op headers and stage heads of the
+// largest pass of the launch; a pass's stage heads follow its own op headers.
 // At most 128 VGPRs (four wavefronts per SIMD): two 512-thread workgroups share a
 // compute unit where their LDS allows it, one computing while the other waits.
 template <int NT, bool MFMA>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_sim(const SimJob* __restrict__ jobs, int n_jobs, int total_wg,
                                             int wg_offset, const PassDesc* __restrict__ passes,
                                             const StageDesc* __restrict__ stages, const KOp* __restrict__ ops,
-                                            const uint4* __restrict__ gtab, float2* __restrict__ base, int hdr_cap,
-                                            int stg_cap) {
+                                            const uint4* __restrict__ gtab, float2* __restrict__ base,
+                                            int rec_cap) {
   const float scale_in = MFMA ? SIM_MFMA_SCALE : 1.0f, scale_out = MFMA ? 1.0f / SIM_MFMA_SCALE : 1.0f;
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* lo_tab = reinterpret_cast<uint64_t*>(smem);
   uint64_t* hi_tab = lo_tab + TAB;
   OpHead* hdr = reinterpret_cast<OpHead*>(hi_tab + TAB);
-  StageHead* stg = reinterpret_cast<StageHead*>(hdr + hdr_cap);
-  float2* sh = reinterpret_cast<float2*>(stg + stg_cap);
+  float2* sh = reinterpret_cast<float2*>(hdr + rec_cap);
   const int tid = threadIdx.x;
 
   for (int w = blockIdx.x; w < total_wg; w += gridDim.x) {
@@ -417,6 +416,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     // the same index in every lane: readfirstlane lets the compiler keep the job in scalar registers
     const SimJob job = jobs[n_jobs > 1 ? __builtin_amdgcn_readfirstlane(find_job(jobs, n_jobs, wg)) : 0];
     const PassDesc* P = passes + job.pass_id;
+    StageHead* stg = reinterpret_cast<StageHead*>(hdr + P->op_count);  // after the pass's op headers
     const int b = P->b;
     const int nb = 1 << b;
     const int nfix = P->nq - b;
@@ -535,8 +535,9 @@ __global__ __launch_bounds__(256) void k_table_copy(uint4* __restrict__ dst, con
     dst[i] = src[i];
 }
 
-constexpr size_t shmem_bytes(int bmax, int hdr_cap, int stg_cap) {
-  return 2 * TAB * sizeof(uint64_t) + (size_t)hdr_cap * sizeof(OpHead) + (size_t)stg_cap * sizeof(StageHead) +
+static_assert(sizeof(OpHead) == sizeof(StageHead), "one LDS record size");
+constexpr size_t shmem_bytes(int bmax, int rec_cap) {
+  return 2 * TAB * sizeof(uint64_t) + (size_t)rec_cap * sizeof(OpHead) +
          sizeof(float2) * (((size_t)1 << bmax) + ((size_t)1 << bmax) / 16);
 }
 
@@ -705,9 +706,9 @@ __global__ __launch_bounds__(64) void k_group_tables(const KOp* __restrict__ ops
 
 template <int NT, bool MFMA>
 int launch_sim_t(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
-                 const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int hdr_cap,
-                 int stg_cap, int grid, hipStream_t s) {
-  const size_t shmem = shmem_bytes(bmax, hdr_cap, stg_cap);
+                 const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int rec_cap,
+                 int grid, hipStream_t s) {
+  const size_t shmem = shmem_bytes(bmax, rec_cap);
   static bool attr_set = false;
   if (!attr_set) {
     CCUT_HIP(hipFuncSetAttribute((const void*)k_sim<NT, MFMA>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -716,25 +717,25 @@ int launch_sim_t(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, 
   }
   ProfScope prof(PROF_SIM, s);
   hipLaunchKernelGGL((k_sim<NT, MFMA>), dim3(grid), dim3(NT), shmem, s, d_jobs, n_jobs, total_wg, wg_offset,
-                     d_passes, d_stages, d_ops, gtab, reinterpret_cast<float2*>(base), hdr_cap, stg_cap);
+                     d_passes, d_stages, d_ops, gtab, reinterpret_cast<float2*>(base), rec_cap);
   CCUT_HIP(hipGetLastError());
   return 0;
 }
 
 template <bool MFMA>
 int launch_sim_m(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
-                 const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int hdr_cap,
-                 int stg_cap, int threads, int grid, hipStream_t s) {
+                 const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int rec_cap,
+                 int threads, int grid, hipStream_t s) {
   switch (threads) {
     case 256:
       return launch_sim_t<256, MFMA>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base,
-                                     bmax, hdr_cap, stg_cap, grid, s);
+                                     bmax, rec_cap, grid, s);
     case 512:
       return launch_sim_t<512, MFMA>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base,
-                                     bmax, hdr_cap, stg_cap, grid, s);
+                                     bmax, rec_cap, grid, s);
     case 1024:
       return launch_sim_t<1024, MFMA>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base,
-                                      bmax, hdr_cap, stg_cap, grid, s);
+                                      bmax, rec_cap, grid, s);
     default:
       return fail(CCUT_EINVAL, "unsupported workgroup size %d", threads);
   }
@@ -742,22 +743,22 @@ int launch_sim_m(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, 
 
 }  // namespace
 
-size_t sim_shmem_bytes(int bmax, int hdr_cap, int stg_cap) { return shmem_bytes(bmax, hdr_cap, stg_cap); }
+size_t sim_shmem_bytes(int bmax, int rec_cap) { return shmem_bytes(bmax, rec_cap); }
 
 int launch_sim(const SimJob* d_jobs, int n_jobs, int total_wg, int wg_offset, const PassDesc* d_passes,
-               const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int hdr_cap,
-               int stg_cap, int threads, int grid_cap, hipStream_t s) {
+               const StageDesc* d_stages, const KOp* d_ops, const uint4* gtab, float* base, int bmax, int rec_cap,
+               int threads, int grid_cap, hipStream_t s) {
   if (total_wg <= 0 || n_jobs <= 0) return 0;
   if (bmax < 1 || bmax > PASS_MAX_B) return fail(CCUT_EINVAL, "bad block bits %d", bmax);
-  if (hdr_cap < 0 || stg_cap < 0 || shmem_bytes(bmax, hdr_cap, stg_cap) > SIM_LDS_MAX)
+  if (rec_cap < 0 || shmem_bytes(bmax, rec_cap) > SIM_LDS_MAX)
     return fail(CCUT_EUNSUPPORTED, "simulation pass needs %zu bytes of LDS (at most %zu)",
-                shmem_bytes(bmax, hdr_cap, stg_cap), (size_t)SIM_LDS_MAX);
+                shmem_bytes(bmax, rec_cap), (size_t)SIM_LDS_MAX);
   const int grid = (grid_cap > 0 && grid_cap < total_wg) ? grid_cap : total_wg;
   if (gtab)
     return launch_sim_m<true>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, gtab, base, bmax,
-                              hdr_cap, stg_cap, threads, grid, s);
+                              rec_cap, threads, grid, s);
   return launch_sim_m<false>(d_jobs, n_jobs, total_wg, wg_offset, d_passes, d_stages, d_ops, nullptr, base, bmax,
-                             hdr_cap, stg_cap, threads, grid, s);
+                             rec_cap, threads, grid, s);
 }
 
 int launch_table_copy(void* dst, const void* host_src, uint64_t bytes, hipStream_t s) {

@@ -119,7 +119,7 @@ int build_tree_launches(ccut_plan* P) {
       const int begin = l == L0 ? 0 : pos[l - 1];
       const int end = l < S.c ? pos[l] : (int)S.prog.ops.size();
       chunk.ops.assign(S.prog.ops.begin() + begin, S.prog.ops.begin() + end);
-      if (int rc = schedule_passes(chunk, P->bmax, P->low_bits, S.chunk_passes[l], l == L0)) return rc;
+      if (int rc = schedule_passes(chunk, P->bmax, P->low_bits, S.chunk_passes[l], l == L0, P->fuse)) return rc;
     }
     max_c = std::max(max_c, S.c);
   }
@@ -183,7 +183,7 @@ int build_sim_tables(ccut_plan* P, bool first) {
   P->jobs.clear();
   P->launches.clear();
   for (auto& S : P->segs)
-    if (int rc = schedule_passes(S.prog, P->bmax, P->low_bits, S.passes)) return rc;
+    if (int rc = schedule_passes(S.prog, P->bmax, P->low_bits, S.passes, true, P->fuse)) return rc;
   const int n_seg = P->n_seg;
   if (P->prefix_on) {
     if (int rc = build_tree_launches(P)) return rc;
@@ -223,10 +223,7 @@ int build_sim_tables(ccut_plan* P, bool first) {
   for (auto& L : P->launches) {
     for (int j = L.job_begin; j < L.job_begin + L.n_jobs; ++j) {
       const PassDesc& d = P->pass_descs[P->jobs[j].pass_id];
-      if (d.stage_count > 0) {
-        L.hdr_cap = std::max(L.hdr_cap, d.op_count);
-        L.stg_cap = std::max(L.stg_cap, d.stage_count);
-      }
+      if (d.stage_count > 0) L.rec_cap = std::max(L.rec_cap, d.op_count + d.stage_count);
     }
   }
 

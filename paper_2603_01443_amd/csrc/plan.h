@@ -53,8 +53,8 @@ struct ccut_plan {
   std::vector<ccut::KOp> kops;
   std::vector<ccut::GroupRef> grefs;  // MFMA operand tables of the register-stage groups
   std::vector<ccut::SimJob> jobs;
-  // hdr_cap / stg_cap: LDS room for the op headers and stage heads of its passes
-  struct Launch { int job_begin, n_jobs, total_wg, hdr_cap = 0, stg_cap = 0; };
+  // rec_cap: LDS room for the op headers and stage heads of its largest pass
+  struct Launch { int job_begin, n_jobs, total_wg, rec_cap = 0; };
   std::vector<Launch> launches;
 
   // Packed table image (ops | passes | jobs | weights) and where it sits in the arena.

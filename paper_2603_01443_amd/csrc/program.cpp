@@ -586,7 +586,58 @@ void stage_kops(const std::vector<KOp>& kops, int b, std::vector<StageDesc>& sta
   }
 }
 
-int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out, bool from_zero) {
+int schedule_raw(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out, bool from_zero);
+
+namespace {
+
+// Op headers plus stage heads a register-stage pass may hold: the kernel copies
+// them (32 bytes each) into LDS beside its block.
+int max_pass_records(int b) {
+  const size_t block = sim_shmem_bytes(b, 0);
+  return block >= SIM_LDS_MAX ? 0 : (int)((SIM_LDS_MAX - block) / 32);
+}
+
+// Appends p to out, split into consecutive passes over the same group until each
+// one's records fit.  Later parts read the state the earlier ones wrote.
+void fit_pass(Pass p, bool fuse, std::vector<Pass>& out) {
+  const int b = (int)p.group.size();
+  bool fits = b < STAGE_MIN_B || p.kops.size() < 2;
+  if (!fits) {
+    const size_t cap = (size_t)max_pass_records(b);
+    fits = 6 * p.kops.size() <= cap;  // per op at most a group header, four members and a stage
+    if (!fits) {
+      std::vector<StageDesc> st;
+      std::vector<KOp> sk;
+      stage_kops(p.kops, b, st, sk, fuse);
+      fits = sk.size() + st.size() <= cap;
+    }
+  }
+  if (fits) {
+    out.push_back(std::move(p));
+    return;
+  }
+  Pass second = p;
+  const size_t h = p.kops.size() / 2;
+  second.kops.assign(p.kops.begin() + h, p.kops.end());
+  second.init = false;
+  second.from_src = false;
+  p.kops.resize(h);
+  fit_pass(std::move(p), fuse, out);
+  fit_pass(std::move(second), fuse, out);
+}
+
+}  // namespace
+
+int schedule_passes(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out, bool from_zero,
+                    bool fuse) {
+  std::vector<Pass> raw;
+  if (int rc = schedule_raw(prog, bmax, low_bits, raw, from_zero)) return rc;
+  out.clear();
+  for (Pass& p : raw) fit_pass(std::move(p), fuse, out);
+  return 0;
+}
+
+int schedule_raw(const Program& prog, int bmax, int low_bits, std::vector<Pass>& out, bool from_zero) {
   out.clear();
   const int nq = prog.nq;
   std::vector<int> pending(prog.ops.size());

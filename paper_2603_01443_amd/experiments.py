@@ -507,7 +507,8 @@ def run_headline(args):
                 tuned = {"launch": ccut.plan_get_launch(plan), "merge": ccut.plan_get_merge(plan),
                          "prefix_sharing": ccut.plan_get_prefix_sharing(plan),
                          "prefix_start": ccut.plan_get_prefix_start(plan),
-                         "block_bits": ccut.plan_get_block_bits(plan)}
+                         "block_bits": ccut.plan_get_block_bits(plan),
+                         "merge_arithmetic": ccut.plan_get_auto_precision(plan)}
                 del plan
             pre, sub, mer, _ = time_cut(q, g, n, sizes, bufs, warm=2, reps=args.reps)
             t_orig = time_uncut(q, g, bufs, reps=max(1, args.reps // 2))

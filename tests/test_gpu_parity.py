@@ -258,6 +258,40 @@ def test_prefix_sharing_matches_oracle(lib, prec, bits, start):
             assert metrics.one_minus_fidelity(ref, got) < 1e-9, (prec, bits, i, r)
 
 
+@pytest.mark.parametrize("fusion", [False, True])
+def test_deep_segment_in_one_block_splits_passes(lib, fusion):
+    """A deep segment program in blocks that hold the whole segment (q = 28 in 14 + 14,
+    d = 60, two cuts, 2^14-amplitude blocks, flat schedule): one pass would need more LDS
+    for its op headers and stage heads than the CU has beside the block, so the schedule
+    splits it into consecutive passes over the same qubits; the variant states match the
+    oracle's, with register-stage fusion off and on."""
+    ccut, pipeline = lib
+    q, d, n, c = 28, 60, 2, 2
+    sizes = [14, 14]
+    g = brickwork(q, d, n, c, seed=6)
+    ocuts = cutting.find_cuts(q, g, sizes)
+    ostates = cutting.variant_states(q, g, sizes, ocuts)
+    run = pipeline.CutRun(q, g, n)
+    ccut.plan_set_block_bits(run.plan, 14)
+    ccut.plan_set_prefix_sharing(run.plan, 0)
+    ccut.plan_set_fusion(run.plan, fusion)
+    assert ccut.plan_get_block_bits(run.plan) == 14
+    assert ccut.plan_stats(run.plan)["passes"] > n      # more than one pass per segment
+    need = run.plan.info()["arena_bytes"]
+    if need > run.arena.numel():
+        run.arena = torch.empty(need, dtype=torch.uint8, device=run.psi.device)
+    run.arena.zero_()
+    run.simulate_subcircuits()
+    torch.cuda.synchronize()
+    pcuts = run.plan.cuts()
+    for i in range(n):
+        for r in range(2 ** c):
+            ref = ostates[oracle_key(pcuts, ocuts, i, r)]
+            got = to_np(run.variant_state(i, r))
+            assert metrics.max_abs_error(ref, got) < fp32_tol(14), (fusion, i, r)
+            assert metrics.one_minus_fidelity(ref, got) < 1e-9, (fusion, i, r)
+
+
 @pytest.mark.parametrize("prec,bits,prefix,start", [("fp16x3", 13, 0, 0), ("fp16x3", 12, 1, 2), ("fp16x3", 11, 1, 0),
                                                      ("fp32", 12, 0, 0), ("fp16x3", 9, 0, 0)])
 def test_gate_fusion_matches_oracle(lib, prec, bits, prefix, start):
