@@ -441,7 +441,9 @@ int ccut_plan_get_sim_precision(const ccut_plan_t* plan, int32_t* out);
  * size whose first launch has a workgroup per compute unit, not below 2^12).
  * A segment with more qubits than bits is simulated in several passes over
  * its state in HBM; smaller blocks trade passes for parallelism when there
- * are fewer variants than compute units.  Reschedules the plan's programs
+ * are fewer variants than compute units.  A pass whose op headers and stage
+ * heads would not fit in LDS beside its block (deep circuits in large blocks)
+ * is split into consecutive passes over the same qubits.  Reschedules the plan's programs
  * (host-only) and may enlarge ccut_plan_info().arena_bytes: query it again
  * before sizing an arena.  Results agree to float32 rounding across sizes.
  * Errors: CCUT_EINVAL.
