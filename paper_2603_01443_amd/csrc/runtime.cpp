@@ -425,6 +425,7 @@ extern "C" int ccut_autotune(ccut_plan_t* plan, void* d_arena, uint64_t arena_by
         plan->sim_grid_cap = c;
         float ms = 0.f;
         int rc = time_call(s, reps, &ms, [&]() { return ccut_simulate_subcircuits(plan, d_arena, arena_bytes, stream); });
+        if (rc == CCUT_EUNSUPPORTED) continue;  // a configuration the launch refuses: not a candidate
         if (rc) {
           plan->sim_per_variant = saved_pv;
           plan->block_bits = saved_bits;
